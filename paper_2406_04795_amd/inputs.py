@@ -1,0 +1,344 @@
+"""Seeded synthetic inputs for the tracing and checking workloads.
+
+Everything here builds *inputs*: the manifold function's parameters (a
+polynomial-kernel decision function, the form a kernel SVM yields), the
+lattice frame, the domain box, seed points on the manifold and the robot /
+obstacle scene.  Nothing here traces, evaluates signs on the lattice or checks
+collisions; both the GPU library and the reference implementation read the
+arrays produced here.
+
+The paper learns f with an SVM from planner samples and finds seeds with
+SLSQP (Sec. IV-A, V-A); neither samples nor trained models exist here, so f
+is drawn at random with the shapes the paper's workloads have and seeds come
+from bisection along segments that cross the zero set.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+PI = math.pi
+
+
+@dataclass
+class Manifold:
+    """f(x) = sum_i alpha_i (gamma <s_i, x> + coef0)^p + bias."""
+
+    d: int
+    p: int
+    gamma: float
+    coef0: float
+    bias: float
+    sv: np.ndarray      # (S, d) float64
+    alpha: np.ndarray   # (S,) float64
+
+    @property
+    def S(self) -> int:
+        return int(self.sv.shape[0])
+
+
+@dataclass
+class Lattice:
+    """x(v) = o + M v; M is a scaled Coxeter A~_d frame, Minv its inverse."""
+
+    M: np.ndarray       # (d, d) float64 row-major
+    Minv: np.ndarray    # (d, d)
+    o: np.ndarray       # (d,)
+    lam: float
+
+
+@dataclass
+class Domain:
+    lo: np.ndarray
+    hi: np.ndarray
+
+
+@dataclass
+class Scene:
+    """Serial revolute robot (link spheres / capsules) and obstacles."""
+
+    joint_T: np.ndarray          # (n, 12) parent->joint transforms, row-major [R|t]
+    joint_axis: np.ndarray       # (n,) int32 in {0,1,2}
+    lsph_link: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    lsph_c: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    lsph_r: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    lcap_link: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    lcap_p0: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    lcap_p1: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    lcap_r: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    osph_c: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    osph_r: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    obox_T: np.ndarray = field(default_factory=lambda: np.zeros((0, 12)))
+    obox_l: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+
+
+@dataclass
+class Workload:
+    name: str
+    f: Manifold
+    lat: Lattice
+    dom: Domain
+    seeds: np.ndarray            # (n_seeds, d) float64
+    k: int = 1                   # 1 = direct trace, >= 2 = batch triangulation
+    scene: Scene | None = None
+    note: str = ""
+
+
+# --------------------------------------------------------------------------
+# Lattice frame
+# --------------------------------------------------------------------------
+def coxeter_frame(d: int, lam: float) -> np.ndarray:
+    """Upper-triangular M with M^T M = lam^2 (I - 11^T/(d+1)).
+
+    With that Gram matrix the images of e_0..e_{d-1} and of -(1,...,1) have
+    equal length and equal pairwise angles, which turns the integer lattice's
+    Kuhn triangulation into the Coxeter triangulation of type A~_d.
+    """
+    G = np.eye(d) - np.ones((d, d)) / (d + 1)
+    U = np.linalg.cholesky(G).T
+    return np.ascontiguousarray(lam * U)
+
+
+def make_lattice(d: int, lam: float, rng: np.random.Generator) -> Lattice:
+    M = coxeter_frame(d, lam)
+    Minv = np.ascontiguousarray(np.linalg.inv(M))
+    o = M @ rng.uniform(0.0, 1.0, d)      # random offset within one cell
+    return Lattice(M=M, Minv=Minv, o=np.ascontiguousarray(o), lam=lam)
+
+
+def box(d: int, half: float = PI) -> Domain:
+    return Domain(lo=np.full(d, -half), hi=np.full(d, half))
+
+
+# --------------------------------------------------------------------------
+# Manifold parameters (numpy evaluation used only to size inputs and seeds)
+# --------------------------------------------------------------------------
+def _f0(fm: Manifold, X: np.ndarray) -> np.ndarray:
+    t = fm.gamma * (X @ fm.sv.T) + fm.coef0
+    return (t ** fm.p) @ fm.alpha
+
+
+def feval_np(fm: Manifold, X: np.ndarray) -> np.ndarray:
+    """f at points X (n, d) in plain numpy; for input generation only."""
+    return _f0(fm, X) + fm.bias
+
+
+def random_manifold(d, S, p, rng, dom: Domain, alpha="normal", gamma=None, coef0=1.0):
+    sv = rng.uniform(dom.lo, dom.hi, size=(S, d))
+    a = rng.standard_normal(S)
+    if alpha == "halfnormal":
+        a = np.abs(a)
+    g = 1.0 / d if gamma is None else gamma
+    return Manifold(d=d, p=p, gamma=float(g), coef0=float(coef0), bias=0.0,
+                    sv=np.ascontiguousarray(sv), alpha=np.ascontiguousarray(a))
+
+
+def sphere_manifold(d: int, R: float, center=None) -> Manifold:
+    """||x - c||^2 - R^2 written as a degree-2 kernel expansion.
+
+    (<e_j, x> - c_j)^2 summed over j: S = d support vectors e_j with
+    gamma = 1, per-SV offset folded into the bias is not possible with a
+    common coef0, so the centre is 0 unless all c_j are equal.
+    """
+    c = 0.0 if center is None else float(center)
+    sv = np.eye(d)
+    return Manifold(d=d, p=2, gamma=1.0, coef0=-c, bias=-R * R,
+                    sv=np.ascontiguousarray(sv), alpha=np.ones(d))
+
+
+def closed_quadratic_bias(fm: Manifold, dom: Domain, rng, n_probe=20000) -> float:
+    """Bias for a convex quadratic f0 so that {f = 0} is closed inside the box.
+
+    b = -(m_in + m_bd)/2 with m_in the minimum of f0 over the box and m_bd an
+    estimate of its minimum over the box boundary; then f > 0 on the boundary
+    and f < 0 at the interior minimiser.
+    """
+    d = fm.d
+    # interior minimum of the convex quadratic (clipped to the box)
+    Q = (fm.gamma ** 2) * (fm.sv.T * fm.alpha) @ fm.sv
+    g = 2 * fm.gamma * fm.coef0 * (fm.sv.T @ fm.alpha)
+    xstar = np.clip(np.linalg.solve(2 * Q, -g), dom.lo, dom.hi)
+    m_in = float(_f0(fm, xstar[None])[0])
+    # boundary minimum: dense random probes on the faces
+    X = rng.uniform(dom.lo, dom.hi, size=(n_probe, d))
+    face = rng.integers(0, d, n_probe)
+    side = rng.integers(0, 2, n_probe)
+    X[np.arange(n_probe), face] = np.where(side == 1, dom.hi[face], dom.lo[face])
+    m_bd = float(_f0(fm, X).min())
+    return -(m_in + m_bd) / 2.0
+
+
+def quantile_bias(fm: Manifold, dom: Domain, rng, eps: float, n_probe=200000) -> float:
+    """Bias so that a fraction eps of the box lies in {f < 0}."""
+    X = rng.uniform(dom.lo, dom.hi, size=(n_probe, fm.d))
+    return -float(np.quantile(_f0(fm, X), eps))
+
+
+def bisection_seeds(fm: Manifold, dom: Domain, rng, n_seeds: int,
+                    n_probe=20000, iters=60) -> np.ndarray:
+    """Points near {f = 0}: bisect segments joining an f<0 and an f>0 probe."""
+    negs = []
+    pos = None
+    drawn = 0
+    while drawn < 4_000_000:
+        X = rng.uniform(dom.lo, dom.hi, size=(n_probe, fm.d))
+        drawn += n_probe
+        F = feval_np(fm, X)
+        negs.append(X[F < 0])
+        if pos is None:
+            pos = X[F >= 0]
+        if sum(len(a) for a in negs) >= n_seeds:
+            break
+    neg = np.concatenate(negs)
+    if len(neg) == 0 or len(pos) == 0:
+        raise ValueError("f has no sign change over the probes")
+    seeds = []
+    for i in range(n_seeds):
+        a = neg[i % len(neg)].copy()
+        # the positive probe nearest to a keeps the crossing local
+        j = np.argmin(((pos - a) ** 2).sum(1) + 1e-9 * i)
+        b = pos[j].copy()
+        for _ in range(iters):
+            m = 0.5 * (a + b)
+            if feval_np(fm, m[None])[0] < 0:
+                a = m
+            else:
+                b = m
+        seeds.append(0.5 * (a + b))
+    return np.ascontiguousarray(np.array(seeds))
+
+
+# --------------------------------------------------------------------------
+# Scenes (Sec. V-C: robot as spheres; obstacles as spheres / boxes)
+# --------------------------------------------------------------------------
+def _T(R=None, t=(0.0, 0.0, 0.0)):
+    R = np.eye(3) if R is None else np.asarray(R, float)
+    out = np.zeros(12)
+    out[[0, 1, 2, 4, 5, 6, 8, 9, 10]] = R.reshape(-1)
+    out[[3, 7, 11]] = t
+    return out
+
+
+def _random_rotation(rng):
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def planar_arm_scene(rng, n_links=3, link=1.0, n_obst=3, r_obst=0.3) -> Scene:
+    """Planar nR arm, unit links along x, z axes; circles as spheres at z=0."""
+    joint_T = np.stack([_T() if i == 0 else _T(t=(link, 0, 0)) for i in range(n_links)])
+    c = np.zeros((n_obst, 3))
+    c[:, :2] = rng.uniform(-3.0, 3.0, size=(n_obst, 2))
+    return Scene(
+        joint_T=joint_T, joint_axis=np.full(n_links, 2, np.int32),
+        lcap_link=np.arange(n_links, dtype=np.int32),
+        lcap_p0=np.zeros((n_links, 3)),
+        lcap_p1=np.tile([link, 0.0, 0.0], (n_links, 1)),
+        lcap_r=np.zeros(n_links),
+        osph_c=c, osph_r=np.full(n_obst, r_obst))
+
+
+_SPATIAL_AXES = [2, 1, 1, 2, 1, 2, 1]
+
+
+def spatial_arm_scene(rng, n_links, link=0.3, capsule_r=None, spheres_per_link=0,
+                      sphere_r=0.05, n_osph=8, osph_r=(0.1, 0.3), n_obox=0,
+                      obox_l=(0.1, 0.4)) -> Scene:
+    """Spatial nR arm: axes z,y,y,z,y,z,...; links of length `link` along z."""
+    joint_T = np.stack([_T() if i == 0 else _T(t=(0, 0, link)) for i in range(n_links)])
+    reach = link * n_links
+    sc = Scene(joint_T=joint_T, joint_axis=np.array(_SPATIAL_AXES[:n_links], np.int32))
+    if capsule_r is not None:
+        sc.lcap_link = np.arange(n_links, dtype=np.int32)
+        sc.lcap_p0 = np.zeros((n_links, 3))
+        sc.lcap_p1 = np.tile([0.0, 0.0, link], (n_links, 1))
+        sc.lcap_r = np.full(n_links, capsule_r)
+    if spheres_per_link:
+        m = spheres_per_link
+        sc.lsph_link = np.repeat(np.arange(n_links, dtype=np.int32), m)
+        zs = (np.arange(m) + 0.5) / m * link
+        sc.lsph_c = np.tile(np.stack([np.zeros(m), np.zeros(m), zs], 1), (n_links, 1))
+        sc.lsph_r = np.full(n_links * m, sphere_r)
+
+    def in_ball(n):
+        v = rng.standard_normal((n, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        return v * (reach * rng.uniform(0.2, 1.0, size=(n, 1)) ** (1 / 3))
+
+    sc.osph_c = in_ball(n_osph)
+    sc.osph_r = rng.uniform(osph_r[0], osph_r[1], n_osph)
+    if n_obox:
+        sc.obox_T = np.stack([_T(_random_rotation(rng), t) for t in in_ball(n_obox)])
+        sc.obox_l = rng.uniform(obox_l[0], obox_l[1], size=(n_obox, 3))
+    return sc
+
+
+# --------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------
+def sphere_case(d: int, R: float, lam: float, seed: int = 0, half=None, n_seeds=1) -> Workload:
+    """f = ||x||^2 - R^2: a single closed component; used by the pins."""
+    rng = np.random.default_rng(seed)
+    dom = box(d, half if half is not None else R + 4 * lam * d + 0.5)
+    fm = sphere_manifold(d, R)
+    lat = make_lattice(d, lam, rng)
+    u = rng.standard_normal((n_seeds, d))
+    seeds = R * u / np.linalg.norm(u, axis=1, keepdims=True)
+    return Workload(f"sphere_d{d}", fm, lat, dom, np.ascontiguousarray(seeds))
+
+
+def quadric_case(d=3, S=50, lam=0.15, seed=0, n_seeds=4, scene=True) -> Workload:
+    """Degree-2 kernel, half-normal coefficients: a closed ellipsoid-like set."""
+    rng = np.random.default_rng(seed)
+    dom = box(d)
+    fm = random_manifold(d, S, 2, rng, dom, alpha="halfnormal")
+    fm.bias = closed_quadratic_bias(fm, dom, rng)
+    lat = make_lattice(d, lam, rng)
+    seeds = bisection_seeds(fm, dom, rng, n_seeds)
+    sc = planar_arm_scene(rng) if (scene and d == 3) else None
+    return Workload(f"quadric_d{d}_S{S}", fm, lat, dom, seeds, 1, sc)
+
+
+def cubic_case(d, S, lam, eps, seed=0, n_seeds=8, k=1, scene=None) -> Workload:
+    """Degree-3 kernel, N(0,1) coefficients, bias at the eps-quantile of f0."""
+    rng = np.random.default_rng(seed)
+    dom = box(d)
+    fm = random_manifold(d, S, 3, rng, dom, alpha="normal")
+    fm.bias = quantile_bias(fm, dom, rng, eps)
+    lat = make_lattice(d, lam, rng)
+    seeds = bisection_seeds(fm, dom, rng, n_seeds)
+    return Workload(f"cubic_d{d}_S{S}", fm, lat, dom, seeds, k, scene)
+
+
+def config_c1(seed=0) -> Workload:
+    """d=3, 50 SVs, degree 2, scale 0.15, planar 3R arm with 3 circles."""
+    w = quadric_case(d=3, S=50, lam=0.15, seed=seed, n_seeds=4)
+    w.name = "d3_S50_p2_lam0.15_fp64"
+    return w
+
+
+def config_c2(seed=0, eps=0.02) -> Workload:
+    """d=5, 500 SVs, degree 3, scale 0.08, 5R arm with capsules vs 8 spheres."""
+    rng = np.random.default_rng(seed + 100)
+    sc = spatial_arm_scene(rng, 5, capsule_r=0.05, n_osph=8)
+    w = cubic_case(5, 500, 0.08, eps, seed=seed, scene=sc)
+    w.name = "d5_S500_p3_lam0.08"
+    return w
+
+
+def config_c3(seed=0, eps=0.002, k=4) -> Workload:
+    """d=6, 2000 SVs, degree 3, scale 0.06, batch k; 6R arm, 8 boxes + 8 spheres."""
+    rng = np.random.default_rng(seed + 200)
+    sc = spatial_arm_scene(rng, 6, spheres_per_link=3, sphere_r=0.05,
+                           n_osph=8, n_obox=8)
+    w = cubic_case(6, 2000, 0.06, eps, seed=seed, k=k, scene=sc)
+    w.name = f"d6_S2000_p3_lam0.06_k{k}"
+    return w
