@@ -1,0 +1,187 @@
+/*
+ * ip.h -- C ABI of the MI355X library that traces an implicit manifold
+ * f(q) = 0 through the Coxeter triangulation of configuration space and
+ * collision-checks the traced cells (Li & Dantam, "Scaling Motion Planning
+ * Infeasibility Proofs", arXiv 2406.04795, Sec. V).
+ *
+ * Conventions shared by every call:
+ *   - Return value: IP_OK (0) or a negative IP_E* code.  Nothing aborts and
+ *     no C++ exception crosses this boundary.  On error, output handles are
+ *     set to NULL and ip_last_error(ctx) holds a message.
+ *   - "host" pointers are read during the call only; the caller keeps
+ *     ownership.  "device" pointers are HIP device addresses on the context's
+ *     device, used on the context's stream; the caller keeps ownership.
+ *   - Handles returned by the library (ip_problem, ip_cells) are owned by the
+ *     caller until released with the matching *_free call, which must happen
+ *     before ip_destroy of the context that made them.
+ *   - All floating-point inputs are FP64.  Matrices are row-major.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef IP_H
+#define IP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IP_MAX_D 7
+
+enum {
+  IP_OK = 0,
+  IP_EINVAL = -1,   /* bad argument (dimension, degree, NaN, NULL) */
+  IP_ENOMEM = -2,   /* device memory or batch budget too small */
+  IP_ERANGE = -3,   /* lattice coordinates of the domain overflow the 64-bit keys */
+  IP_EDEVICE = -4,  /* HIP runtime error (message in ip_last_error) */
+  IP_EAGAIN = -5    /* result not ready (serving loop) */
+};
+
+enum {
+  IP_FP64 = 0,          /* every f evaluation in FP64, canonical order */
+  IP_FP32_CERTIFY = 1   /* FP32 evaluation with an error bound; vertices whose
+                           sign the bound cannot settle are re-evaluated in
+                           FP64, so the traced set equals the FP64 one */
+};
+
+typedef struct ip_ctx ip_ctx;
+typedef struct ip_problem ip_problem;
+typedef struct ip_cells ip_cells;
+
+/* Manifold function, the decision function of a polynomial-kernel SVM
+ * (Sec. IV-A: the learned manifold):
+ *   f(x) = sum_{i<n_sv} alpha_i * (gamma * <sv_i, x> + coef0)^degree + bias.
+ * The FP64 value is defined by this evaluation order: x from the lattice
+ * (see ip_space), then for i = 0..n_sv-1 in order: dot = fma chain over
+ * j = 0..d-1 of sv_ij * x_j starting at 0; t = fma(gamma, dot, coef0);
+ * t^degree by repeated multiplication; acc = fma(alpha_i, t^degree, acc);
+ * finally f = acc + bias.  Sign bit s = !(f < 0). */
+typedef struct {
+  int32_t d;             /* ambient dimension, 2..IP_MAX_D */
+  int32_t degree;        /* >= 1 */
+  int64_t n_sv;          /* >= 1 */
+  double gamma, coef0, bias;
+  const double *sv;      /* host, n_sv x d */
+  const double *alpha;   /* host, n_sv */
+} ip_fparams;
+
+/* Coxeter triangulation frame and domain (Sec. IV-B, V-A).  Lattice vertex
+ * v in Z^d has coordinates x_j = offset_j + sum_k M[j][k] v_k (fma chain over
+ * k from offset_j).  Simplices are Kuhn simplices of Z^d (vertex + ordered
+ * partition), so M fixes the scale lambda and the Coxeter shape.  Minv is
+ * used for point location.  The domain is the closed box [lo, hi]; an edge is
+ * traced only if both endpoints lie in it. */
+typedef struct {
+  int32_t d;
+  const double *M;       /* host, d x d */
+  const double *Minv;    /* host, d x d */
+  const double *offset;  /* host, d */
+  const double *lo;      /* host, d */
+  const double *hi;      /* host, d */
+} ip_space;
+
+/* Robot and obstacles for the batch collision check (Sec. V-C, Appendix A).
+ * Serial revolute robot: T_i = T_{i-1} * J_i * Rot(axis_i, q_i), T_{-1} = I,
+ * with 3x4 row-major [R|t] transforms.  Robot geometry is given in link
+ * frames (spheres, and capsules = segments with a radius); obstacles are
+ * world-frame spheres and boxes (pose world-from-box, full extents).
+ * Capsule-vs-box pairs are not defined (IP_EINVAL).  Touching collides. */
+typedef struct {
+  int32_t n_joints;            /* equals d of the configurations */
+  const double *joint_T;       /* host, n_joints x 12 */
+  const int32_t *joint_axis;   /* host, n_joints, 0=x 1=y 2=z */
+  int32_t n_lsph;
+  const int32_t *lsph_link;    /* host */
+  const double *lsph_c;        /* host, x3 */
+  const double *lsph_r;
+  int32_t n_lcap;
+  const int32_t *lcap_link;
+  const double *lcap_p0;       /* x3 */
+  const double *lcap_p1;       /* x3 */
+  const double *lcap_r;
+  int32_t n_osph;
+  const double *osph_c;        /* x3 */
+  const double *osph_r;
+  int32_t n_obox;
+  const double *obox_T;        /* x12 */
+  const double *obox_l;        /* x3 */
+} ip_scene;
+
+typedef struct {
+  int64_t n_cells;       /* traced edges (1-simplices) = intersection points */
+  int64_t n_vertices;    /* unique lattice vertices whose f was evaluated */
+  int64_t n_fallback;    /* vertices re-evaluated in FP64 (IP_FP32_CERTIFY) */
+  int64_t n_cofaces;     /* 2-simplex cofaces expanded by the search */
+  int64_t n_sigma;       /* coarse n-simplices (batch triangulation) */
+  int64_t n_batches;     /* batches of coarse n-simplices */
+  int64_t n_template_edges; /* fine edges tested in batch mode */
+  int32_t levels;        /* breadth-first levels of the search */
+  int32_t regrows;       /* hash-table growths */
+  double ms_total;       /* wall time of ip_trace on the stream */
+  double ms_feval;       /* time in f-evaluation kernels (HIP events) */
+  double ms_expand;      /* time in frontier-expansion kernels */
+  double ms_points;      /* time in the intersection-point kernel */
+  double ms_check;       /* time in the collision kernel (ip_check_cells) */
+} ip_stats;
+
+/* Create a context on HIP device `device`; work is issued on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The context keeps device
+ * workspace between calls. */
+int ip_create(ip_ctx **ctx, int device, void *hip_stream);
+void ip_destroy(ip_ctx *ctx);
+const char *ip_last_error(const ip_ctx *ctx);
+
+/* Upload one proof problem: manifold, frame/domain and seed points (host,
+ * n_seeds x d; points on or near f = 0, Sec. V-A).  coarse_k = 1 traces
+ * directly at the frame's scale; coarse_k >= 2 uses batch triangulation
+ * (Sec. V-B): trace on the lattice coarsened by k, then subdivide every
+ * n-simplex coface of the coarse edges by k.  IP_ERANGE if the domain's
+ * lattice coordinates do not fit the keys. */
+int ip_problem_create(ip_ctx *ctx, const ip_fparams *f, const ip_space *sp,
+                      const double *seeds, int64_t n_seeds, int32_t coarse_k,
+                      ip_problem **out);
+void ip_problem_free(ip_problem *p);
+
+/* Trace (Sec. V-A locate + breadth-first search; Sec. V-B batches).
+ * batch_budget_bytes bounds the per-batch device workspace in batch mode
+ * (0 = library default); the traced set does not depend on it.
+ * precision: IP_FP64 or IP_FP32_CERTIFY.  flags: reserved, pass 0.
+ * The result holds the traced edges and their intersection points
+ * p = x_a + t (x_b - x_a), t = f_a / (f_a - f_b), a the smaller endpoint. */
+int ip_trace(ip_ctx *ctx, const ip_problem *p, uint64_t batch_budget_bytes,
+             int32_t precision, uint32_t flags, ip_cells **out);
+
+int64_t ip_cells_count(const ip_cells *c);
+int ip_cells_stats(const ip_cells *c, ip_stats *out);
+/* Copy cells to host buffers (any may be NULL): v (n x d int32, smaller
+ * endpoint), mask (n, endpoint b = v + sum_{j in mask} e_j), pts (n x d). */
+int ip_cells_download(ip_ctx *ctx, const ip_cells *c, int32_t *v, uint32_t *mask,
+                      double *pts);
+/* Device view of the intersection points: SoA, pts[j * ld + i]. */
+int ip_cells_points(const ip_cells *c, const double **pts_dev, int64_t *ld);
+void ip_cells_free(ip_cells *c);
+
+/* Collision verdicts for n configurations (Sec. V-C).  q_dev: device SoA,
+ * q[j * ld + i], j < n_joints.  verdict_dev: device, n bytes, 1 = collision.
+ * Evaluated in FP64 in a fixed operation order (own sine/cosine). */
+int ip_check(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n,
+             int64_t ld, uint8_t *verdict_dev);
+
+/* Check the cells' points, keep the verdicts on the device and gather the
+ * free (verdict 0) points (Sec. V-B: only C_free points go back to the
+ * host).  *n_free receives their count. */
+int ip_check_cells(ip_ctx *ctx, ip_cells *c, const ip_scene *scene, int64_t *n_free);
+/* Host copies of the verdicts (n bytes) and free points (n_free x d). */
+int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict,
+                            double *free_pts);
+
+/* f at lattice vertices (device v_dev: n x d int32 -> device f_dev: n).
+ * IP_FP64: canonical FP64.  IP_FP32_CERTIFY: FP32 with the bound, FP64 for
+ * the vertices the bound cannot settle; bound_dev (may be NULL) receives the
+ * bound used (0 for FP64 results). */
+int ip_feval(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n,
+             int32_t precision, double *f_dev, double *bound_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,354 @@
+// C ABI entry points (include/ip.h): argument validation, context and
+// handle management.  All device work is done by the kernels in trace.hip,
+// feval.hip and check.hip.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ip_internal.h"
+
+int ip_fail(ip_ctx *ctx, int code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int ip_hip(ip_ctx *ctx, hipError_t e, const char *what) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
+  (void)hipGetLastError();
+  return ip_fail(ctx, e == hipErrorOutOfMemory ? IP_ENOMEM : IP_EDEVICE, buf);
+}
+
+int ip_ensure(ip_ctx *ctx, DevBuf &b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return IP_OK;
+  if (b.p) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(b.p);
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+  hipError_t e = hipMalloc(&b.p, bytes < 256 ? 256 : bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return ip_fail(ctx, IP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return IP_OK;
+}
+
+namespace {
+
+bool finite_all(const double *p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Key packing range of lattice coordinates for vertices inside the box:
+// z = Minv (y - o) / mul over the box corners, with a margin of 2.
+int build_lattice(ip_ctx *ctx, const ip_space *sp, int32_t mul, LatDev *L) {
+  const int d = sp->d;
+  memset(L, 0, sizeof(*L));
+  L->d = d;
+  L->mul = mul;
+  L->B = (63 - d) / d;
+  for (int j = 0; j < d; ++j) {
+    for (int k = 0; k < d; ++k) {
+      L->M[j * 8 + k] = sp->M[j * d + k];
+      L->Minv[j * 8 + k] = sp->Minv[j * d + k];
+    }
+    L->o[j] = sp->offset[j];
+    L->lo[j] = sp->lo[j];
+    L->hi[j] = sp->hi[j];
+  }
+  for (int j = 0; j < d; ++j) {
+    double zl = 0.0, zh = 0.0;
+    for (int k = 0; k < d; ++k) {
+      double a = sp->Minv[j * d + k] * (sp->lo[k] - sp->offset[k]);
+      double b = sp->Minv[j * d + k] * (sp->hi[k] - sp->offset[k]);
+      zl += a < b ? a : b;
+      zh += a < b ? b : a;
+    }
+    zl /= mul;
+    zh /= mul;
+    double vmin = std::floor(zl) - 2.0, vmax = std::ceil(zh) + 2.0;
+    if (!(vmin > -2.0e9 && vmax < 2.0e9)) return ip_fail(ctx, IP_ERANGE, "lattice coordinates overflow int32");
+    double range = vmax - vmin + 1.0;
+    if (range > std::ldexp(1.0, L->B))
+      return ip_fail(ctx, IP_ERANGE,
+                     "domain spans " + std::to_string((long long)range) + " lattice steps on axis " +
+                         std::to_string(j) + "; keys hold " + std::to_string(1ll << L->B));
+    L->vmin[j] = (int32_t)vmin;
+  }
+  return IP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ip_create(ip_ctx **out, int device, void *stream) {
+  if (!out) return IP_EINVAL;
+  *out = nullptr;
+  ip_ctx *ctx = new (std::nothrow) ip_ctx();
+  if (!ctx) return IP_ENOMEM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipMalloc((void **)&ctx->ctr_dev, sizeof(Counters));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->ctr_host, sizeof(Counters), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (ctx->ctr_dev) (void)hipFree(ctx->ctr_dev);
+    if (ctx->ctr_host) (void)hipHostFree(ctx->ctr_host);
+    delete ctx;
+    return IP_EDEVICE;
+  }
+  memset(ctx->ctr_host, 0, sizeof(Counters));
+  *out = ctx;
+  return IP_OK;
+}
+
+void ip_destroy(ip_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  DevBuf *bufs[] = {&ctx->vt_keys, &ctx->vt_vals, &ctx->vt_aux, &ctx->et_keys, &ctx->eval_list,
+                    &ctx->fb_list, &ctx->scratch, &ctx->scene};
+  for (DevBuf *b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->ctr_dev) (void)hipFree(ctx->ctr_dev);
+  if (ctx->ctr_host) (void)hipHostFree(ctx->ctr_host);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  delete ctx;
+}
+
+const char *ip_last_error(const ip_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ip_problem_create(ip_ctx *ctx, const ip_fparams *f, const ip_space *sp, const double *seeds, int64_t n_seeds,
+                      int32_t coarse_k, ip_problem **out) {
+  if (!ctx) return IP_EINVAL;
+  if (!out) return ip_fail(ctx, IP_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!f || !sp || (!seeds && n_seeds > 0)) return ip_fail(ctx, IP_EINVAL, "null argument");
+  const int d = f->d;
+  if (d < 2 || d > IP_MAX_D || sp->d != d) return ip_fail(ctx, IP_EINVAL, "dimension must be 2..7 and match");
+  if (f->degree < 1 || f->degree > 64) return ip_fail(ctx, IP_EINVAL, "degree must be 1..64");
+  if (f->n_sv < 1 || !f->sv || !f->alpha) return ip_fail(ctx, IP_EINVAL, "need at least one support vector");
+  if (coarse_k < 1 || coarse_k > 64) return ip_fail(ctx, IP_EINVAL, "coarse_k must be 1..64");
+  if (n_seeds < 1) return ip_fail(ctx, IP_EINVAL, "need at least one seed");
+  if (!sp->M || !sp->Minv || !sp->offset || !sp->lo || !sp->hi) return ip_fail(ctx, IP_EINVAL, "null frame");
+  if (!finite_all(f->sv, f->n_sv * d) || !finite_all(f->alpha, f->n_sv) || !std::isfinite(f->gamma) ||
+      !std::isfinite(f->coef0) || !std::isfinite(f->bias) || !finite_all(sp->M, d * d) ||
+      !finite_all(sp->Minv, d * d) || !finite_all(sp->offset, d) || !finite_all(sp->lo, d) ||
+      !finite_all(sp->hi, d) || !finite_all(seeds, n_seeds * d))
+    return ip_fail(ctx, IP_EINVAL, "non-finite input");
+  for (int j = 0; j < d; ++j)
+    if (!(sp->lo[j] <= sp->hi[j])) return ip_fail(ctx, IP_EINVAL, "empty domain box");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  ip_problem *p = new (std::nothrow) ip_problem();
+  if (!p) return ip_fail(ctx, IP_ENOMEM, "host allocation failed");
+  p->ctx = ctx;
+  p->d = d;
+  p->k = coarse_k;
+  int rc = build_lattice(ctx, sp, 1, &p->fine);
+  if (rc == IP_OK) rc = build_lattice(ctx, sp, coarse_k, &p->coarse);
+  if (rc != IP_OK) {
+    delete p;
+    return rc;
+  }
+  // support-vector records: s_0..s_{d-1}, alpha, padding (64 bytes)
+  const int64_t S = f->n_sv;
+  std::vector<double> rec((size_t)S * 8, 0.0);
+  std::vector<float> rec32((size_t)S * 8, 0.0f);
+  p->sv_host.assign(f->sv, f->sv + S * d);
+  for (int64_t i = 0; i < S; ++i) {
+    double nn = 0.0;
+    for (int j = 0; j < d; ++j) {
+      rec[i * 8 + j] = f->sv[i * d + j];
+      rec32[i * 8 + j] = (float)f->sv[i * d + j];
+      nn += f->sv[i * d + j] * f->sv[i * d + j];
+    }
+    rec[i * 8 + d] = f->alpha[i];
+    rec32[i * 8 + d] = (float)f->alpha[i];
+    p->sum_abs_alpha += std::fabs(f->alpha[i]);
+    if (std::sqrt(nn) > p->sv_norm_max) p->sv_norm_max = std::sqrt(nn);
+  }
+  hipError_t e = hipMalloc((void **)&p->rec_dev, rec.size() * 8);
+  if (e == hipSuccess) e = hipMalloc((void **)&p->rec32_dev, rec32.size() * 4);
+  if (e == hipSuccess) e = hipMalloc((void **)&p->seeds_dev, (size_t)n_seeds * d * 8);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->rec_dev, rec.data(), rec.size() * 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->rec32_dev, rec32.data(), rec32.size() * 4, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->seeds_dev, seeds, (size_t)n_seeds * d * 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    int r = ip_hip(ctx, e, "ip_problem_create upload");
+    ip_problem_free(p);
+    return r;
+  }
+  p->n_seeds = n_seeds;
+  p->f.rec = p->rec_dev;
+  p->f.rec32 = p->rec32_dev;
+  p->f.S = S;
+  p->f.p = f->degree;
+  p->f.gamma = f->gamma;
+  p->f.coef0 = f->coef0;
+  p->f.bias = f->bias;
+  *out = p;
+  return IP_OK;
+}
+
+void ip_problem_free(ip_problem *p) {
+  if (!p) return;
+  if (p->ctx) (void)hipStreamSynchronize(p->ctx->stream);
+  if (p->rec_dev) (void)hipFree(p->rec_dev);
+  if (p->rec32_dev) (void)hipFree(p->rec32_dev);
+  if (p->seeds_dev) (void)hipFree(p->seeds_dev);
+  delete p;
+}
+
+int ip_trace(ip_ctx *ctx, const ip_problem *p, uint64_t batch_budget_bytes, int32_t precision, uint32_t flags,
+             ip_cells **out) {
+  if (!ctx) return IP_EINVAL;
+  if (!out || !p) return ip_fail(ctx, IP_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->ctx != ctx) return ip_fail(ctx, IP_EINVAL, "problem belongs to another context");
+  if (precision != IP_FP64 && precision != IP_FP32_CERTIFY) return ip_fail(ctx, IP_EINVAL, "unknown precision");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  ip_cells *c = new (std::nothrow) ip_cells();
+  if (!c) return ip_fail(ctx, IP_ENOMEM, "host allocation failed");
+  c->ctx = ctx;
+  IP_TRY_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+  int rc = ip_trace_impl(ctx, p, batch_budget_bytes, precision, flags, c);
+  if (rc == IP_OK) {
+    hipError_t e = hipEventRecord(ctx->ev1, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ctx->ev1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    if (e != hipSuccess) rc = ip_hip(ctx, e, "ip_trace timing");
+    c->st.ms_total = ms;
+  }
+  if (rc != IP_OK) {
+    ip_cells_free(c);
+    return rc;
+  }
+  *out = c;
+  return IP_OK;
+}
+
+int64_t ip_cells_count(const ip_cells *c) { return c ? c->n : -1; }
+
+int ip_cells_stats(const ip_cells *c, ip_stats *out) {
+  if (!c || !out) return IP_EINVAL;
+  *out = c->st;
+  return IP_OK;
+}
+
+int ip_cells_download(ip_ctx *ctx, const ip_cells *c, int32_t *v, uint32_t *mask, double *pts) {
+  if (!ctx) return IP_EINVAL;
+  if (!c) return ip_fail(ctx, IP_EINVAL, "null cells");
+  const int64_t n = c->n;
+  const int d = c->d;
+  if (n == 0) return IP_OK;
+  if (v || mask) {
+    std::vector<uint64_t> keys((size_t)n);
+    IP_TRY_HIP(ctx, hipMemcpyAsync(keys.data(), c->keys, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const uint64_t m = (1ull << c->B) - 1ull;
+    for (int64_t i = 0; i < n; ++i) {
+      uint64_t k = keys[i] & ~IP_SIGN_BIT;
+      if (v)
+        for (int j = 0; j < d; ++j) v[i * d + j] = (int32_t)((k >> (j * c->B)) & m) + c->vmin[j];
+      if (mask) mask[i] = (uint32_t)(k >> (d * c->B)) & ((1u << d) - 1u);
+    }
+  }
+  if (pts) {
+    std::vector<double> soa((size_t)n * d);
+    for (int j = 0; j < d; ++j)
+      IP_TRY_HIP(ctx, hipMemcpyAsync(soa.data() + (size_t)j * n, c->pts + (size_t)j * c->ld, (size_t)n * 8,
+                                     hipMemcpyDeviceToHost, ctx->stream));
+    IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t i = 0; i < n; ++i)
+      for (int j = 0; j < d; ++j) pts[i * d + j] = soa[(size_t)j * n + i];
+  }
+  return IP_OK;
+}
+
+int ip_cells_points(const ip_cells *c, const double **pts_dev, int64_t *ld) {
+  if (!c || !pts_dev || !ld) return IP_EINVAL;
+  *pts_dev = c->pts;
+  *ld = c->ld;
+  return IP_OK;
+}
+
+void ip_cells_free(ip_cells *c) {
+  if (!c) return;
+  if (c->ctx) (void)hipStreamSynchronize(c->ctx->stream);
+  if (c->keys) (void)hipFree(c->keys);
+  if (c->pts) (void)hipFree(c->pts);
+  if (c->verdict) (void)hipFree(c->verdict);
+  if (c->free_pts) (void)hipFree(c->free_pts);
+  delete c;
+}
+
+int ip_check(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n, int64_t ld, uint8_t *verdict_dev) {
+  if (!ctx) return IP_EINVAL;
+  if (!scene || (n > 0 && (!q_dev || !verdict_dev)) || n < 0 || ld < n)
+    return ip_fail(ctx, IP_EINVAL, "ip_check: bad arguments");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  return ip_check_impl(ctx, scene, q_dev, n, ld, verdict_dev);
+}
+
+int ip_check_cells(ip_ctx *ctx, ip_cells *c, const ip_scene *scene, int64_t *n_free) {
+  if (!ctx) return IP_EINVAL;
+  if (!c || !scene) return ip_fail(ctx, IP_EINVAL, "null argument");
+  if (scene->n_joints != c->d) return ip_fail(ctx, IP_EINVAL, "scene joints must equal the dimension");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  if (!c->verdict) IP_TRY_HIP(ctx, hipMalloc((void **)&c->verdict, (size_t)(c->n ? c->n : 1)));
+  IP_TRY_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+  IP_TRY(ip_check_impl(ctx, scene, c->pts, c->n, c->ld, c->verdict));
+  IP_TRY_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+  IP_TRY(ip_compact_free_impl(ctx, c));
+  float ms = 0.0f;
+  IP_TRY_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  c->st.ms_check = ms;
+  if (n_free) *n_free = c->n_free;
+  return IP_OK;
+}
+
+int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict, double *free_pts) {
+  if (!ctx) return IP_EINVAL;
+  if (!c || !c->verdict) return ip_fail(ctx, IP_EINVAL, "cells have not been checked");
+  const int d = c->d;
+  if (verdict && c->n)
+    IP_TRY_HIP(ctx, hipMemcpyAsync(verdict, c->verdict, (size_t)c->n, hipMemcpyDeviceToHost, ctx->stream));
+  if (free_pts && c->n_free) {
+    std::vector<double> soa((size_t)c->n_free * d);
+    for (int j = 0; j < d; ++j)
+      IP_TRY_HIP(ctx, hipMemcpyAsync(soa.data() + (size_t)j * c->n_free, c->free_pts + (size_t)j * c->n,
+                                     (size_t)c->n_free * 8, hipMemcpyDeviceToHost, ctx->stream));
+    IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t i = 0; i < c->n_free; ++i)
+      for (int j = 0; j < d; ++j) free_pts[i * d + j] = soa[(size_t)j * c->n_free + i];
+  }
+  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return IP_OK;
+}
+
+int ip_feval(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, int32_t precision, double *f_dev,
+             double *bound_dev) {
+  if (!ctx) return IP_EINVAL;
+  if (!p || (n > 0 && (!v_dev || !f_dev)) || n < 0) return ip_fail(ctx, IP_EINVAL, "ip_feval: bad arguments");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  if (n == 0) return IP_OK;
+  return ip_feval_impl(ctx, p, v_dev, n, precision, f_dev, bound_dev);
+}
+
+}  // extern "C"

@@ -1,0 +1,321 @@
+// Internal definitions shared by the library's HIP sources: device-side
+// lattice frame, key packing, open-addressing hash tables, coface
+// enumeration of the permutahedral representation, and the host-side
+// context / problem / result objects behind the C ABI in ip.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ip.h"
+
+#define IP_EMPTY_KEY 0xFFFFFFFFFFFFFFFFull
+// NaN payload marking a vertex slot whose f has not been evaluated yet.
+#define IP_UNEVAL_BITS 0x7FF4DEADBEEF0001ull
+#define IP_SIGN_BIT 0x8000000000000000ull
+
+// ---------------------------------------------------------------------------
+// Lattice frame on the device (passed by value as a kernel argument).
+// Vertex u has coordinates x_j = o_j + sum_k M[j][k] * (mul * u_k), with an
+// fma chain over k; mul = 1 on the fine lattice and k on the coarse lattice
+// of batch triangulation, so coarse vertices share the fine vertices' bits.
+// ---------------------------------------------------------------------------
+struct LatDev {
+  int32_t d;
+  int32_t B;         // key bits per coordinate
+  int32_t mul;       // lattice refinement factor (see above)
+  int32_t pad;
+  int32_t vmin[8];   // key offset per coordinate
+  double M[64];      // row-major, stride 8
+  double Minv[64];
+  double o[8], lo[8], hi[8];
+};
+
+// Manifold parameters on the device.  rec holds one 64-byte record per
+// support vector: s_0..s_{d-1}, alpha, zero padding (8 doubles).
+struct FDev {
+  const double *rec;
+  const float *rec32;   // the same records rounded to FP32
+  int64_t S;
+  int32_t p;
+  int32_t pad;
+  double gamma, coef0, bias;
+};
+
+struct Counters {
+  unsigned long long n_eval;     // eval-list length (reset per pass)
+  unsigned long long vt_count;   // vertices inserted (total)
+  unsigned long long n_out;      // output-list length (== edges in ET)
+  unsigned long long n_cof;      // cofaces expanded in the current level
+  unsigned long long n_fb;       // FP64 fallback list length
+  unsigned long long n_fb_total; // fallbacks over the whole call
+  unsigned long long n_aux;      // general-purpose append counter
+  unsigned int vt_fail;          // vertex-table insert found the table full
+  unsigned int et_fail;          // edge-table insert found the table full
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+// SplitMix64 finalizer (Steele, Lea & Flood 2014; constants as published by
+// Vigna) as the table hash.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  uint32_t lo = __shfl((unsigned int)(v & 0xffffffffu), src, 64);
+  uint32_t hi = __shfl((unsigned int)(v >> 32), src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int D>
+__device__ __forceinline__ void lat_coords(const LatDev &L, const int32_t *v, double *x) {
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double acc = L.o[j];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc = fma(L.M[j * 8 + k], (double)(L.mul * v[k]), acc);
+    x[j] = acc;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ bool lat_in_box(const LatDev &L, const double *x) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < D; ++j) ok = ok && (x[j] >= L.lo[j]) && (x[j] <= L.hi[j]);
+  return ok;
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t vpack(const LatDev &L, const int32_t *v) {
+  uint64_t k = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) k |= (uint64_t)(uint32_t)(v[j] - L.vmin[j]) << (j * L.B);
+  return k;
+}
+
+template <int D>
+__device__ __forceinline__ void vunpack(const LatDev &L, uint64_t k, int32_t *v) {
+  const uint64_t m = (1ull << L.B) - 1ull;
+#pragma unroll
+  for (int j = 0; j < D; ++j) v[j] = (int32_t)((k >> (j * L.B)) & m) + L.vmin[j];
+}
+
+// True when every coordinate fits the key field.  Vertices inside the domain
+// always fit (the host sizes the fields from the box); a vertex that does not
+// fit lies outside the box and must not be packed.
+template <int D>
+__device__ __forceinline__ bool vin_range(const LatDev &L, const int32_t *v) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < D; ++j) ok = ok && (uint32_t)(v[j] - L.vmin[j]) < (1u << L.B);
+  return ok;
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t ekey(const LatDev &L, const int32_t *v, uint32_t mask) {
+  return vpack<D>(L, v) | ((uint64_t)mask << (D * L.B));
+}
+
+template <int D>
+__device__ __forceinline__ void eunpack(const LatDev &L, uint64_t key, int32_t *v, uint32_t *mask) {
+  key &= ~IP_SIGN_BIT;
+  vunpack<D>(L, key, v);
+  *mask = (uint32_t)(key >> (D * L.B)) & ((1u << D) - 1u);
+}
+
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Open addressing with linear probing.  Returns 1 when `key` was inserted,
+// 0 when it was present, -1 when the table is full; *slot gets its position.
+__device__ __forceinline__ int ht_insert(uint64_t *keys, uint64_t mask, uint64_t key, uint64_t *slot) {
+  uint64_t h = mix64(key) & mask;
+  for (uint64_t n = 0; n <= mask; ++n) {
+    uint64_t cur = ld_relaxed(keys + h);
+    if (cur == key) {
+      *slot = h;
+      return 0;
+    }
+    if (cur == IP_EMPTY_KEY) {
+      uint64_t prev = atomicCAS((unsigned long long *)(keys + h), (unsigned long long)IP_EMPTY_KEY,
+                                (unsigned long long)key);
+      if (prev == IP_EMPTY_KEY) {
+        *slot = h;
+        return 1;
+      }
+      if (prev == key) {
+        *slot = h;
+        return 0;
+      }
+    }
+    h = (h + 1) & mask;
+  }
+  return -1;
+}
+
+// Lookup in a table that no thread modifies during the kernel.
+__device__ __forceinline__ int64_t ht_find(const uint64_t *keys, uint64_t mask, uint64_t key) {
+  uint64_t h = mix64(key) & mask;
+  for (uint64_t n = 0; n <= mask; ++n) {
+    uint64_t cur = keys[h];
+    if (cur == key) return (int64_t)h;
+    if (cur == IP_EMPTY_KEY) return -1;
+    h = (h + 1) & mask;
+  }
+  return -1;
+}
+
+// Deposit the low bits of src into the set positions of mask (ascending).
+__device__ __forceinline__ uint32_t pdep32(uint32_t src, uint32_t mask) {
+  uint32_t out = 0;
+  for (uint32_t b = 1; mask; b <<= 1) {
+    uint32_t low = mask & (0u - mask);
+    if (src & b) out |= low;
+    mask ^= low;
+  }
+  return out;
+}
+
+// Number of 2-simplex cofaces of edge (v, (R, Q)): ordered two-part splits
+// of R plus those of Q = {0..D} \ R, i.e. (2^|R| - 2) + (2^|Q| - 2).
+template <int D>
+__device__ __forceinline__ int n_cofaces2(uint32_t R) {
+  int nP = __popc(R);
+  return (1 << nP) - 2 + (1 << (D + 1 - nP)) - 2;
+}
+
+// Third vertex c of coface r of edge (v, R).  Splitting R into (A, R\A)
+// gives c = v + 1_A.  Splitting Q into (A, Q\A) gives c = v + 1_R + 1_A when
+// D is not in A; when D is in A the root -(1..1) wraps the cycle and
+// c = v - 1_{Q\A}.
+template <int D>
+__device__ __forceinline__ void coface_vertex(const int32_t *v, uint32_t R, int r, int32_t *c) {
+  const uint32_t full = (1u << (D + 1)) - 1u;
+  const uint32_t Q = full & ~R;
+  const int splitR = (1 << __popc(R)) - 2;
+  if (r < splitR) {
+    uint32_t A = pdep32((uint32_t)r + 1u, R);
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = v[j] + (int32_t)((A >> j) & 1u);
+  } else {
+    uint32_t A = pdep32((uint32_t)(r - splitR) + 1u, Q);
+    if (!((A >> D) & 1u)) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) c[j] = v[j] + (int32_t)((R >> j) & 1u) + (int32_t)((A >> j) & 1u);
+    } else {
+      uint32_t Bm = Q & ~A;
+#pragma unroll
+      for (int j = 0; j < D; ++j) c[j] = v[j] - (int32_t)((Bm >> j) & 1u);
+    }
+  }
+}
+
+// Canonical edge between two vertices of one simplex (their difference is a
+// 0/1 vector up to sign): the componentwise smaller endpoint and the support.
+template <int D>
+__device__ __forceinline__ bool edge_canon(const int32_t *a, const int32_t *b, int32_t *vmin, uint32_t *mask) {
+  uint32_t m = 0;
+  bool pos = false;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    int32_t df = b[j] - a[j];
+    if (df != 0) {
+      m |= 1u << j;
+      pos = df > 0;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j) vmin[j] = pos ? a[j] : b[j];
+  *mask = m;
+  return pos;  // true when a is the smaller endpoint
+}
+
+// ---------------------------------------------------------------------------
+// Host-side objects
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct ip_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  Counters *ctr_dev = nullptr;
+  Counters *ctr_host = nullptr;  // pinned
+  // persistent workspace (grow-only)
+  DevBuf vt_keys, vt_vals, vt_aux, et_keys, eval_list, fb_list, scratch;
+  DevBuf scene;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct ip_problem {
+  ip_ctx *ctx = nullptr;
+  int32_t d = 0;
+  int32_t k = 1;
+  LatDev fine;      // fine lattice (mul = 1)
+  LatDev coarse;    // coarse lattice (mul = k); equal to fine when k = 1
+  FDev f;
+  double *rec_dev = nullptr;
+  float *rec32_dev = nullptr;
+  double *seeds_dev = nullptr;
+  int64_t n_seeds = 0;
+  double sum_abs_alpha = 0;
+  double sv_norm_max = 0;     // max over SVs of ||s_i||_2
+  std::vector<double> sv_host;  // n_sv x d
+};
+
+struct ip_cells {
+  ip_ctx *ctx = nullptr;
+  int32_t d = 0;
+  int32_t B = 0;
+  int32_t vmin[8] = {0};
+  int64_t n = 0;
+  uint64_t *keys = nullptr;    // n keys (sign bit cleared)
+  double *pts = nullptr;       // SoA d x ld
+  int64_t ld = 0;
+  uint8_t *verdict = nullptr;  // n (after ip_check_cells)
+  double *free_pts = nullptr;  // SoA d x ld_free
+  int64_t n_free = 0;
+  ip_stats st = {};
+};
+
+// Error helpers used by the host code.
+int ip_fail(ip_ctx *ctx, int code, const std::string &msg);
+int ip_hip(ip_ctx *ctx, hipError_t e, const char *what);
+int ip_ensure(ip_ctx *ctx, DevBuf &b, size_t bytes);
+
+#define IP_TRY_HIP(ctx, call)                            \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return ip_hip(ctx, e_, #call); \
+  } while (0)
+#define IP_TRY(call)        \
+  do {                      \
+    int r_ = (call);        \
+    if (r_ != IP_OK) return r_; \
+  } while (0)
+
+// Entry points implemented across the sources.
+int ip_trace_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, uint32_t flags,
+                  ip_cells *out);
+int ip_feval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, int32_t prec,
+                  double *f_dev, double *bound_dev);
+int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n, int64_t ld,
+                  uint8_t *verdict_dev);
+int ip_compact_free_impl(ip_ctx *ctx, ip_cells *c);
+
+// f evaluation of the vertices listed in `list` (slots of the vertex table);
+// results go into vt_vals[slot].  Defined in feval.hip.
+int launch_feval64(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list,
+                   uint64_t n_list, const uint64_t *vt_keys, double *vt_vals);

@@ -1,0 +1,289 @@
+"""Python binding of the C ABI in include/ip.h (argument marshalling only).
+
+Every function named ip_* forwards to the entry point of the same name in
+libip.so; all computation happens in the library's HIP kernels.  If the
+library has not been built this module raises on import: there is no other
+code path.  PyTorch is used only for device buffers and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libip.so")
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"{LIBPATH} is missing: build it with paper_2406_04795_amd/build.py "
+                      "(or __graft_entry__.build()); there is no fallback path")
+
+_lib = C.CDLL(LIBPATH)
+
+IP_OK, IP_EINVAL, IP_ENOMEM, IP_ERANGE, IP_EDEVICE, IP_EAGAIN = 0, -1, -2, -3, -4, -5
+IP_FP64, IP_FP32_CERTIFY = 0, 1
+IP_MAX_D = 7
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_vp = C.c_void_p
+
+
+class ip_fparams(C.Structure):
+    _fields_ = [("d", C.c_int32), ("degree", C.c_int32), ("n_sv", C.c_int64),
+                ("gamma", C.c_double), ("coef0", C.c_double), ("bias", C.c_double),
+                ("sv", _dp), ("alpha", _dp)]
+
+
+class ip_space(C.Structure):
+    _fields_ = [("d", C.c_int32), ("M", _dp), ("Minv", _dp), ("offset", _dp),
+                ("lo", _dp), ("hi", _dp)]
+
+
+class ip_scene(C.Structure):
+    _fields_ = [("n_joints", C.c_int32), ("joint_T", _dp), ("joint_axis", _ip),
+                ("n_lsph", C.c_int32), ("lsph_link", _ip), ("lsph_c", _dp), ("lsph_r", _dp),
+                ("n_lcap", C.c_int32), ("lcap_link", _ip), ("lcap_p0", _dp), ("lcap_p1", _dp),
+                ("lcap_r", _dp),
+                ("n_osph", C.c_int32), ("osph_c", _dp), ("osph_r", _dp),
+                ("n_obox", C.c_int32), ("obox_T", _dp), ("obox_l", _dp)]
+
+
+class ip_stats(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_vertices", C.c_int64), ("n_fallback", C.c_int64),
+                ("n_cofaces", C.c_int64), ("n_sigma", C.c_int64), ("n_batches", C.c_int64),
+                ("n_template_edges", C.c_int64), ("levels", C.c_int32), ("regrows", C.c_int32),
+                ("ms_total", C.c_double), ("ms_feval", C.c_double), ("ms_expand", C.c_double),
+                ("ms_points", C.c_double), ("ms_check", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = C.POINTER
+_sig = {
+    "ip_create": (C.c_int, [_P(_vp), C.c_int, _vp]),
+    "ip_destroy": (None, [_vp]),
+    "ip_last_error": (C.c_char_p, [_vp]),
+    "ip_problem_create": (C.c_int, [_vp, _P(ip_fparams), _P(ip_space), _dp, C.c_int64, C.c_int32,
+                                    _P(_vp)]),
+    "ip_problem_free": (None, [_vp]),
+    "ip_trace": (C.c_int, [_vp, _vp, C.c_uint64, C.c_int32, C.c_uint32, _P(_vp)]),
+    "ip_cells_count": (C.c_int64, [_vp]),
+    "ip_cells_stats": (C.c_int, [_vp, _P(ip_stats)]),
+    "ip_cells_download": (C.c_int, [_vp, _vp, _ip, C.POINTER(C.c_uint32), _dp]),
+    "ip_cells_points": (C.c_int, [_vp, _P(_vp), _P(C.c_int64)]),
+    "ip_cells_free": (None, [_vp]),
+    "ip_check": (C.c_int, [_vp, _P(ip_scene), _vp, C.c_int64, C.c_int64, _vp]),
+    "ip_check_cells": (C.c_int, [_vp, _vp, _P(ip_scene), _P(C.c_int64)]),
+    "ip_cells_download_check": (C.c_int, [_vp, _vp, C.POINTER(C.c_uint8), _dp]),
+    "ip_feval": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, _vp, _vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class IPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ip error {code}: {msg}")
+        self.code = code
+
+
+def _chk(ctx, rc):
+    if rc != IP_OK:
+        msg = _lib.ip_last_error(ctx).decode() if ctx else ""
+        raise IPError(rc, msg)
+
+
+def _d(keep, a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    keep.append(a)
+    return a.ctypes.data_as(_dp)
+
+
+def _i(keep, a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    keep.append(a)
+    return a.ctypes.data_as(_ip)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+# --------------------------------------------------------------------------
+# Same-name wrappers
+# --------------------------------------------------------------------------
+def ip_create(device: int = 0, stream=None):
+    h = _vp()
+    _chk(None, _lib.ip_create(C.byref(h), device, _stream_handle(stream)))
+    return h
+
+
+def ip_destroy(ctx):
+    _lib.ip_destroy(ctx)
+
+
+def ip_last_error(ctx) -> str:
+    return _lib.ip_last_error(ctx).decode()
+
+
+def ip_problem_create(ctx, f, lat, dom, seeds, coarse_k=1):
+    """f: inputs.Manifold, lat: inputs.Lattice, dom: inputs.Domain."""
+    keep = []
+    fp = ip_fparams(f.d, f.p, f.S, f.gamma, f.coef0, f.bias, _d(keep, f.sv), _d(keep, f.alpha))
+    sp = ip_space(f.d, _d(keep, lat.M), _d(keep, lat.Minv), _d(keep, lat.o), _d(keep, dom.lo),
+                  _d(keep, dom.hi))
+    seeds = np.ascontiguousarray(seeds, dtype=np.float64)
+    h = _vp()
+    _chk(ctx, _lib.ip_problem_create(ctx, C.byref(fp), C.byref(sp), seeds.ctypes.data_as(_dp),
+                                     seeds.shape[0], coarse_k, C.byref(h)))
+    return h
+
+
+def ip_problem_free(p):
+    _lib.ip_problem_free(p)
+
+
+def ip_trace(ctx, prob, budget=0, precision=IP_FP64, flags=0):
+    h = _vp()
+    _chk(ctx, _lib.ip_trace(ctx, prob, budget, precision, flags, C.byref(h)))
+    return h
+
+
+def ip_cells_count(cells) -> int:
+    return int(_lib.ip_cells_count(cells))
+
+
+def ip_cells_stats(cells) -> dict:
+    st = ip_stats()
+    _chk(None, _lib.ip_cells_stats(cells, C.byref(st)))
+    return st.as_dict()
+
+
+def ip_cells_download(ctx, cells, d):
+    n = ip_cells_count(cells)
+    v = np.zeros((n, d), np.int32)
+    m = np.zeros(n, np.uint32)
+    p = np.zeros((n, d), np.float64)
+    _chk(ctx, _lib.ip_cells_download(ctx, cells, v.ctypes.data_as(_ip),
+                                     m.ctypes.data_as(C.POINTER(C.c_uint32)), p.ctypes.data_as(_dp)))
+    return v, m, p
+
+
+def ip_cells_points(cells):
+    ptr = _vp()
+    ld = C.c_int64()
+    _chk(None, _lib.ip_cells_points(cells, C.byref(ptr), C.byref(ld)))
+    return ptr.value, ld.value
+
+
+def ip_cells_free(cells):
+    _lib.ip_cells_free(cells)
+
+
+def _scene_struct(sc, keep):
+    n = int(sc.joint_T.shape[0])
+    return ip_scene(n, _d(keep, sc.joint_T), _i(keep, sc.joint_axis),
+                    len(sc.lsph_r), _i(keep, sc.lsph_link), _d(keep, sc.lsph_c), _d(keep, sc.lsph_r),
+                    len(sc.lcap_r), _i(keep, sc.lcap_link), _d(keep, sc.lcap_p0),
+                    _d(keep, sc.lcap_p1), _d(keep, sc.lcap_r),
+                    len(sc.osph_r), _d(keep, sc.osph_c), _d(keep, sc.osph_r),
+                    len(sc.obox_l), _d(keep, sc.obox_T), _d(keep, sc.obox_l))
+
+
+def ip_check(ctx, scene, q_dev_ptr: int, n: int, ld: int, verdict_dev_ptr: int):
+    keep = []
+    s = _scene_struct(scene, keep)
+    _chk(ctx, _lib.ip_check(ctx, C.byref(s), q_dev_ptr, n, ld, verdict_dev_ptr))
+
+
+def ip_check_cells(ctx, cells, scene) -> int:
+    keep = []
+    s = _scene_struct(scene, keep)
+    nf = C.c_int64()
+    _chk(ctx, _lib.ip_check_cells(ctx, cells, C.byref(s), C.byref(nf)))
+    return nf.value
+
+
+def ip_cells_download_check(ctx, cells, d, n_free):
+    n = ip_cells_count(cells)
+    ver = np.zeros(n, np.uint8)
+    fp = np.zeros((n_free, d), np.float64)
+    _chk(ctx, _lib.ip_cells_download_check(ctx, cells, ver.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                           fp.ctypes.data_as(_dp)))
+    return ver, fp
+
+
+def ip_feval(ctx, prob, v_dev_ptr: int, n: int, precision, f_dev_ptr: int, bound_dev_ptr: int = 0):
+    _chk(ctx, _lib.ip_feval(ctx, prob, v_dev_ptr, n, precision, f_dev_ptr, bound_dev_ptr or None))
+
+
+# --------------------------------------------------------------------------
+# Small conveniences over the same calls (still marshalling only)
+# --------------------------------------------------------------------------
+class Context:
+    def __init__(self, device=0, stream=None):
+        self.h = ip_create(device, stream)
+
+    def close(self):
+        if self.h:
+            ip_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Problem:
+    def __init__(self, ctx: Context, wl, coarse_k=None):
+        self.ctx = ctx
+        self.d = wl.f.d
+        self.h = ip_problem_create(ctx.h, wl.f, wl.lat, wl.dom, wl.seeds,
+                                   wl.k if coarse_k is None else coarse_k)
+
+    def close(self):
+        if self.h:
+            ip_problem_free(self.h)
+            self.h = None
+
+
+class Cells:
+    def __init__(self, ctx: Context, prob: Problem, budget=0, precision=IP_FP64):
+        self.ctx = ctx
+        self.d = prob.d
+        self.h = ip_trace(ctx.h, prob.h, budget, precision)
+        self.n_free = None
+
+    @property
+    def n(self):
+        return ip_cells_count(self.h)
+
+    def stats(self):
+        return ip_cells_stats(self.h)
+
+    def download(self):
+        return ip_cells_download(self.ctx.h, self.h, self.d)
+
+    def check(self, scene):
+        self.n_free = ip_check_cells(self.ctx.h, self.h, scene)
+        return self.n_free
+
+    def download_check(self):
+        return ip_cells_download_check(self.ctx.h, self.h, self.d, self.n_free)
+
+    def close(self):
+        if self.h:
+            ip_cells_free(self.h)
+            self.h = None

@@ -1,0 +1,216 @@
+"""GPU parity: the HIP library against the oracle, element by element.
+
+Traced edge sets and collision verdicts must be identical; FP64 values
+(f at vertices, intersection points) are produced in the same operation order
+on both sides and must agree bit for bit (the stated tolerance for FP64
+points is 1e-12 relative; these tests hold the stronger equality).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2406_04795_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ip():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    from paper_2406_04795_amd import ip as _ip
+    return _ip
+
+
+@pytest.fixture(scope="module")
+def ctx(ip):
+    c = ip.Context(0)
+    yield c
+    c.close()
+
+
+def _order(v, m):
+    keys = [m] + [v[:, j] for j in reversed(range(v.shape[1]))]
+    return np.lexsort(keys)
+
+
+def trace(ip, ctx, wl, **kw):
+    p = ip.Problem(ctx, wl)
+    try:
+        c = ip.Cells(ctx, p, **kw)
+        try:
+            v, m, pts = c.download()
+            st = c.stats()
+        finally:
+            c.close()
+    finally:
+        p.close()
+    o = _order(v, m)
+    return v[o], m[o], pts[o], st
+
+
+CASES = {
+    "sphere_d2": lambda: I.sphere_case(2, 1.0, 0.05),
+    "c1_quadric_d3": I.config_c1,
+    "sphere_d4": lambda: I.sphere_case(4, 1.0, 0.3),
+    "cubic_d5": lambda: I.cubic_case(5, 500, 0.35, 0.02, seed=1, n_seeds=4),
+    "cubic_d6": lambda: I.cubic_case(6, 2000, 0.6, 0.002, seed=2, n_seeds=4),
+    "sphere_d7": lambda: I.sphere_case(7, 1.0, 0.9),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_trace_matches_oracle(ip, ctx, name):
+    wl = CASES[name]()
+    print(f"case {name}", flush=True)
+    ov, om = O.trace_direct(wl)
+    gv, gm, gpts, st = trace(ip, ctx, wl)
+    assert len(ov) > 0
+    assert len(gv) == len(ov), (len(gv), len(ov))
+    assert np.array_equal(gv, ov) and np.array_equal(gm, om)
+    opts, _ = O.points(wl, ov, om)
+    scale = np.maximum(np.abs(opts).max(1, keepdims=True), 1.0)
+    assert (np.abs(gpts - opts) <= 1e-12 * scale).all()
+    assert np.array_equal(gpts.view(np.uint64), opts.view(np.uint64))
+    assert st["n_cells"] == len(ov)
+
+
+def test_trace_repeat_and_table_growth_invariance(ip, ctx):
+    wl = CASES["cubic_d5"]()
+    a = trace(ip, ctx, wl)
+    # a second call starts from the grown tables of the first
+    b = trace(ip, ctx, wl)
+    # a fresh context starts from the smallest tables and grows mid-trace
+    c2 = ip.Context(0)
+    try:
+        c = trace(ip, c2, wl)
+    finally:
+        c2.close()
+    for x in (b, c):
+        assert np.array_equal(a[0], x[0]) and np.array_equal(a[1], x[1])
+        assert np.array_equal(a[2].view(np.uint64), x[2].view(np.uint64))
+
+
+@pytest.mark.parametrize("d,S,p", [(2, 7, 1), (3, 50, 2), (5, 500, 3), (6, 2000, 3), (7, 33, 4), (4, 64, 5)])
+def test_feval_fp64_bitwise(ip, ctx, d, S, p):
+    import torch
+    rng = np.random.default_rng(100 + d)
+    dom = I.box(d)
+    fm = I.random_manifold(d, S, p, rng, dom)
+    fm.bias = 0.125
+    lat = I.make_lattice(d, 0.2, rng)
+    wl = I.Workload("fe", fm, lat, dom, np.zeros((1, d)))
+    n = 3 * 512 + 37          # several launch tiles and a ragged tail
+    V = rng.integers(-30, 30, size=(n, d)).astype(np.int32)
+    want = O.feval(fm, lat, V)
+    prob = ip.Problem(ctx, wl)
+    try:
+        vd = torch.from_numpy(V).cuda()
+        fd = torch.empty(n, dtype=torch.float64, device="cuda")
+        ip.ip_feval(ctx.h, prob.h, vd.data_ptr(), n, ip.IP_FP64, fd.data_ptr())
+        torch.cuda.synchronize()
+        got = fd.cpu().numpy()
+    finally:
+        prob.close()
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def _dev_soa(q):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(q.T)).cuda()
+
+
+def _check_gpu(ip, ctx, scene, q):
+    import torch
+    n = q.shape[0]
+    qd = _dev_soa(q)
+    vd = torch.zeros(max(n, 1), dtype=torch.uint8, device="cuda")
+    ip.ip_check(ctx.h, scene, qd.data_ptr(), n, n, vd.data_ptr())
+    torch.cuda.synchronize()
+    return vd.cpu().numpy()[:n]
+
+
+@pytest.mark.parametrize("which", ["c1", "c2", "c3"])
+def test_check_verdicts_bitwise(ip, ctx, which):
+    rng = np.random.default_rng(11)
+    if which == "c1":
+        wl = I.config_c1()
+        sc = wl.scene
+        d = 3
+    elif which == "c2":
+        sc = I.spatial_arm_scene(np.random.default_rng(100), 5, capsule_r=0.05, n_osph=8)
+        d = 5
+    else:
+        sc = I.spatial_arm_scene(np.random.default_rng(200), 6, spheres_per_link=3,
+                                 sphere_r=0.05, n_osph=8, n_obox=8)
+        d = 6
+    n = 20000 + 77
+    q = rng.uniform(-np.pi, np.pi, size=(n, d))
+    want = O.check(sc, q)
+    got = _check_gpu(ip, ctx, sc, q)
+    assert 0 < want.mean() < 1
+    assert np.array_equal(got, want)
+
+
+def test_check_cells_and_free_points(ip, ctx):
+    wl = I.config_c1()
+    p = ip.Problem(ctx, wl)
+    c = ip.Cells(ctx, p)
+    try:
+        v, m, pts = c.download()
+        nf = c.check(wl.scene)
+        ver, fp = c.download_check()
+    finally:
+        c.close()
+        p.close()
+    want = O.check(wl.scene, pts)
+    assert np.array_equal(ver, want)
+    assert nf == int((want == 0).sum())
+    free = pts[want == 0]
+
+    def rows(a):
+        return a[np.lexsort(a.T[::-1])] if len(a) else a
+
+    assert np.array_equal(rows(free), rows(fp))
+
+
+def test_edge_cases(ip, ctx):
+    # seed outside the domain: nothing to trace
+    wl = I.sphere_case(3, 1.0, 0.1)
+    wl.seeds = np.full((1, 3), 50.0)
+    assert trace(ip, ctx, wl)[0].shape[0] == 0
+    # seed far from the manifold: its simplex has no sign change
+    wl = I.sphere_case(3, 1.0, 0.1)
+    wl.seeds = np.zeros((1, 3))
+    assert trace(ip, ctx, wl)[0].shape[0] == 0
+    # many duplicate seeds give the same set as one
+    wl = I.sphere_case(3, 1.0, 0.1)
+    one = trace(ip, ctx, wl)
+    wl.seeds = np.repeat(wl.seeds, 1000, axis=0)
+    many = trace(ip, ctx, wl)
+    assert np.array_equal(one[0], many[0]) and np.array_equal(one[1], many[1])
+    # empty check
+    sc = I.planar_arm_scene(np.random.default_rng(0))
+    assert _check_gpu(ip, ctx, sc, np.zeros((0, 3))).shape[0] == 0
+
+
+def test_argument_errors(ip, ctx):
+    wl = I.sphere_case(3, 1.0, 0.1)
+    bad = I.sphere_case(3, 1.0, 0.1)
+    bad.f.sv = bad.f.sv.copy()
+    bad.f.sv[0, 0] = np.nan
+    with pytest.raises(ip.IPError) as e:
+        ip.Problem(ctx, bad)
+    assert e.value.code == ip.IP_EINVAL
+    # a domain too wide for the 8-bit keys of d = 7 at a fine scale
+    big = I.sphere_case(7, 1.0, 0.01, half=50.0)
+    with pytest.raises(ip.IPError) as e:
+        ip.Problem(ctx, big)
+    assert e.value.code == ip.IP_ERANGE
+    p = ip.Problem(ctx, wl)
+    try:
+        with pytest.raises(ip.IPError) as e:
+            ip.ip_trace(ctx.h, p.h, 0, 7)
+        assert e.value.code == ip.IP_EINVAL
+    finally:
+        p.close()
