@@ -51,7 +51,7 @@ def flops_per_vertex(f) -> int:
     return f.S * (2 * f.d + f.p + 3)
 
 
-def cpu_baseline(wl, budget_s: float = 20.0):
+def cpu_baseline(wl, budget_s: float = 24.0):
     """The oracle (single thread) on a bounded sample of the same workload:
     the same manifold, scale and scene, traced inside a sub-box of the domain
     centred on the first seed, plus the collision check of those cells."""
@@ -70,9 +70,11 @@ def cpu_baseline(wl, budget_s: float = 20.0):
         t0 = time.perf_counter()
         v, m = O.trace_direct(sub)
         t_trace = time.perf_counter() - t0
-        if t_trace > budget_s / 4 or half > 1.0:
+        # the oracle's point pass re-evaluates f at both ends of every cell,
+        # about 4x the trace time; stop growing the sub-box at ~1/6 of budget
+        if t_trace > budget_s / 6 or half > 1.0:
             break
-        half *= 1.6
+        half *= 1.25
     t0 = time.perf_counter()
     pts, _ = O.points(sub, v, m)
     t_pts = time.perf_counter() - t0
@@ -184,7 +186,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "d": wl.f.d, "n_sv": wl.f.S, "degree": wl.f.p,
                    "scale": wl.lat.lam, "coarse_k": wl.k, "cells": n_cells,
-                   "free_cells": int(nf), "vertices": nv, "levels": stats[-1]["levels"]},
+                   "free_cells": int(nf), "vertices": nv, "levels": stats[-1]["levels"],
+                   "cofaces": int(cof)},
         "phases_ms": {"trace": float(np.mean([s["ms_total"] for s in stats])),
                       "feval": f_ms, "expand": x_ms,
                       "points": float(np.mean([s["ms_points"] for s in stats])),

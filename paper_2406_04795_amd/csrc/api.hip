@@ -53,7 +53,7 @@ int build_lattice(ip_ctx *ctx, const ip_space *sp, int32_t mul, LatDev *L) {
   memset(L, 0, sizeof(*L));
   L->d = d;
   L->mul = mul;
-  L->B = (63 - d) / d;
+  L->B = 0;
   for (int j = 0; j < d; ++j) {
     for (int k = 0; k < d; ++k) {
       L->M[j * 8 + k] = sp->M[j * d + k];
@@ -75,13 +75,18 @@ int build_lattice(ip_ctx *ctx, const ip_space *sp, int32_t mul, LatDev *L) {
     zh /= mul;
     double vmin = std::floor(zl) - 2.0, vmax = std::ceil(zh) + 2.0;
     if (!(vmin > -2.0e9 && vmax < 2.0e9)) return ip_fail(ctx, IP_ERANGE, "lattice coordinates overflow int32");
-    double range = vmax - vmin + 1.0;
-    if (range > std::ldexp(1.0, L->B))
-      return ip_fail(ctx, IP_ERANGE,
-                     "domain spans " + std::to_string((long long)range) + " lattice steps on axis " +
-                         std::to_string(j) + "; keys hold " + std::to_string(1ll << L->B));
+    const double range = vmax - vmin + 1.0;
+    int bits = 1;
+    while (std::ldexp(1.0, bits) < range && bits < 31) ++bits;
+    if (bits > L->B) L->B = bits;
     L->vmin[j] = (int32_t)vmin;
   }
+  // an edge key holds d coordinates of B bits and a d-bit direction mask
+  // below the frontier's sign bit
+  if (d * L->B + d > 63)
+    return ip_fail(ctx, IP_ERANGE,
+                   "domain spans too many lattice steps: " + std::to_string(L->B) + " bits per coordinate in " +
+                       std::to_string(d) + " dimensions exceed the 64-bit keys");
   return IP_OK;
 }
 

@@ -614,6 +614,607 @@ int trace_direct(Run &s, ip_stats &st, uint64_t *n_out_ret) {
   return IP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batch triangulation (Sec. V-B, Figs. 5-6)
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int ifact(int n) {
+  int f = 1;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+// Index of the n-th set bit of m (n counted from 0, ascending).
+__device__ __forceinline__ int nth_bit(uint32_t m, int n) {
+  for (int i = 0; i < n; ++i) m &= m - 1u;
+  return __ffs((int)m) - 1;
+}
+
+// Lehmer code of a permutation w of {0..D-1} in the factorial number system.
+template <int D>
+__device__ __forceinline__ uint32_t lehmer_encode(const int32_t *w) {
+  uint32_t code = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = i + 1; j < D; ++j) c += (uint32_t)(w[j] < w[i]);
+    code = code * (uint32_t)(D - i) + c;
+  }
+  return code;
+}
+
+template <int D>
+__device__ __forceinline__ void lehmer_decode(uint32_t code, int32_t *w) {
+  uint32_t c[D];
+#pragma unroll
+  for (int i = D - 1; i >= 0; --i) {
+    c[i] = code % (uint32_t)(D - i);
+    code /= (uint32_t)(D - i);
+  }
+  uint32_t avail = (1u << D) - 1u;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    w[i] = nth_bit(avail, (int)c[i]);
+    avail &= ~(1u << w[i]);
+  }
+}
+
+// Coarse n-simplex key: coarse vertex in the high bits, Lehmer code of the
+// coordinate order w in the low LB bits.
+template <int D>
+__device__ __forceinline__ uint64_t sig_key(const LatDev &Lc, const int32_t *v, const int32_t *w, int LB) {
+  return (vpack<D>(Lc, v) << LB) | (uint64_t)lehmer_encode<D>(w);
+}
+
+template <int D>
+__device__ __forceinline__ void sig_unpack(const LatDev &Lc, uint64_t key, int LB, int32_t *v, int32_t *w) {
+  lehmer_decode<D>((uint32_t)(key & ((1ull << LB) - 1ull)), w);
+  vunpack<D>(Lc, key >> LB, v);
+}
+
+// Number of n-simplex cofaces of edge (v, (R, Q)): |R|! |Q|! (Sec. V-B).
+template <int D>
+__device__ __forceinline__ int n_cofacesn(uint32_t R) {
+  int nR = __popc(R);
+  return ifact(nR) * ifact(D + 1 - nR);
+}
+
+__global__ void count_ncof_kernel(const uint64_t *edges, uint64_t n, int D, int B, unsigned long long *total) {
+  unsigned long long acc = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t R = (uint32_t)((edges[i] & ~IP_SIGN_BIT) >> (D * B)) & ((1u << D) - 1u);
+    int nR = __popc(R);
+    acc += (unsigned long long)(ifact(nR) * ifact(D + 1 - nR));
+  }
+  if (acc) atomicAdd(total, acc);
+}
+
+// Sec. V-B: n-simplex cofaces of the coarse intersecting edges, hashed to
+// remove duplicates; the winners are listed in discovery order.
+template <int D>
+__global__ __launch_bounds__(kBlock) void sigma_kernel(LatDev Lc, int LB, const uint64_t *__restrict__ edges,
+                                                       uint64_t n, uint64_t *sig_tab, uint64_t sig_mask,
+                                                       uint64_t *sig_list, Counters *ctr) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const uint64_t nchunks = (n + 63) >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (uint64_t ch = wave; ch < nchunks; ch += n_waves) {
+    const uint64_t ei = ch * 64 + lane;
+    uint64_t e = 0;
+    int cnt = 0;
+    if (ei < n) {
+      e = edges[ei];
+      cnt = n_cofacesn<D>((uint32_t)((e & ~IP_SIGN_BIT) >> (D * Lc.B)) & ((1u << D) - 1u));
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      int t = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += t;
+    }
+    const int excl = incl - cnt;
+    const int total = __shfl(incl, 63, 64);
+    for (int base = 0; base < total; base += 64) {
+      const int idx = base + lane;
+      const bool valid = idx < total;
+      int j = 0;
+#pragma unroll
+      for (int step = 32; step; step >>= 1) {
+        int pc = __shfl(excl, j + step, 64);
+        if (pc <= idx) j += step;
+      }
+      const uint64_t me = shfl64(e, j);
+      const int r = idx - __shfl(excl, j, 64);
+      bool is_new = false;
+      uint64_t key = 0;
+      if (valid) {
+        int32_t v[D];
+        uint32_t R;
+        eunpack<D>(Lc, me, v, &R);
+        const uint32_t Q = ((1u << (D + 1)) - 1u) & ~R;
+        const int nR = __popc(R), nQ = D + 1 - nR;
+        const int fQ = ifact(nQ);
+        // orderings of R and of Q from the factorial number system
+        int32_t pi[D + 1], rho[D + 1];
+        {
+          uint32_t code = (uint32_t)(r / fQ);
+          uint32_t avail = R;
+          for (int i = 0; i < nR; ++i) {
+            int f = ifact(nR - 1 - i);
+            int c = (int)(code / (uint32_t)f);
+            code %= (uint32_t)f;
+            pi[i] = nth_bit(avail, c);
+            avail &= ~(1u << pi[i]);
+          }
+          code = (uint32_t)(r % fQ);
+          avail = Q;
+          for (int i = 0; i < nQ; ++i) {
+            int f = ifact(nQ - 1 - i);
+            int c = (int)(code / (uint32_t)f);
+            code %= (uint32_t)f;
+            rho[i] = nth_bit(avail, c);
+            avail &= ~(1u << rho[i]);
+          }
+        }
+        // rotate the cycle (pi, rho) so that D comes last: the start vertex
+        // is v - 1_{rho after D}, the order is (rho after D, pi, rho before D)
+        int jd = 0;
+        for (int i = 0; i < nQ; ++i)
+          if (rho[i] == D) jd = i;
+        int32_t vs[D], w[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) vs[q] = v[q];
+        int m = 0;
+        for (int i = jd + 1; i < nQ; ++i) {
+          vs[rho[i]] -= 1;
+          w[m++] = rho[i];
+        }
+        for (int i = 0; i < nR; ++i) w[m++] = pi[i];
+        for (int i = 0; i < jd; ++i) w[m++] = rho[i];
+        if (vin_range<D>(Lc, vs)) {
+          key = sig_key<D>(Lc, vs, w, LB);
+          uint64_t slot;
+          int ins = ht_insert(sig_tab, sig_mask, key, &slot);
+          if (ins == 1)
+            is_new = true;
+          else if (ins < 0)
+            atomicOr(&ctr->et_fail, 1u);
+        } else {
+          atomicOr(&ctr->vt_fail, 1u);
+        }
+      }
+      const uint64_t bal = __ballot(is_new);
+      if (bal) {
+        const int leader = __ffsll((long long)bal) - 1;
+        unsigned long long b0 = 0;
+        if (lane == leader) b0 = atomicAdd(&ctr->n_aux, (unsigned long long)__popcll(bal));
+        b0 = shfl64(b0, leader);
+        if (is_new) sig_list[b0 + __popcll(bal & below)] = key;
+      }
+    }
+  }
+}
+
+// Template point p of coarse simplex (v, w) in fine lattice coordinates:
+// y_{w_i} = k v_{w_i} + u_i (Eq. 1 with the coarse edge directions e_{w_i}).
+template <int D>
+__device__ __forceinline__ void template_point(const int32_t *v, const int32_t *w, int k, uint64_t up, int32_t *y) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) y[w[i]] = k * v[w[i]] + (int32_t)((up >> (8 * i)) & 0xffu);
+}
+
+// Fine vertices of a batch of coarse simplices: insert into the batch vertex
+// table, remember the slot of every (simplex, template point).
+template <int D>
+__global__ __launch_bounds__(kBlock) void batch_vertices_kernel(LatDev Lf, LatDev Lc, int LB, int k,
+                                                                const uint64_t *__restrict__ sig, uint64_t nb,
+                                                                const uint64_t *__restrict__ tpts, int NP,
+                                                                uint64_t *vt_keys, uint64_t vt_mask,
+                                                                uint32_t *eval_list, uint32_t *pslot,
+                                                                Counters *ctr) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t total = nb * (uint64_t)NP;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t start = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t rounds = (total + stride - 1) / stride;
+  for (uint64_t it = 0; it < rounds; ++it) {
+    const uint64_t t = start + it * stride;
+    bool is_new = false;
+    uint64_t slot = 0;
+    if (t < total) {
+      const uint64_t s = t / (uint64_t)NP;
+      const int p = (int)(t - s * (uint64_t)NP);
+      int32_t v[D], w[D], y[D];
+      sig_unpack<D>(Lc, sig[s], LB, v, w);
+      template_point<D>(v, w, k, tpts[p], y);
+      double x[D];
+      lat_coords<D>(Lf, y, x);
+      uint32_t ps = 0xffffffffu;
+      if (lat_in_box<D>(Lf, x)) {
+        int ins = ht_insert(vt_keys, vt_mask, vpack<D>(Lf, y), &slot);
+        if (ins >= 0) {
+          ps = (uint32_t)slot;
+          is_new = ins == 1;
+        } else {
+          atomicOr(&ctr->vt_fail, 1u);
+        }
+      }
+      pslot[t] = ps;
+    }
+    const uint64_t bal = __ballot(is_new);
+    if (bal) {
+      const int leader = __ffsll((long long)bal) - 1;
+      unsigned long long b0 = 0;
+      if (lane == leader) b0 = atomicAdd(&ctr->n_eval, (unsigned long long)__popcll(bal));
+      b0 = shfl64(b0, leader);
+      if (is_new) eval_list[b0 + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)slot;
+    }
+  }
+}
+
+// Fine edges of the subdivision (Sec. V-B, Fig. 6): sign test on the two
+// endpoint values, insertion of the intersecting ones into the global fine
+// edge set; new edges are appended to the output key list.
+template <int D>
+__global__ __launch_bounds__(kBlock) void batch_edges_kernel(LatDev Lf, LatDev Lc, int LB, int k,
+                                                             const uint64_t *__restrict__ sig, uint64_t nb,
+                                                             const uint64_t *__restrict__ tpts, int NP,
+                                                             const uint32_t *__restrict__ tedge, int NE,
+                                                             const uint32_t *__restrict__ pslot,
+                                                             const double *__restrict__ vt_vals, uint64_t *et_keys,
+                                                             uint64_t et_mask, uint64_t *out, Counters *ctr) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t total = nb * (uint64_t)NE;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t start = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t rounds = (total + stride - 1) / stride;
+  unsigned long long hits = 0;
+  for (uint64_t it = 0; it < rounds; ++it) {
+    const uint64_t t = start + it * stride;
+    bool is_new = false;
+    uint64_t key = 0;
+    if (t < total) {
+      const uint64_t s = t / (uint64_t)NE;
+      const int e = (int)(t - s * (uint64_t)NE);
+      const uint32_t te = tedge[e];
+      const int a = (int)(te & 0xfffu), b = (int)((te >> 12) & 0xfffu);
+      const uint32_t Rl = te >> 24;
+      const uint32_t sa = pslot[s * NP + a], sb = pslot[s * NP + b];
+      if (sa != 0xffffffffu && sb != 0xffffffffu) {
+        const bool pa = !(vt_vals[sa] < 0.0), pb = !(vt_vals[sb] < 0.0);
+        if (pa != pb) {
+          ++hits;
+          int32_t v[D], w[D], y[D];
+          sig_unpack<D>(Lc, sig[s], LB, v, w);
+          template_point<D>(v, w, k, tpts[a], y);
+          uint32_t Rg = 0;
+#pragma unroll
+          for (int i = 0; i < D; ++i) Rg |= ((Rl >> i) & 1u) << w[i];
+          key = ekey<D>(Lf, y, Rg);
+          uint64_t slot;
+          int ins = ht_insert(et_keys, et_mask, key, &slot);
+          if (ins == 1)
+            is_new = true;
+          else if (ins < 0)
+            atomicOr(&ctr->et_fail, 1u);
+        }
+      }
+    }
+    const uint64_t bal = __ballot(is_new);
+    if (bal) {
+      const int leader = __ffsll((long long)bal) - 1;
+      unsigned long long b0 = 0;
+      if (lane == leader) b0 = atomicAdd(&ctr->n_out, (unsigned long long)__popcll(bal));
+      b0 = shfl64(b0, leader);
+      if (is_new) out[b0 + __popcll(bal & ((1ull << lane) - 1ull))] = key;
+    }
+  }
+  if (hits) atomicAdd(&ctr->n_cof, hits);
+}
+
+// Intersection points of the edges out[lo .. hi), endpoints looked up in the
+// batch vertex table.
+template <int D>
+__global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo, uint64_t hi, const uint64_t *vt_keys,
+                                    const double *vt_vals, uint64_t vt_mask, double *pts, int64_t ld) {
+  for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (uint64_t)gridDim.x * blockDim.x) {
+    int32_t a[D], b[D];
+    uint32_t R;
+    eunpack<D>(L, keys[i], a, &R);
+#pragma unroll
+    for (int j = 0; j < D; ++j) b[j] = a[j] + (int32_t)((R >> j) & 1u);
+    int64_t ha = ht_find(vt_keys, vt_mask, vpack<D>(L, a));
+    int64_t hb = ht_find(vt_keys, vt_mask, vpack<D>(L, b));
+    double fa = ha >= 0 ? vt_vals[ha] : NAN;
+    double fb = hb >= 0 ? vt_vals[hb] : NAN;
+    double xa[D], xb[D];
+    lat_coords<D>(L, a, xa);
+    lat_coords<D>(L, b, xb);
+    double t = fa / (fa - fb);
+#pragma unroll
+    for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = fma(t, xb[j] - xa[j], xa[j]);
+  }
+}
+
+__global__ void et_rebuild_keys_kernel(const uint64_t *keys, uint64_t n, uint64_t *et, uint64_t mask, Counters *ctr) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t slot;
+    if (ht_insert(et, mask, keys[i], &slot) < 0) atomicOr(&ctr->et_fail, 1u);
+  }
+}
+
+// Local subdivision template (Sec. V-B, Eq. 2 read with >=): points u with
+// k >= u_0 >= ... >= u_{d-1} >= 0 and edges (u, R) whose other end u + 1_R
+// is inside too.  Points packed 8 bits per coordinate; edges packed as
+// (index a | index b << 12 | R << 24).
+struct Template {
+  std::vector<uint64_t> pts;
+  std::vector<uint32_t> edges;
+};
+
+Template make_template(int d, int k) {
+  Template T;
+  std::vector<std::vector<int>> P;
+  std::vector<int> u(d, 0);
+  auto inside = [&](const std::vector<int> &x) {
+    if (x[0] > k) return false;
+    for (int i = 0; i + 1 < d; ++i)
+      if (x[i] < x[i + 1]) return false;
+    return x[d - 1] >= 0;
+  };
+  for (;;) {
+    if (inside(u)) P.push_back(u);
+    int j = 0;
+    while (j < d && u[j] == k) u[j++] = 0;
+    if (j == d) break;
+    ++u[j];
+  }
+  auto index_of = [&](const std::vector<int> &x) -> int {
+    for (size_t i = 0; i < P.size(); ++i)
+      if (P[i] == x) return (int)i;
+    return -1;
+  };
+  for (auto &x : P) {
+    uint64_t pk = 0;
+    for (int i = 0; i < d; ++i) pk |= (uint64_t)x[i] << (8 * i);
+    T.pts.push_back(pk);
+  }
+  for (size_t a = 0; a < P.size(); ++a)
+    for (uint32_t R = 1; R < (1u << d); ++R) {
+      std::vector<int> y = P[a];
+      for (int i = 0; i < d; ++i) y[i] += (int)((R >> i) & 1u);
+      if (!inside(y)) continue;
+      int b = index_of(y);
+      T.edges.push_back((uint32_t)a | ((uint32_t)b << 12) | (R << 24));
+    }
+  return T;
+}
+
+int lehmer_bits(int d) {
+  int f = ifact(d), b = 0;
+  while ((1 << b) < f) ++b;
+  return b < 1 ? 1 : b;
+}
+
+template <int D>
+int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res) {
+  ip_stats &st = res->st;
+  const int k = p->k;
+  const int LB = lehmer_bits(D);
+  if (D * p->coarse.B + LB > 63)
+    return ip_fail(ctx, IP_ERANGE, "coarse simplex keys do not fit 63 bits for this domain and k");
+  Template T = make_template(D, k);
+  const int NP = (int)T.pts.size(), NE = (int)T.edges.size();
+  if (NP >= 4096) return ip_fail(ctx, IP_EINVAL, "subdivision template too large (reduce k)");
+  // ---- coarse trace (Sec. V-B: trace at scale k * lambda)
+  Run s;
+  s.ctx = ctx;
+  s.p = p;
+  s.L = p->coarse;
+  IP_TRY(vt_init(s, 1ull << 16));
+  IP_TRY(et_init(s, 1ull << 16));
+  uint64_t nc = 0;
+  {
+    int rc = trace_direct<D>(s, st, &nc);
+    if (rc != IP_OK) {
+      if (s.out) (void)hipFree(s.out);
+      return rc;
+    }
+  }
+  uint64_t *coarse_edges = s.out;
+  s.out = nullptr;
+  s.out_cap = 0;
+  auto free_coarse = [&]() {
+    if (coarse_edges) (void)hipFree(coarse_edges);
+    coarse_edges = nullptr;
+  };
+  // ---- Sigma: n-cofaces of the coarse edges, deduplicated
+  void *sig_tab = nullptr, *sig_list = nullptr;
+  uint64_t nsig = 0;
+  {
+    IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+    if (nc) {
+      hipLaunchKernelGGL(count_ncof_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, ctx->stream, coarse_edges, nc, D,
+                         p->coarse.B, &ctx->ctr_dev->n_aux);
+      IP_TRY_HIP(ctx, hipGetLastError());
+    }
+    IP_TRY(read_ctr(ctx));
+    const uint64_t bound = ctx->ctr_host->n_aux;
+    const uint64_t cap = pow2_at_least(bound * 2 + 2);
+    int rc = alloc(ctx, &sig_tab, cap * 8);
+    if (rc == IP_OK) rc = alloc(ctx, &sig_list, (bound + 1) * 8);
+    if (rc != IP_OK) {
+      free_coarse();
+      if (sig_tab) (void)hipFree(sig_tab);
+      return rc;
+    }
+    IP_TRY(fill(ctx, sig_tab, cap, IP_EMPTY_KEY));
+    IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+    if (nc) {
+      hipLaunchKernelGGL((sigma_kernel<D>), dim3(grid_for(nc * 4, 8192)), dim3(kBlock), 0, ctx->stream, p->coarse, LB,
+                         coarse_edges, nc, (uint64_t *)sig_tab, cap - 1, (uint64_t *)sig_list, ctx->ctr_dev);
+      IP_TRY_HIP(ctx, hipGetLastError());
+    }
+    IP_TRY(read_ctr(ctx));
+    nsig = ctx->ctr_host->n_aux;
+    free_coarse();
+    (void)hipFree(sig_tab);
+    sig_tab = nullptr;
+  }
+  st.n_sigma = (int64_t)nsig;
+  // ---- template on the device
+  void *tpts = nullptr, *tedge = nullptr;
+  IP_TRY(alloc(ctx, &tpts, T.pts.size() * 8));
+  IP_TRY(alloc(ctx, &tedge, T.edges.size() * 4));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(tpts, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(tedge, T.edges.data(), T.edges.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  // ---- batches: per coarse simplex NP slots, NP vertex-table entries at
+  // load <= 1/2 (16 B key+value each, twice) and NP eval-list entries
+  const uint64_t per_sigma = (uint64_t)NP * (4 + 2 * 16 + 2 * 4);
+  if (budget == 0) budget = 4ull << 30;
+  if (budget < per_sigma) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
+  uint64_t B = budget / per_sigma;
+  if (B > nsig) B = nsig ? nsig : 1;
+  if (B * (uint64_t)NP * 2 > (1ull << 31)) B = (1ull << 31) / ((uint64_t)NP * 2);
+  Run f;
+  f.ctx = ctx;
+  f.p = p;
+  f.L = p->fine;
+  const uint64_t vcap = pow2_at_least(B * (uint64_t)NP * 2);
+  IP_TRY(ip_ensure(ctx, ctx->vt_keys, vcap * 8));
+  IP_TRY(ip_ensure(ctx, ctx->vt_vals, vcap * 8));
+  IP_TRY(ip_ensure(ctx, ctx->eval_list, vcap * 4));
+  IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * (uint64_t)NP * 4));
+  f.vt_keys = (uint64_t *)ctx->vt_keys.p;
+  f.vt_vals = (double *)ctx->vt_vals.p;
+  f.eval = (uint32_t *)ctx->eval_list.p;
+  f.vt_cap = f.eval_cap = vcap;
+  uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
+  // global fine edge set + output keys (capacity tied to the set's)
+  uint64_t et_cap = 1ull << 20;
+  IP_TRY(et_init(f, et_cap));
+  IP_TRY(out_reserve(f, et_cap, 0));
+  double *pts = nullptr;
+  uint64_t pts_ld = 0;
+  uint64_t n_out = 0;
+  Counters *c = ctx->ctr_host;
+  IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+  Timer tf, tx, tp;
+  int64_t batches = 0;
+  int rc = IP_OK;
+  for (uint64_t b0 = 0; b0 < nsig && rc == IP_OK; b0 += B) {
+    const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
+    const uint64_t *sig = (const uint64_t *)sig_list + b0;
+    ++batches;
+    IP_TRY(fill(ctx, f.vt_keys, vcap, IP_EMPTY_KEY));
+    IP_TRY(fill(ctx, f.vt_vals, vcap, IP_UNEVAL_BITS));
+    IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
+    IP_TRY(tx.start(ctx, &st.ms_expand));
+    hipLaunchKernelGGL((batch_vertices_kernel<D>), dim3(grid_for(nb * NP)), dim3(kBlock), 0, ctx->stream, p->fine,
+                       p->coarse, LB, k, sig, nb, (const uint64_t *)tpts, NP, f.vt_keys, vcap - 1, f.eval, pslot,
+                       ctx->ctr_dev);
+    IP_TRY_HIP(ctx, hipGetLastError());
+    IP_TRY(tx.stop(ctx));
+    IP_TRY(read_ctr(ctx));
+    if (c->vt_fail) {
+      rc = ip_fail(ctx, IP_ENOMEM, "batch vertex table overflow");
+      break;
+    }
+    IP_TRY(tf.start(ctx, &st.ms_feval));
+    IP_TRY(eval_pending(f, c->n_eval));
+    IP_TRY(tf.stop(ctx));
+    st.n_vertices += (int64_t)c->n_eval;
+    // keep the fine edge set at load <= 1/2 before the batch; on overflow
+    // grow it from the output keys (which include the partial appends of the
+    // failed launch) and replay the launch, which skips edges already present
+    const uint64_t batch_lo = n_out;
+    uint64_t n_keys = n_out;
+    int guard = 0;
+    for (;;) {
+      if (n_keys * 2 > f.et_cap || c->et_fail) {
+        if (++guard > 40) return ip_fail(ctx, IP_ENOMEM, "edge table cannot grow");
+        const uint64_t ncap = pow2_at_least(std::max<uint64_t>(n_keys * 4, f.et_cap * 2));
+        IP_TRY(out_reserve(f, ncap, n_keys));
+        void *nk = nullptr;
+        IP_TRY(alloc(ctx, &nk, ncap * 8));
+        IP_TRY(fill(ctx, nk, ncap, IP_EMPTY_KEY));
+        IP_TRY(zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->et_fail));
+        if (n_keys) {
+          hipLaunchKernelGGL(et_rebuild_keys_kernel, dim3(grid_for(n_keys)), dim3(kBlock), 0, ctx->stream, f.out,
+                             n_keys, (uint64_t *)nk, ncap - 1, ctx->ctr_dev);
+          IP_TRY_HIP(ctx, hipGetLastError());
+        }
+        IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        (void)hipFree(ctx->et_keys.p);
+        ctx->et_keys = {nk, ncap * 8};
+        f.et_keys = (uint64_t *)nk;
+        f.et_cap = ncap;
+        ++f.regrows;
+      }
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
+      IP_TRY(tx.start(ctx, &st.ms_expand));
+      hipLaunchKernelGGL((batch_edges_kernel<D>), dim3(grid_for(nb * NE)), dim3(kBlock), 0, ctx->stream, p->fine,
+                         p->coarse, LB, k, sig, nb, (const uint64_t *)tpts, NP, (const uint32_t *)tedge, NE, pslot,
+                         f.vt_vals, f.et_keys, f.et_cap - 1, f.out, ctx->ctr_dev);
+      IP_TRY_HIP(ctx, hipGetLastError());
+      IP_TRY(tx.stop(ctx));
+      IP_TRY(read_ctr(ctx));
+      if (!c->et_fail) break;
+      n_keys = c->n_out;
+    }
+    st.n_template_edges += (int64_t)(nb * (uint64_t)NE);
+    const uint64_t lo = batch_lo, hi = c->n_out;
+    if (hi > pts_ld) {
+      // grow the SoA point buffer, copying the columns
+      const uint64_t nld = std::max<uint64_t>(hi, pts_ld * 2);
+      double *np_ = nullptr;
+      IP_TRY(alloc(ctx, (void **)&np_, nld * D * 8));
+      if (pts && lo) {
+        for (int j = 0; j < D; ++j)
+          IP_TRY_HIP(ctx, hipMemcpyAsync(np_ + (uint64_t)j * nld, pts + (uint64_t)j * pts_ld, lo * 8,
+                                         hipMemcpyDeviceToDevice, ctx->stream));
+      }
+      IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      if (pts) (void)hipFree(pts);
+      pts = np_;
+      pts_ld = nld;
+    }
+    if (hi > lo) {
+      IP_TRY(tp.start(ctx, &st.ms_points));
+      hipLaunchKernelGGL((batch_points_kernel<D>), dim3(grid_for(hi - lo)), dim3(kBlock), 0, ctx->stream, p->fine, f.out,
+                         lo, hi, f.vt_keys, f.vt_vals, vcap - 1, pts, (int64_t)pts_ld);
+      IP_TRY_HIP(ctx, hipGetLastError());
+      IP_TRY(tp.stop(ctx));
+    }
+    n_out = hi;
+  }
+  IP_TRY(tf.flush(ctx));
+  IP_TRY(tx.flush(ctx));
+  IP_TRY(tp.flush(ctx));
+  (void)hipFree(tpts);
+  (void)hipFree(tedge);
+  (void)hipFree(sig_list);
+  if (rc != IP_OK) {
+    if (f.out) (void)hipFree(f.out);
+    if (pts) (void)hipFree(pts);
+    return rc;
+  }
+  if (!pts) IP_TRY(alloc(ctx, (void **)&pts, 8 * D));
+  res->d = D;
+  res->B = p->fine.B;
+  for (int j = 0; j < 8; ++j) res->vmin[j] = p->fine.vmin[j];
+  res->n = (int64_t)n_out;
+  res->keys = f.out;
+  res->pts = pts;
+  res->ld = (int64_t)(pts_ld ? pts_ld : 1);
+  st.n_cells = (int64_t)n_out;
+  st.n_batches = batches;
+  st.regrows += s.regrows + f.regrows;
+  return IP_OK;
+}
+
 template <int D>
 int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_cells *res) {
   (void)budget;
@@ -622,7 +1223,7 @@ int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_
   s.ctx = ctx;
   s.p = p;
   s.L = p->fine;
-  if (p->k != 1) return ip_fail(ctx, IP_EINVAL, "batch triangulation (coarse_k > 1) not available");
+  if (p->k != 1) return trace_batch<D>(ctx, p, budget, res);
   const uint64_t vt0 = std::max<uint64_t>(1ull << 20, ctx->vt_keys.bytes / 8);
   const uint64_t et0 = std::max<uint64_t>(1ull << 20, ctx->et_keys.bytes / 8);
   IP_TRY(vt_init(s, pow2_at_least(vt0) == vt0 ? vt0 : pow2_at_least(vt0) / 2));
