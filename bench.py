@@ -51,7 +51,7 @@ def flops_per_vertex(f) -> int:
     return f.S * (2 * f.d + f.p + 3)
 
 
-def cpu_baseline(wl, budget_s: float = 24.0):
+def cpu_baseline(wl, budget_s: float = 20.0):
     """The oracle (single thread) on a bounded sample of the same workload:
     the same manifold, scale and scene, traced inside a sub-box of the domain
     centred on the first seed, plus the collision check of those cells."""
@@ -71,8 +71,8 @@ def cpu_baseline(wl, budget_s: float = 24.0):
         v, m = O.trace_direct(sub)
         t_trace = time.perf_counter() - t0
         # the oracle's point pass re-evaluates f at both ends of every cell,
-        # about 4x the trace time; stop growing the sub-box at ~1/6 of budget
-        if t_trace > budget_s / 6 or half > 1.0:
+        # about 2.5x the trace time; stop growing the sub-box at ~1/8 of budget
+        if t_trace > budget_s / 8 or half > 1.0:
             break
         half *= 1.25
     t0 = time.perf_counter()

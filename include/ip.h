@@ -153,7 +153,8 @@ int ip_trace(ip_ctx *ctx, const ip_problem *p, uint64_t batch_budget_bytes,
 int64_t ip_cells_count(const ip_cells *c);
 int ip_cells_stats(const ip_cells *c, ip_stats *out);
 /* Copy cells to host buffers (any may be NULL): v (n x d int32, smaller
- * endpoint), mask (n, endpoint b = v + sum_{j in mask} e_j), pts (n x d). */
+ * endpoint), mask (n, endpoint b = v + sum_{j in mask} e_j), pts (n x d).
+ * ctx may be NULL: the context that traced the cells is used. */
 int ip_cells_download(ip_ctx *ctx, const ip_cells *c, int32_t *v, uint32_t *mask,
                       double *pts);
 /* Device view of the intersection points: SoA, pts[j * ld + i]. */
@@ -180,6 +181,62 @@ int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict,
  * bound used (0 for FP64 results). */
 int ip_feval(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n,
              int32_t precision, double *f_dev, double *bound_dev);
+
+/* ------------------------------------------------------------------------
+ * Serving loop (the proof requests of the planning loop, Sec. IV-A / Fig. 1:
+ * each retraining of the manifold produces a new trace + check request).
+ * A server owns max_slots slots, each a context with its own HIP stream and
+ * workspace, and one host thread per slot.  Requests queue in arrival order
+ * and are admitted to a free slot when the sum of the projected device bytes
+ * of the running requests plus the new one fits pool_bytes (a request larger
+ * than the pool runs alone).  Admitted requests run concurrently on their
+ * streams, so their kernels overlap on the device; a request's result does
+ * not depend on what else runs.
+ * ------------------------------------------------------------------------ */
+typedef struct ip_server ip_server;
+
+enum { IP_KEEP_CELLS = 1 };  /* request flag: keep the traced cells in the result */
+
+typedef struct {
+  const ip_fparams *f;       /* host, copied by ip_server_submit */
+  const ip_space *sp;        /* host, copied */
+  const double *seeds;       /* host, n_seeds x d, copied */
+  int64_t n_seeds;
+  int32_t coarse_k;
+  int32_t precision;         /* IP_FP64 or IP_FP32_CERTIFY */
+  const ip_scene *scene;     /* host, copied; NULL = trace only */
+  uint64_t batch_budget;     /* as for ip_trace */
+  uint64_t mem_bytes;        /* projected device bytes (admission); 0 = pool / slots */
+  uint32_t flags;            /* IP_KEEP_CELLS */
+} ip_request;
+
+typedef struct {
+  int32_t status;            /* IP_OK or the error code of the request */
+  int32_t d;
+  ip_stats stats;
+  int64_t n_cells;
+  int64_t n_free;
+  uint64_t digest[2];        /* order-independent digest of the traced edge keys:
+                                sum and xor of SplitMix64(key), mod 2^64 */
+  double t_submit, t_start, t_done;  /* seconds, server's monotonic clock */
+  double *free_pts;          /* host, n_free x d (NULL without a scene) */
+  ip_cells *cells;           /* with IP_KEEP_CELLS; download with ctx = NULL */
+  char error[160];
+} ip_result;
+
+int ip_server_create(ip_server **out, int device, uint64_t pool_bytes, int32_t max_slots);
+/* Queue a request; *id identifies it.  Inputs are copied before return. */
+int ip_server_submit(ip_server *s, const ip_request *req, uint64_t *id);
+/* IP_EAGAIN while the request is queued or running; then the result, which
+ * the caller releases with ip_result_free.  Each result is returned once. */
+int ip_server_poll(ip_server *s, uint64_t id, ip_result **out);
+int ip_server_wait(ip_server *s, uint64_t id, ip_result **out);
+void ip_result_free(ip_result *r);
+/* Waits for running requests, drops queued ones.  Results must be freed
+ * before their server is destroyed. */
+void ip_server_destroy(ip_server *s);
+/* Seconds on the server's clock (for arrival schedules). */
+double ip_server_clock(const ip_server *s);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // C ABI entry points (include/ip.h): argument validation, context and
 // handle management.  All device work is done by the kernels in trace.hip,
 // feval.hip and check.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -90,6 +91,105 @@ int build_lattice(ip_ctx *ctx, const ip_space *sp, int32_t mul, LatDev *L) {
   return IP_OK;
 }
 
+void mono_dfs(int d, int left, int jmin, std::vector<int> &cur, std::vector<std::vector<int>> &out) {
+  for (int j = jmin; j < d; ++j) {
+    cur.push_back(j);
+    out.push_back(cur);
+    if (left > 1) mono_dfs(d, left - 1, j, cur, out);
+    cur.pop_back();
+  }
+}
+
+double binom(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Monomial-basis coefficients of f and the error-bound constants of the FP32
+// certified path.  With t_i = gamma <s_i, x> + coef0,
+//   sum_i alpha_i t_i^p = sum_k C(p,k) coef0^(p-k) gamma^k sum_i alpha_i <s_i,x>^k
+// and <s_i,x>^k expands into the monomials of degree k with multinomial
+// weights.  Every FP64 step is covered by a forward error bound (Higham's
+// gamma_n = n u / (1 - n u), here with generous integer factors).
+int build_poly(ip_ctx *ctx, ip_problem *p, const ip_fparams *f, const ip_space *sp) {
+  p->poly = PolyDev{};
+  const int d = f->d, P = f->degree;
+  const int64_t S = f->n_sv;
+  if (P > 4) return IP_OK;
+  std::vector<std::vector<int>> monos;
+  std::vector<int> cur;
+  mono_dfs(d, P, 0, cur, monos);
+  const int M = (int)monos.size() + 1;
+  const double u64 = std::ldexp(1.0, -53), u32 = std::ldexp(1.0, -24);
+  double X[8], X2 = 0.0;
+  for (int j = 0; j < d; ++j) {
+    X[j] = std::max(std::fabs(sp->lo[j]), std::fabs(sp->hi[j])) * (1.0 + 1e-12);
+    X2 += X[j] * X[j];
+  }
+  X2 = std::sqrt(X2) * (1.0 + 1e-12);
+  std::vector<double> c(M), e(M);
+  double sum_a = 0.0, abs_a = 0.0, c0p = 1.0;
+  for (int64_t i = 0; i < S; ++i) {
+    sum_a += f->alpha[i];
+    abs_a += std::fabs(f->alpha[i]);
+  }
+  for (int q = 0; q < P; ++q) c0p *= f->coef0;
+  c[0] = c0p * sum_a + f->bias;
+  e[0] = u64 * ((double)(S + P + 4) * std::fabs(c0p) * abs_a + std::fabs(f->bias) + 2.0 * std::fabs(c[0])) * 1.01;
+  double fact[8] = {1, 1, 2, 6, 24, 120, 720, 5040};
+  for (size_t mi = 0; mi < monos.size(); ++mi) {
+    const std::vector<int> &m = monos[mi];
+    const int k = (int)m.size();
+    int cnt[8] = {0};
+    for (int j : m) ++cnt[j];
+    double multi = fact[k];
+    for (int j = 0; j < d; ++j) multi /= fact[cnt[j]];
+    double scale = binom(P, k) * multi;
+    for (int q = 0; q < P - k; ++q) scale *= f->coef0;
+    for (int q = 0; q < k; ++q) scale *= f->gamma;
+    double sum = 0.0, ab = 0.0;
+    for (int64_t i = 0; i < S; ++i) {
+      double t = f->alpha[i];
+      for (int j : m) t *= f->sv[i * d + j];
+      sum += t;
+      ab += std::fabs(t);
+    }
+    c[mi + 1] = scale * sum;
+    e[mi + 1] = u64 * ((double)(S + 2 * P + 4) * std::fabs(scale) * ab + (double)(2 * P + 12) * std::fabs(c[mi + 1])) * 1.01;
+  }
+  double E0 = e[0];
+  for (size_t mi = 0; mi < monos.size(); ++mi) {
+    double xm = 1.0;
+    for (int j : monos[mi]) xm *= X[j];
+    E0 += e[mi + 1] * xm * (1.0 + 1e-12);
+  }
+  double sg = 0.0;
+  for (int64_t i = 0; i < S; ++i) {
+    double nn = 0.0;
+    for (int j = 0; j < d; ++j) nn += f->sv[i * d + j] * f->sv[i * d + j];
+    double g = std::fabs(f->gamma) * std::sqrt(nn) * (1.0 + 1e-12) * X2 + std::fabs(f->coef0);
+    double gp = 1.0;
+    for (int q = 0; q < P; ++q) gp *= g;
+    sg += std::fabs(f->alpha[i]) * gp;
+  }
+  p->poly.B64 = u64 * (double)((P - 1) + P * (d + 2) + S + 3) * sg * 1.01 + 2.0 * u64 * std::fabs(f->bias);
+  p->poly.K32 = u32 * (double)(2 * P + M + 4) * (1.0 + (double)(M + 4) * u32) * 1.001;
+  p->poly.E0 = E0 * (1.0 + 1e-9);
+  p->poly.M = M;
+  p->poly.p = P;
+  std::vector<float> cf(M);
+  for (int m = 0; m < M; ++m) cf[m] = (float)c[m];
+  for (int m = 0; m < M; ++m)
+    if (!std::isfinite(cf[m])) return IP_OK;  // out of FP32 range: FP64 only
+  IP_TRY_HIP(ctx, hipMalloc((void **)&p->poly_dev, sizeof(float) * (size_t)M));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(p->poly_dev, cf.data(), sizeof(float) * (size_t)M, hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  p->poly.c = p->poly_dev;
+  p->poly.ok = 1;
+  return IP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -170,26 +270,13 @@ int ip_problem_create(ip_ctx *ctx, const ip_fparams *f, const ip_space *sp, cons
   // support-vector records: s_0..s_{d-1}, alpha, padding (64 bytes)
   const int64_t S = f->n_sv;
   std::vector<double> rec((size_t)S * 8, 0.0);
-  std::vector<float> rec32((size_t)S * 8, 0.0f);
-  p->sv_host.assign(f->sv, f->sv + S * d);
   for (int64_t i = 0; i < S; ++i) {
-    double nn = 0.0;
-    for (int j = 0; j < d; ++j) {
-      rec[i * 8 + j] = f->sv[i * d + j];
-      rec32[i * 8 + j] = (float)f->sv[i * d + j];
-      nn += f->sv[i * d + j] * f->sv[i * d + j];
-    }
+    for (int j = 0; j < d; ++j) rec[i * 8 + j] = f->sv[i * d + j];
     rec[i * 8 + d] = f->alpha[i];
-    rec32[i * 8 + d] = (float)f->alpha[i];
-    p->sum_abs_alpha += std::fabs(f->alpha[i]);
-    if (std::sqrt(nn) > p->sv_norm_max) p->sv_norm_max = std::sqrt(nn);
   }
   hipError_t e = hipMalloc((void **)&p->rec_dev, rec.size() * 8);
-  if (e == hipSuccess) e = hipMalloc((void **)&p->rec32_dev, rec32.size() * 4);
   if (e == hipSuccess) e = hipMalloc((void **)&p->seeds_dev, (size_t)n_seeds * d * 8);
   if (e == hipSuccess) e = hipMemcpyAsync(p->rec_dev, rec.data(), rec.size() * 8, hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->rec32_dev, rec32.data(), rec32.size() * 4, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(p->seeds_dev, seeds, (size_t)n_seeds * d * 8, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -200,12 +287,16 @@ int ip_problem_create(ip_ctx *ctx, const ip_fparams *f, const ip_space *sp, cons
   }
   p->n_seeds = n_seeds;
   p->f.rec = p->rec_dev;
-  p->f.rec32 = p->rec32_dev;
   p->f.S = S;
   p->f.p = f->degree;
   p->f.gamma = f->gamma;
   p->f.coef0 = f->coef0;
   p->f.bias = f->bias;
+  rc = build_poly(ctx, p, f, sp);
+  if (rc != IP_OK) {
+    ip_problem_free(p);
+    return rc;
+  }
   *out = p;
   return IP_OK;
 }
@@ -214,8 +305,8 @@ void ip_problem_free(ip_problem *p) {
   if (!p) return;
   if (p->ctx) (void)hipStreamSynchronize(p->ctx->stream);
   if (p->rec_dev) (void)hipFree(p->rec_dev);
-  if (p->rec32_dev) (void)hipFree(p->rec32_dev);
   if (p->seeds_dev) (void)hipFree(p->seeds_dev);
+  if (p->poly_dev) (void)hipFree(p->poly_dev);
   delete p;
 }
 
@@ -257,6 +348,7 @@ int ip_cells_stats(const ip_cells *c, ip_stats *out) {
 }
 
 int ip_cells_download(ip_ctx *ctx, const ip_cells *c, int32_t *v, uint32_t *mask, double *pts) {
+  if (!ctx && c) ctx = c->ctx;
   if (!ctx) return IP_EINVAL;
   if (!c) return ip_fail(ctx, IP_EINVAL, "null cells");
   const int64_t n = c->n;
@@ -329,6 +421,7 @@ int ip_check_cells(ip_ctx *ctx, ip_cells *c, const ip_scene *scene, int64_t *n_f
 }
 
 int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict, double *free_pts) {
+  if (!ctx && c) ctx = c->ctx;
   if (!ctx) return IP_EINVAL;
   if (!c || !c->verdict) return ip_fail(ctx, IP_EINVAL, "cells have not been checked");
   const int d = c->d;

@@ -203,28 +203,27 @@ __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__
   }
 }
 
-// Gather the free (verdict 0) points: wave ballot + one atomic per wave.
+// Gather the free (verdict 0) points: indices staged per wave in LDS, one
+// atomic per 128 free points, then the columns are copied.
 __global__ __launch_bounds__(256) void gather_free_kernel(const uint8_t *verdict, const double *pts, int64_t n,
                                                           int64_t ld, int d, double *free_pts, int64_t ld_free,
                                                           unsigned long long *count) {
-  const int lane = threadIdx.x & 63;
+  constexpr int kStage = 128;
+  __shared__ uint32_t st[4][kStage];
+  const int wib = threadIdx.x >> 6;
+  int sn = 0;
+  auto put = [&](unsigned long long pos, uint32_t i) {
+    for (int j = 0; j < d; ++j) free_pts[(int64_t)j * ld_free + (int64_t)pos] = pts[(int64_t)j * ld + (int64_t)i];
+  };
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t rounds = (n + stride - 1) / stride;
   for (int64_t it = 0; it < rounds; ++it) {
     const int64_t i = start + it * stride;
     const bool fr = i < n && verdict[i] == 0;
-    const uint64_t bal = __ballot(fr);
-    if (!bal) continue;
-    const int leader = __ffsll((long long)bal) - 1;
-    unsigned long long b0 = 0;
-    if (lane == leader) b0 = atomicAdd(count, (unsigned long long)__popcll(bal));
-    b0 = shfl64(b0, leader);
-    if (fr) {
-      const int64_t pos = (int64_t)b0 + __popcll(bal & ((1ull << lane) - 1ull));
-      for (int j = 0; j < d; ++j) free_pts[(int64_t)j * ld_free + pos] = pts[(int64_t)j * ld + i];
-    }
+    stage_put<kStage>(st[wib], sn, fr, (uint32_t)i, put, count);
   }
+  stage_flush(st[wib], sn, put, count);
 }
 
 int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
@@ -342,6 +341,7 @@ int ip_compact_free_impl(ip_ctx *ctx, ip_cells *c) {
     c->free_pts = nullptr;
   }
   const int64_t n = c->n;
+  if (n >= (1ll << 32)) return ip_fail(ctx, IP_EINVAL, "more than 2^32 cells in one check");
   IP_TRY_HIP(ctx, hipMalloc((void **)&c->free_pts, sizeof(double) * (size_t)(n ? n : 1) * c->d));
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
   if (n) {

@@ -1,21 +1,36 @@
 // f evaluation at lattice vertices (the edge sign tests of Sec. V-A and the
 // subdivision vertices of Sec. V-B need f at every vertex they touch).
 //
-// FP64 kernel: one lane per vertex, R vertices per lane (register blocking),
-// support vectors consumed in index order so the accumulation order is the
-// canonical one of ip.h and the result is bit-identical on every device.
-// Every lane of a wave reads the same 64-byte support-vector record at the
-// same time, so the record is a wave-uniform load served from the scalar
-// cache into SGPRs and used as the scalar operand of v_fma_f64.
+// Canonical FP64 kernel: one lane per vertex, R vertices per lane (register
+// blocking), support vectors consumed in index order so the accumulation
+// order is the canonical one of ip.h and the result is bit-identical on every
+// device.  Every lane of a wave reads the same 64-byte support-vector record
+// at the same time, so the record is a wave-uniform load served from the
+// scalar cache into SGPRs and used as the scalar operand of v_fma_f64.
+//
+// FP32 certified kernel: the decision function of a degree-p polynomial
+// kernel is a polynomial of degree p in d variables; it is evaluated in FP32
+// in its monomial basis (C(d+p, p) coefficients, precomputed on the host in
+// FP64 with rigorous error bounds) together with a rigorous bound B32 on
+// |f32 - F|, F the exact value at the canonical FP64 coordinates.  With B64 a
+// bound on |f64 - F| for the canonical FP64 value, a vertex with
+// |f32| > B32 + B64 has sign(f32) = sign(F) = sign(f64); every other vertex
+// is re-evaluated by the canonical FP64 kernel, so the sign bits, and the
+// traced set, equal the FP64 ones.
 #include "ip_internal.h"
 
 namespace {
 
-template <int D, int P, int R, bool FROM_KEYS>
+// MODE 0: vertex-table entries listed by slot (key at keys[slot * 4], result
+//         to out[slot * 4]);
+// MODE 1: raw int32 vertices, result to out[i];
+// MODE 2: raw int32 vertices at the indices in list, result to out[index].
+template <int D, int P, int R, int MODE>
 __global__ __launch_bounds__(256) void feval64_kernel(FDev F, LatDev L, const uint32_t *__restrict__ list,
                                                       uint64_t n, const uint64_t *__restrict__ keys,
                                                       const int32_t *__restrict__ vraw,
                                                       double *__restrict__ out) {
+  constexpr uint64_t S4 = MODE == 0 ? 4 : 1;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * R;
   for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * R; base < n; base += stride) {
     double x[R][D];
@@ -24,14 +39,15 @@ __global__ __launch_bounds__(256) void feval64_kernel(FDev F, LatDev L, const ui
     for (int r = 0; r < R; ++r) {
       uint64_t i = base + r < n ? base + r : n - 1;
       int32_t v[D];
-      if (FROM_KEYS) {
+      if (MODE == 0) {
         uint32_t s = list[i];
         dst[r] = s;
-        vunpack<D>(L, keys[s], v);
+        vunpack<D>(L, keys[(uint64_t)s * 4], v);
       } else {
-        dst[r] = i;
+        const uint64_t src = MODE == 2 ? (uint64_t)list[i] : i;
+        dst[r] = src;
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = vraw[i * D + j];
+        for (int j = 0; j < D; ++j) v[j] = vraw[src * D + j];
       }
       lat_coords<D>(L, v, x[r]);
     }
@@ -63,11 +79,11 @@ __global__ __launch_bounds__(256) void feval64_kernel(FDev F, LatDev L, const ui
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (base + r < n) out[dst[r]] = acc[r] + F.bias;
+      if (base + r < n) out[dst[r] * S4] = acc[r] + F.bias;
   }
 }
 
-template <int D, int P, bool FROM_KEYS>
+template <int D, int P, int MODE>
 void launch64(hipStream_t st, const FDev &F, const LatDev &L, const uint32_t *list, uint64_t n,
               const uint64_t *keys, const int32_t *vraw, double *out) {
   constexpr int R = D <= 4 ? 4 : 2;
@@ -75,34 +91,153 @@ void launch64(hipStream_t st, const FDev &F, const LatDev &L, const uint32_t *li
   uint64_t blocks = (threads + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) return;
-  hipLaunchKernelGGL((feval64_kernel<D, P, R, FROM_KEYS>), dim3((unsigned)blocks), dim3(256), 0, st, F, L,
-                     list, n, keys, vraw, out);
+  hipLaunchKernelGGL((feval64_kernel<D, P, R, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, F, L, list, n, keys,
+                     vraw, out);
 }
 
-template <int D, bool FROM_KEYS>
+template <int D, int MODE>
 void launch64_p(hipStream_t st, const FDev &F, const LatDev &L, const uint32_t *list, uint64_t n,
                 const uint64_t *keys, const int32_t *vraw, double *out) {
   switch (F.p) {
-    case 1: launch64<D, 1, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
-    case 2: launch64<D, 2, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
-    case 3: launch64<D, 3, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
-    case 4: launch64<D, 4, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
-    default: launch64<D, 0, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
+    case 1: launch64<D, 1, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 2: launch64<D, 2, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 3: launch64<D, 3, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 4: launch64<D, 4, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    default: launch64<D, 0, MODE>(st, F, L, list, n, keys, vraw, out); break;
   }
 }
 
-template <bool FROM_KEYS>
+template <int MODE>
 int dispatch64(ip_ctx *ctx, const FDev &F, const LatDev &L, const uint32_t *list, uint64_t n,
                const uint64_t *keys, const int32_t *vraw, double *out) {
   if (n == 0) return IP_OK;
   hipStream_t st = ctx->stream;
   switch (L.d) {
-    case 2: launch64_p<2, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
-    case 3: launch64_p<3, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
-    case 4: launch64_p<4, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
-    case 5: launch64_p<5, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
-    case 6: launch64_p<6, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
-    case 7: launch64_p<7, FROM_KEYS>(st, F, L, list, n, keys, vraw, out); break;
+    case 2: launch64_p<2, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 3: launch64_p<3, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 4: launch64_p<4, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 5: launch64_p<5, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 6: launch64_p<6, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 7: launch64_p<7, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
+  }
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 monomial-basis evaluation with certification
+// ---------------------------------------------------------------------------
+// Depth-first walk over the monomials x_{j1} x_{j2} ... x_{jk}, j1 <= ... <=
+// jk, k = 1..K, in the order the host stored the coefficients: at index J
+// the monomial mono * x_J, then its extensions by x_{j >= J}, then J + 1.
+template <int D, int K, int J>
+struct Mono {
+  static __device__ __forceinline__ void run(const float *x, float mono, const float *__restrict__ C, int &ci,
+                                             float &acc, float &aabs) {
+    if constexpr (J < D) {
+      const float m = mono * x[J];
+      const float c = C[ci];
+      ++ci;
+      acc = fmaf(c, m, acc);
+      aabs = fmaf(fabsf(c), fabsf(m), aabs);
+      if constexpr (K > 1) Mono<D, K - 1, J>::run(x, m, C, ci, acc, aabs);
+      Mono<D, K, J + 1>::run(x, mono, C, ci, acc, aabs);
+    }
+  }
+};
+
+// MODE 0: vertex-table slots (f to vt[slot].f, bound to vb[slot]);
+// MODE 1: raw vertices (f to out[i], bound to bout[i]).
+// Vertices the bound cannot settle get vb = -1 (resp. bout = 0) and are
+// appended to fb (slot, resp. index) for canonical FP64 re-evaluation.
+template <int D, int P, int MODE>
+__global__ __launch_bounds__(256) void feval32_kernel(PolyDev Q, LatDev L, const uint32_t *__restrict__ list,
+                                                      uint64_t n, VEnt *vt, float *vb,
+                                                      const int32_t *__restrict__ vraw, double *out, double *bout,
+                                                      uint32_t *fb, unsigned long long *fb_ctr) {
+  constexpr int kStage = 128;
+  __shared__ uint32_t st[4][kStage];
+  const int wib = threadIdx.x >> 6;
+  int sn = 0;
+  auto put = [&](unsigned long long pos, uint32_t s) { fb[pos] = s; };
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t start = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t rounds = (n + stride - 1) / stride;
+  for (uint64_t it = 0; it < rounds; ++it) {
+    const uint64_t i = start + it * stride;
+    bool unsure = false;
+    uint32_t id = 0;
+    if (i < n) {
+      int32_t v[D];
+      if (MODE == 0) {
+        id = list[i];
+        vunpack<D>(L, vt[id].key, v);
+      } else {
+        id = (uint32_t)i;
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = vraw[i * D + j];
+      }
+      double x64[D];
+      lat_coords<D>(L, v, x64);
+      float x[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) x[j] = (float)x64[j];
+      float acc = Q.c[0], aabs = fabsf(Q.c[0]);
+      int ci = 1;
+      Mono<D, P, 0>::run(x, 1.0f, Q.c, ci, acc, aabs);
+      const double b32 = Q.K32 * (double)aabs + Q.E0;
+      const double f32 = (double)acc;
+      unsure = !(fabs(f32) > b32 + Q.B64);
+      if (MODE == 0) {
+        if (!unsure) vt[id].f = f32;
+        vb[id] = unsure ? -1.0f : (float)(b32 * (1.0 + 1e-6));
+      } else {
+        out[i] = f32;
+        bout[i] = unsure ? 0.0 : b32 + Q.B64;
+      }
+    }
+    stage_put<kStage>(st[wib], sn, unsure, id, put, fb_ctr);
+  }
+  stage_flush(st[wib], sn, put, fb_ctr);
+}
+
+__global__ void set_vb_kernel(const uint32_t *list, uint64_t n, float *vb, float v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    vb[list[i]] = v;
+}
+
+template <int D, int MODE>
+void launch32_p(hipStream_t st, const PolyDev &Q, const LatDev &L, const uint32_t *list, uint64_t n, VEnt *vt,
+                float *vb, const int32_t *vraw, double *out, double *bout, uint32_t *fb, unsigned long long *fb_ctr) {
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) return;
+#define IP_L32(PP)                                                                                               \
+  hipLaunchKernelGGL((feval32_kernel<D, PP, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, Q, L, list, n, vt, vb, \
+                     vraw, out, bout, fb, fb_ctr)
+  switch (Q.p) {
+    case 1: IP_L32(1); break;
+    case 2: IP_L32(2); break;
+    case 3: IP_L32(3); break;
+    case 4: IP_L32(4); break;
+    default: break;
+  }
+#undef IP_L32
+}
+
+template <int MODE>
+int dispatch32(ip_ctx *ctx, const PolyDev &Q, const LatDev &L, const uint32_t *list, uint64_t n, VEnt *vt, float *vb,
+               const int32_t *vraw, double *out, double *bout, uint32_t *fb, unsigned long long *fb_ctr) {
+  if (n == 0) return IP_OK;
+  hipStream_t st = ctx->stream;
+  switch (L.d) {
+    case 2: launch32_p<2, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
+    case 3: launch32_p<3, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
+    case 4: launch32_p<4, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
+    case 5: launch32_p<5, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
+    case 6: launch32_p<6, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
+    case 7: launch32_p<7, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
     default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
   }
   IP_TRY_HIP(ctx, hipGetLastError());
@@ -112,13 +247,52 @@ int dispatch64(ip_ctx *ctx, const FDev &F, const LatDev &L, const uint32_t *list
 }  // namespace
 
 int launch_feval64(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n_list,
-                   const uint64_t *vt_keys, double *vt_vals) {
-  return dispatch64<true>(ctx, p->f, L, list, n_list, vt_keys, nullptr, vt_vals);
+                   VEnt *vt) {
+  return dispatch64<0>(ctx, p->f, L, list, n_list, (const uint64_t *)vt, nullptr, (double *)vt + 1);
+}
+
+int launch_feval32(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n_list,
+                   VEnt *vt, float *vb, uint32_t *fb, unsigned long long *fb_ctr) {
+  return dispatch32<0>(ctx, p->poly, L, list, n_list, vt, vb, nullptr, nullptr, nullptr, fb, fb_ctr);
+}
+
+int launch_set_vb(ip_ctx *ctx, const uint32_t *list, uint64_t n, float *vb, float v) {
+  if (n == 0) return IP_OK;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(set_vb_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, list, n, vb, v);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
 }
 
 int ip_feval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, int32_t prec,
                   double *f_dev, double *bound_dev) {
-  if (prec != IP_FP64) return ip_fail(ctx, IP_EINVAL, "ip_feval: precision not supported yet");
-  if (bound_dev) IP_TRY_HIP(ctx, hipMemsetAsync(bound_dev, 0, sizeof(double) * (size_t)n, ctx->stream));
-  return dispatch64<false>(ctx, p->f, p->fine, nullptr, (uint64_t)n, nullptr, v_dev, f_dev);
+  if (prec == IP_FP64 || !p->poly.ok) {
+    if (bound_dev) IP_TRY_HIP(ctx, hipMemsetAsync(bound_dev, 0, sizeof(double) * (size_t)n, ctx->stream));
+    return dispatch64<1>(ctx, p->f, p->fine, nullptr, (uint64_t)n, nullptr, v_dev, f_dev);
+  }
+  // FP32 pass, then canonical FP64 for the unsettled indices
+  double *bnd = bound_dev;
+  void *tmp_b = nullptr, *fbl = nullptr;
+  if (!bnd) {
+    IP_TRY_HIP(ctx, hipMalloc(&tmp_b, sizeof(double) * (size_t)n));
+    bnd = (double *)tmp_b;
+  }
+  IP_TRY_HIP(ctx, hipMalloc(&fbl, sizeof(uint32_t) * (size_t)n));
+  IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+  int rc = dispatch32<1>(ctx, p->poly, p->fine, nullptr, (uint64_t)n, nullptr, nullptr, v_dev, f_dev, bnd,
+                         (uint32_t *)fbl, &ctx->ctr_dev->n_fb);
+  unsigned long long nfb = 0;
+  if (rc == IP_OK) {
+    hipError_t e = hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) rc = ip_hip(ctx, e, "ip_feval counters");
+    nfb = ctx->ctr_host->n_fb;
+  }
+  if (rc == IP_OK) rc = dispatch64<2>(ctx, p->f, p->fine, (const uint32_t *)fbl, nfb, nullptr, v_dev, f_dev);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (tmp_b) (void)hipFree(tmp_b);
+  (void)hipFree(fbl);
+  ctx->last_fallback = (int64_t)nfb;
+  return rc;
 }

@@ -38,11 +38,24 @@ struct LatDev {
 // support vector: s_0..s_{d-1}, alpha, zero padding (8 doubles).
 struct FDev {
   const double *rec;
-  const float *rec32;   // the same records rounded to FP32
   int64_t S;
   int32_t p;
   int32_t pad;
   double gamma, coef0, bias;
+};
+
+// FP32 monomial-basis form of f (see feval.hip).  c[0] is the constant term
+// (bias included), c[1..M-1] the monomial coefficients in depth-first order.
+// For every vertex in the domain: |f32 - F| <= K32 * S_abs + E0, with S_abs
+// the FP32 sum of |c_m| |x^m| computed beside f32, and |f64 - F| <= B64 for
+// the canonical FP64 value, F the exact value at the canonical coordinates.
+struct PolyDev {
+  const float *c;
+  int32_t M;
+  int32_t p;
+  int32_t ok;   // 0: degree above 4, every vertex is evaluated in FP64
+  int32_t pad;
+  double K32, E0, B64;
 };
 
 struct Counters {
@@ -174,6 +187,91 @@ __device__ __forceinline__ int64_t ht_find(const uint64_t *keys, uint64_t mask, 
   return -1;
 }
 
+// Vertex-table entry: packed vertex key, f at the vertex (NaN payload while
+// pending), and a bitmask of the visited edges (v, R) whose smaller endpoint
+// is this vertex, bit R of the 2^d-bit mask (the edge set of the search).
+struct __attribute__((aligned(32))) VEnt {
+  uint64_t key;
+  double f;
+  unsigned long long m[2];
+};
+
+// Strided variants: the key of slot h lives at base[h * SW].
+template <int SW>
+__device__ __forceinline__ int ht_insert_s(uint64_t *base, uint64_t mask, uint64_t key, uint64_t *slot) {
+  uint64_t h = mix64(key) & mask;
+  for (uint64_t n = 0; n <= mask; ++n) {
+    uint64_t *p = base + h * SW;
+    uint64_t cur = ld_relaxed(p);
+    if (cur == key) {
+      *slot = h;
+      return 0;
+    }
+    if (cur == IP_EMPTY_KEY) {
+      uint64_t prev = atomicCAS((unsigned long long *)p, (unsigned long long)IP_EMPTY_KEY, (unsigned long long)key);
+      if (prev == IP_EMPTY_KEY || prev == key) {
+        *slot = h;
+        return prev == IP_EMPTY_KEY ? 1 : 0;
+      }
+    }
+    h = (h + 1) & mask;
+  }
+  return -1;
+}
+
+template <int SW>
+__device__ __forceinline__ int64_t ht_find_s(const uint64_t *base, uint64_t mask, uint64_t key) {
+  uint64_t h = mix64(key) & mask;
+  for (uint64_t n = 0; n <= mask; ++n) {
+    uint64_t cur = base[h * SW];
+    if (cur == key) return (int64_t)h;
+    if (cur == IP_EMPTY_KEY) return -1;
+    h = (h + 1) & mask;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ int vt_insert(VEnt *vt, uint64_t mask, uint64_t key, uint64_t *slot) {
+  return ht_insert_s<4>((uint64_t *)vt, mask, key, slot);
+}
+__device__ __forceinline__ int64_t vt_find(const VEnt *vt, uint64_t mask, uint64_t key) {
+  return ht_find_s<4>((const uint64_t *)vt, mask, key);
+}
+
+// Wave-level staged append: the lanes' items go to a per-wave LDS buffer and
+// are copied to the global list with one atomicAdd per STAGE items, instead
+// of one atomic per wave and step on a single counter.  All lanes of the
+// wave must call these together; `n` is wave-uniform.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, typename W>
+__device__ __forceinline__ void stage_flush(T *st, int &n, W writer, unsigned long long *ctr) {
+  if (n == 0) return;
+  wave_lds_sync();
+  const int lane = __lane_id();
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(ctr, (unsigned long long)n);
+  base = shfl64(base, 0);
+  for (int i = lane; i < n; i += 64) writer(base + (unsigned long long)i, st[i]);
+  wave_lds_sync();
+  n = 0;
+}
+
+template <int STAGE, typename T, typename W>
+__device__ __forceinline__ void stage_put(T *st, int &n, bool pred, const T &item, W writer,
+                                          unsigned long long *ctr) {
+  const uint64_t bal = __ballot(pred);
+  if (!bal) return;
+  const int nb = __popcll(bal);
+  if (n + nb > STAGE) stage_flush(st, n, writer, ctr);
+  if (pred) st[n + __popcll(bal & ((1ull << __lane_id()) - 1ull))] = item;
+  n += nb;
+}
+
 // Deposit the low bits of src into the set positions of mask (ascending).
 __device__ __forceinline__ uint32_t pdep32(uint32_t src, uint32_t mask) {
   uint32_t out = 0;
@@ -254,9 +352,11 @@ struct ip_ctx {
   Counters *ctr_dev = nullptr;
   Counters *ctr_host = nullptr;  // pinned
   // persistent workspace (grow-only)
-  DevBuf vt_keys, vt_vals, vt_aux, et_keys, eval_list, fb_list, scratch;
+  DevBuf vt_keys;   // vertex table (VEnt entries)
+  DevBuf vt_vals, vt_aux, et_keys, eval_list, fb_list, scratch;
   DevBuf scene;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int64_t last_fallback = 0;  // FP64 re-evaluations of the last ip_feval
 };
 
 struct ip_problem {
@@ -267,12 +367,10 @@ struct ip_problem {
   LatDev coarse;    // coarse lattice (mul = k); equal to fine when k = 1
   FDev f;
   double *rec_dev = nullptr;
-  float *rec32_dev = nullptr;
   double *seeds_dev = nullptr;
   int64_t n_seeds = 0;
-  double sum_abs_alpha = 0;
-  double sv_norm_max = 0;     // max over SVs of ||s_i||_2
-  std::vector<double> sv_host;  // n_sv x d
+  PolyDev poly = {};
+  float *poly_dev = nullptr;
 };
 
 struct ip_cells {
@@ -317,5 +415,12 @@ int ip_compact_free_impl(ip_ctx *ctx, ip_cells *c);
 
 // f evaluation of the vertices listed in `list` (slots of the vertex table);
 // results go into vt_vals[slot].  Defined in feval.hip.
+// FP32 certified evaluation of the listed slots: vt[slot].f and vb[slot]
+// (the bound, or -1 when the vertex needs FP64); unsettled slots are
+// appended to fb (counter fb_ctr).  Then set vb[list[i]] = v.
+int launch_feval32(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n_list,
+                   VEnt *vt, float *vb, uint32_t *fb, unsigned long long *fb_ctr);
+int launch_set_vb(ip_ctx *ctx, const uint32_t *list, uint64_t n, float *vb, float v);
+// vt: vertex-table entries; the result goes into vt[slot].f.
 int launch_feval64(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list,
-                   uint64_t n_list, const uint64_t *vt_keys, double *vt_vals);
+                   uint64_t n_list, VEnt *vt);

@@ -1,0 +1,315 @@
+// Serving loop (include/ip.h, ip_server_*): a queue of proof requests, slots
+// that each own a context (HIP stream + workspace) and a host thread, and
+// admission by projected device memory.  Requests on different slots run on
+// different streams, so their kernels overlap on the device; a request joins
+// as soon as a slot and memory are free, not when a whole batch finishes.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "ip_internal.h"
+
+namespace {
+
+// Order-independent digest of the traced edge keys.
+__global__ void digest_kernel(const uint64_t *keys, int64_t n, unsigned long long *sum, unsigned long long *x) {
+  unsigned long long s = 0, q = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t h = mix64(keys[i]);
+    s += h;
+    q ^= h;
+  }
+  for (int off = 32; off; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    q ^= __shfl_xor(q, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(sum, s);
+    atomicXor(x, q);
+  }
+}
+
+// Deep copy of a request's host inputs.
+struct OwnedRequest {
+  ip_fparams f;
+  ip_space sp;
+  ip_scene sc;
+  bool has_scene = false;
+  std::vector<double> sv, alpha, M, Minv, off, lo, hi, seeds;
+  std::vector<double> jT, lsc, lsr, lp0, lp1, lcr, osc, osr, obT, obl;
+  std::vector<int32_t> jax, lsl, lcl;
+  int64_t n_seeds = 0;
+  int32_t k = 1, prec = IP_FP64;
+  uint64_t budget = 0, bytes = 0;
+  uint32_t flags = 0;
+};
+
+template <typename T>
+std::vector<T> cp(const T *p, int64_t n) {
+  return (p && n > 0) ? std::vector<T>(p, p + n) : std::vector<T>();
+}
+
+void own(const ip_request *r, OwnedRequest &o) {
+  const int d = r->f->d;
+  o.sv = cp(r->f->sv, r->f->n_sv * d);
+  o.alpha = cp(r->f->alpha, r->f->n_sv);
+  o.f = *r->f;
+  o.f.sv = o.sv.data();
+  o.f.alpha = o.alpha.data();
+  o.M = cp(r->sp->M, d * d);
+  o.Minv = cp(r->sp->Minv, d * d);
+  o.off = cp(r->sp->offset, d);
+  o.lo = cp(r->sp->lo, d);
+  o.hi = cp(r->sp->hi, d);
+  o.sp = {d, o.M.data(), o.Minv.data(), o.off.data(), o.lo.data(), o.hi.data()};
+  o.n_seeds = r->n_seeds;
+  o.seeds = cp(r->seeds, r->n_seeds * d);
+  o.k = r->coarse_k;
+  o.prec = r->precision;
+  o.budget = r->batch_budget;
+  o.flags = r->flags;
+  if (r->scene) {
+    const ip_scene *s = r->scene;
+    o.has_scene = true;
+    o.jT = cp(s->joint_T, 12 * (int64_t)s->n_joints);
+    o.jax = cp(s->joint_axis, s->n_joints);
+    o.lsl = cp(s->lsph_link, s->n_lsph);
+    o.lsc = cp(s->lsph_c, 3 * (int64_t)s->n_lsph);
+    o.lsr = cp(s->lsph_r, s->n_lsph);
+    o.lcl = cp(s->lcap_link, s->n_lcap);
+    o.lp0 = cp(s->lcap_p0, 3 * (int64_t)s->n_lcap);
+    o.lp1 = cp(s->lcap_p1, 3 * (int64_t)s->n_lcap);
+    o.lcr = cp(s->lcap_r, s->n_lcap);
+    o.osc = cp(s->osph_c, 3 * (int64_t)s->n_osph);
+    o.osr = cp(s->osph_r, s->n_osph);
+    o.obT = cp(s->obox_T, 12 * (int64_t)s->n_obox);
+    o.obl = cp(s->obox_l, 3 * (int64_t)s->n_obox);
+    o.sc = {s->n_joints, o.jT.data(), o.jax.data(), s->n_lsph, o.lsl.data(), o.lsc.data(), o.lsr.data(),
+            s->n_lcap, o.lcl.data(), o.lp0.data(), o.lp1.data(), o.lcr.data(), s->n_osph, o.osc.data(),
+            o.osr.data(), s->n_obox, o.obT.data(), o.obl.data()};
+  }
+}
+
+struct Job {
+  OwnedRequest req;
+  ip_result *res = nullptr;
+  bool done = false;
+};
+
+}  // namespace
+
+struct ip_server {
+  int device = 0;
+  uint64_t pool = 0;
+  std::vector<ip_ctx *> ctxs;
+  std::vector<hipStream_t> streams;
+  std::vector<std::thread> workers;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, std::unique_ptr<Job>> jobs;
+  uint64_t next_id = 1;
+  uint64_t in_use = 0;
+  int running = 0;
+  bool stop = false;
+  std::chrono::steady_clock::time_point t0;
+
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+
+  void run_job(ip_ctx *ctx, Job &job) {
+    ip_result *r = job.res;
+    OwnedRequest &q = job.req;
+    r->d = q.f.d;
+    ip_problem *p = nullptr;
+    ip_cells *c = nullptr;
+    int rc = ip_problem_create(ctx, &q.f, &q.sp, q.seeds.data(), q.n_seeds, q.k, &p);
+    if (rc == IP_OK) rc = ip_trace(ctx, p, q.budget, q.prec, 0, &c);
+    if (rc == IP_OK && q.has_scene) rc = ip_check_cells(ctx, c, &q.sc, &r->n_free);
+    if (rc == IP_OK) {
+      unsigned long long *dg = &ctx->ctr_dev->n_aux;  // two adjacent counters
+      hipError_t e = hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream);
+      if (e == hipSuccess && c->n > 0) {
+        hipLaunchKernelGGL(digest_kernel, dim3(256), dim3(256), 0, ctx->stream, c->keys, c->n, &ctx->ctr_dev->n_eval,
+                           &ctx->ctr_dev->n_aux);
+        e = hipGetLastError();
+      }
+      (void)dg;
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+      if (e != hipSuccess) rc = ip_hip(ctx, e, "server digest");
+      r->digest[0] = ctx->ctr_host->n_eval;
+      r->digest[1] = ctx->ctr_host->n_aux;
+    }
+    if (rc == IP_OK) {
+      r->n_cells = c->n;
+      ip_cells_stats(c, &r->stats);
+      if (q.has_scene && r->n_free > 0) {
+        r->free_pts = new (std::nothrow) double[(size_t)r->n_free * q.f.d];
+        if (!r->free_pts)
+          rc = ip_fail(ctx, IP_ENOMEM, "host allocation failed");
+        else
+          rc = ip_cells_download_check(ctx, c, nullptr, r->free_pts);
+      }
+    }
+    if (rc == IP_OK && (q.flags & IP_KEEP_CELLS)) {
+      r->cells = c;
+      c = nullptr;
+    }
+    if (rc != IP_OK) snprintf(r->error, sizeof(r->error), "%s", ip_last_error(ctx));
+    r->status = rc;
+    if (c) ip_cells_free(c);
+    if (p) ip_problem_free(p);
+  }
+
+  void worker(int slot) {
+    ip_ctx *ctx = ctxs[slot];
+    (void)hipSetDevice(device);
+    for (;;) {
+      uint64_t id = 0;
+      Job *job = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] {
+          if (stop) return true;
+          if (queue.empty()) return false;
+          const uint64_t b = jobs[queue.front()]->req.bytes;
+          return in_use + b <= pool || running == 0;
+        });
+        if (stop) return;
+        id = queue.front();
+        queue.pop_front();
+        job = jobs[id].get();
+        in_use += job->req.bytes;
+        ++running;
+        job->res->t_start = now();
+      }
+      run_job(ctx, *job);
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        job->res->t_done = now();
+        job->done = true;
+        in_use -= job->req.bytes;
+        --running;
+      }
+      cv_done.notify_all();
+      cv_work.notify_all();
+    }
+  }
+};
+
+extern "C" {
+
+int ip_server_create(ip_server **out, int device, uint64_t pool_bytes, int32_t max_slots) {
+  if (!out) return IP_EINVAL;
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 64) return IP_EINVAL;
+  ip_server *s = new (std::nothrow) ip_server();
+  if (!s) return IP_ENOMEM;
+  s->device = device;
+  s->pool = pool_bytes ? pool_bytes : (64ull << 30);
+  s->t0 = std::chrono::steady_clock::now();
+  if (hipSetDevice(device) != hipSuccess) {
+    delete s;
+    return IP_EDEVICE;
+  }
+  for (int i = 0; i < max_slots; ++i) {
+    hipStream_t st = nullptr;
+    ip_ctx *c = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess || ip_create(&c, device, st) != IP_OK) {
+      if (st) (void)hipStreamDestroy(st);
+      ip_server_destroy(s);
+      return IP_EDEVICE;
+    }
+    s->streams.push_back(st);
+    s->ctxs.push_back(c);
+  }
+  for (int i = 0; i < max_slots; ++i) s->workers.emplace_back([s, i] { s->worker(i); });
+  *out = s;
+  return IP_OK;
+}
+
+int ip_server_submit(ip_server *s, const ip_request *req, uint64_t *id) {
+  if (!s || !req || !id || !req->f || !req->sp || !req->seeds || req->n_seeds < 1) return IP_EINVAL;
+  if (req->f->d < 2 || req->f->d > IP_MAX_D || req->sp->d != req->f->d) return IP_EINVAL;
+  if (req->scene && req->scene->n_joints != req->f->d) return IP_EINVAL;
+  auto job = std::unique_ptr<Job>(new (std::nothrow) Job());
+  if (!job) return IP_ENOMEM;
+  own(req, job->req);
+  job->req.bytes = req->mem_bytes ? req->mem_bytes : s->pool / std::max<size_t>(1, s->ctxs.size());
+  job->res = new (std::nothrow) ip_result();
+  if (!job->res) return IP_ENOMEM;
+  memset(job->res, 0, sizeof(ip_result));
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    job->res->t_submit = s->now();
+    *id = s->next_id++;
+    s->jobs[*id] = std::move(job);
+    s->queue.push_back(*id);
+  }
+  s->cv_work.notify_all();
+  return IP_OK;
+}
+
+int ip_server_poll(ip_server *s, uint64_t id, ip_result **out) {
+  if (!s || !out) return IP_EINVAL;
+  *out = nullptr;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(id);
+  if (it == s->jobs.end()) return IP_EINVAL;
+  if (!it->second->done) return IP_EAGAIN;
+  *out = it->second->res;
+  s->jobs.erase(it);
+  return IP_OK;
+}
+
+int ip_server_wait(ip_server *s, uint64_t id, ip_result **out) {
+  if (!s || !out) return IP_EINVAL;
+  *out = nullptr;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(id);
+  if (it == s->jobs.end()) return IP_EINVAL;
+  Job *job = it->second.get();
+  s->cv_done.wait(lk, [&] { return job->done; });
+  *out = job->res;
+  s->jobs.erase(id);
+  return IP_OK;
+}
+
+void ip_result_free(ip_result *r) {
+  if (!r) return;
+  delete[] r->free_pts;
+  if (r->cells) ip_cells_free(r->cells);
+  delete r;
+}
+
+void ip_server_destroy(ip_server *s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->queue.clear();
+  }
+  s->cv_work.notify_all();
+  for (auto &t : s->workers)
+    if (t.joinable()) t.join();
+  for (auto &kv : s->jobs) {
+    if (kv.second->res) ip_result_free(kv.second->res);
+  }
+  s->jobs.clear();
+  for (ip_ctx *c : s->ctxs) ip_destroy(c);
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  delete s;
+}
+
+double ip_server_clock(const ip_server *s) { return s ? s->now() : 0.0; }
+
+}  // extern "C"

@@ -1,17 +1,21 @@
-// Manifold tracing on the Coxeter triangulation (Sec. V-A, Figs. 3-4).
+// Manifold tracing on the Coxeter triangulation (Sec. V-A, Figs. 3-4) and
+// batch triangulation (Sec. V-B, Figs. 5-6).
 //
-// State lives in three device hash tables / lists:
-//   VT  vertex table: packed vertex key -> f (FP64; NaN payload = pending).
-//       Every lattice vertex the search touches is evaluated once.
-//   ET  edge table: packed canonical edge keys (the visited set).
-//   OUT append-only list of traced edges; the frontier of a level is a
-//       contiguous range of it (the edges inserted by the previous level).
-// One breadth-first level = pass 1 (enumerate the 2-cofaces of the frontier
-// edges, insert their third vertices into VT, list the new ones), f
-// evaluation of the new vertices, pass 2 (for each coface pick the one other
-// edge that changes sign, insert it into ET, append winners to OUT).
-// The host reads a small counter block after each pass to size the next
-// launch and to grow tables; growth replays a pass, which is idempotent.
+// Direct mode state:
+//   VT   vertex table (open addressing, 32-byte VEnt entries): packed vertex
+//        key, f at the vertex, and a bitmask of the visited edges whose
+//        smaller endpoint is this vertex.  The bitmask is the search's
+//        visited set: marking edge (v, R) is one atomicOr on bit R of v's
+//        entry, an entry the search touches anyway.
+//   OUT  append-only list of traced edges (key + the VT slots of both ends);
+//        the frontier of a level is a contiguous range of it.
+//   CSL  per level, the VT slot of the third vertex of every coface.
+// One breadth-first level = pass 1 (third vertices of the 2-cofaces of the
+// frontier edges into VT, slots into CSL, new vertices listed), f evaluation
+// of the new vertices, pass 2 (per coface: the other sign-changing edge is
+// marked in its smaller endpoint's entry; first markers append to OUT).
+// The host reads a small counter block after each pass; table growth rehashes
+// VT, re-points OUT's slots and replays pass 1, which is idempotent.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -21,10 +25,27 @@
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kStage = 128;  // per-wave staged append entries
+
+struct OutRec {
+  uint64_t key;
+  uint64_t slots;  // slot of the smaller endpoint | slot of the other << 32
+};
 
 __global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+__global__ void fill_vent_kernel(VEnt *p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    VEnt e;
+    e.key = IP_EMPTY_KEY;
+    e.f = __longlong_as_double((long long)IP_UNEVAL_BITS);
+    e.m[0] = 0ull;
+    e.m[1] = 0ull;
+    p[i] = e;
+  }
 }
 
 __global__ void zero_counter_kernel(unsigned long long *p) { *p = 0ull; }
@@ -58,11 +79,19 @@ __device__ void locate(const LatDev &L, const double *y, int32_t *v, int32_t *w)
   }
 }
 
+// Mark edge (v, mask) in the entry of its smaller endpoint; true if this
+// call was the first to mark it.
+__device__ __forceinline__ bool mark_edge(VEnt *vt, uint64_t owner, uint32_t mask) {
+  const unsigned long long bit = 1ull << (mask & 63u);
+  const unsigned long long old = atomicOr(&vt[owner].m[mask >> 6], bit);
+  return !(old & bit);
+}
+
 // Sec. V-A "find all n-simplices": locate each seed and register the
 // vertices of its n-simplex that lie in the domain.
 template <int D>
-__global__ void seed_vertices_kernel(LatDev L, const double *seeds, int64_t ns, uint64_t *vt_keys,
-                                     uint64_t vt_mask, uint32_t *eval_list, Counters *ctr) {
+__global__ void seed_vertices_kernel(LatDev L, const double *seeds, int64_t ns, VEnt *vt, uint64_t vt_mask,
+                                     uint32_t *eval_list, Counters *ctr) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ns) return;
   int32_t v[D], w[D];
@@ -73,7 +102,7 @@ __global__ void seed_vertices_kernel(LatDev L, const double *seeds, int64_t ns, 
     lat_coords<D>(L, v, x);
     if (!lat_in_box<D>(L, x)) continue;
     uint64_t slot;
-    int r = ht_insert(vt_keys, vt_mask, vpack<D>(L, v), &slot);
+    int r = vt_insert(vt, vt_mask, vpack<D>(L, v), &slot);
     if (r == 1) {
       unsigned long long idx = atomicAdd(&ctr->n_eval, 1ull);
       eval_list[idx] = (uint32_t)slot;
@@ -86,9 +115,8 @@ __global__ void seed_vertices_kernel(LatDev L, const double *seeds, int64_t ns, 
 
 // Sec. V-A "find all interesting n-simplices' edges" + "hash all edges".
 template <int D>
-__global__ void seed_edges_kernel(LatDev L, const double *seeds, int64_t ns, const uint64_t *vt_keys,
-                                  const double *vt_vals, uint64_t vt_mask, uint64_t *et_keys,
-                                  uint64_t et_mask, uint64_t *out, Counters *ctr) {
+__global__ void seed_edges_kernel(LatDev L, const double *seeds, int64_t ns, VEnt *vt, uint64_t vt_mask,
+                                  OutRec *out, Counters *ctr) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ns) return;
   int32_t v[D], w[D], u[D + 1][D];
@@ -100,29 +128,25 @@ __global__ void seed_edges_kernel(LatDev L, const double *seeds, int64_t ns, con
     for (int j = 0; j < D; ++j) u[m + 1][j] = u[m][j];
     u[m + 1][w[m]] += 1;
   }
+  int64_t sl[D + 1];
   double fv[D + 1];
-  bool inb[D + 1];
   for (int m = 0; m <= D; ++m) {
-    int64_t h = vin_range<D>(L, u[m]) ? ht_find(vt_keys, vt_mask, vpack<D>(L, u[m])) : -1;
-    inb[m] = h >= 0;
-    fv[m] = inb[m] ? vt_vals[h] : 0.0;
+    sl[m] = vin_range<D>(L, u[m]) ? vt_find(vt, vt_mask, vpack<D>(L, u[m])) : -1;
+    fv[m] = sl[m] >= 0 ? vt[sl[m]].f : 0.0;
   }
   for (int a = 0; a <= D; ++a)
     for (int b = a + 1; b <= D; ++b) {
-      if (!inb[a] || !inb[b]) continue;
-      bool sa = !(fv[a] < 0.0), sb = !(fv[b] < 0.0);
+      if (sl[a] < 0 || sl[b] < 0) continue;
+      const bool sa = !(fv[a] < 0.0), sb = !(fv[b] < 0.0);
       if (sa == sb) continue;
       int32_t vm[D];
       uint32_t mask;
-      bool a_min = edge_canon<D>(u[a], u[b], vm, &mask);
-      uint64_t key = ekey<D>(L, vm, mask);
-      uint64_t slot;
-      int r = ht_insert(et_keys, et_mask, key, &slot);
-      if (r == 1) {
+      const bool a_min = edge_canon<D>(u[a], u[b], vm, &mask);
+      const uint64_t smin = (uint64_t)(a_min ? sl[a] : sl[b]), smax = (uint64_t)(a_min ? sl[b] : sl[a]);
+      if (mark_edge(vt, smin, mask)) {
         unsigned long long idx = atomicAdd(&ctr->n_out, 1ull);
-        out[idx] = key | ((a_min ? sa : sb) ? IP_SIGN_BIT : 0ull);
-      } else if (r < 0) {
-        atomicOr(&ctr->et_fail, 1u);
+        out[idx].key = ekey<D>(L, vm, mask) | ((a_min ? sa : sb) ? IP_SIGN_BIT : 0ull);
+        out[idx].slots = smin | (smax << 32);
       }
     }
 }
@@ -131,26 +155,31 @@ __global__ void seed_edges_kernel(LatDev L, const double *seeds, int64_t ns, con
 // cofaces' edges" / "hash all edges").  Each wave takes 64 frontier edges,
 // prefix-sums their coface counts and walks the flattened (edge, coface)
 // list 64 at a time, so lanes stay busy whatever the mix of edge classes.
-//   EDGES = false: pass 1, register third vertices in VT.
-//   EDGES = true : pass 2, sign test and insertion of the new edge.
+//   EDGES = false: pass 1, third vertices into VT and CSL.
+//   EDGES = true : pass 2, sign test and marking of the new edge.
 template <int D, bool EDGES>
-__global__ __launch_bounds__(kBlock) void expand_kernel(LatDev L, const uint64_t *__restrict__ front,
-                                                        uint64_t lo, uint64_t hi, uint64_t *vt_keys,
-                                                        const double *__restrict__ vt_vals, uint64_t vt_mask,
-                                                        uint32_t *eval_list, uint64_t *et_keys,
-                                                        uint64_t et_mask, uint64_t *out, Counters *ctr) {
+__global__ __launch_bounds__(kBlock) void expand_kernel(LatDev L, OutRec *out, uint64_t lo, uint64_t hi, VEnt *vt,
+                                                        uint64_t vt_mask, uint32_t *cslot, uint32_t *eval_list,
+                                                        Counters *ctr) {
+  constexpr int MAXC = (1 << D) - 2;  // most 2-cofaces an edge can have
+  __shared__ OutRec st_out[EDGES ? kBlock / 64 : 1][EDGES ? kStage : 1];
+  __shared__ uint32_t st_ev[EDGES ? 1 : kBlock / 64][EDGES ? 1 : kStage];
   const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   const uint64_t nchunks = (hi - lo + 63) >> 6;
-  const uint64_t below = (1ull << lane) - 1ull;
+  int sn = 0;
   unsigned long long cof_acc = 0, new_acc = 0;
+  auto put_out = [&](unsigned long long pos, const OutRec &r) { out[pos] = r; };
+  auto put_ev = [&](unsigned long long pos, uint32_t s) { eval_list[pos] = s; };
   for (uint64_t ch = wave; ch < nchunks; ch += n_waves) {
     const uint64_t ei = lo + ch * 64 + lane;
-    uint64_t e = 0;
+    uint64_t e = 0, es = 0;
     int cnt = 0;
     if (ei < hi) {
-      e = front[ei];
+      e = out[ei].key;
+      if (EDGES) es = out[ei].slots;
       cnt = n_cofaces2<D>((uint32_t)((e & ~IP_SIGN_BIT) >> (D * L.B)) & ((1u << D) - 1u));
     }
     int incl = cnt;
@@ -174,142 +203,202 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LatDev L, const uint64_t
       }
       const uint64_t me = shfl64(e, j);
       const int r = idx - __shfl(excl, j, 64);
-      bool is_new = false;
-      uint64_t payload = 0;
-      if (valid) {
-        int32_t v[D], c[D];
-        uint32_t R;
-        eunpack<D>(L, me, v, &R);
-        coface_vertex<D>(v, R, r, c);
-        if (!EDGES) {
+      const uint64_t crow = (ch * 64 + (uint64_t)j) * MAXC + (uint64_t)r;
+      if (!EDGES) {
+        bool is_new = false;
+        uint32_t slot32 = 0;
+        if (valid) {
+          int32_t v[D], c[D];
+          uint32_t R;
+          eunpack<D>(L, me, v, &R);
+          coface_vertex<D>(v, R, r, c);
           double x[D];
           lat_coords<D>(L, c, x);
+          uint32_t cs = 0xffffffffu;
           if (lat_in_box<D>(L, x)) {
             uint64_t slot;
-            int ins = ht_insert(vt_keys, vt_mask, vpack<D>(L, c), &slot);
-            if (ins == 1) {
-              is_new = true;
-              payload = slot;
-            } else if (ins < 0) {
+            int ins = vt_insert(vt, vt_mask, vpack<D>(L, c), &slot);
+            if (ins >= 0) {
+              cs = (uint32_t)slot;
+              is_new = ins == 1;
+              slot32 = cs;
+            } else {
               atomicOr(&ctr->vt_fail, 1u);
             }
           }
-        } else {
-          const int64_t h = vin_range<D>(L, c) ? ht_find(vt_keys, vt_mask, vpack<D>(L, c)) : -1;
-          if (h >= 0) {
-            const bool sc = !(vt_vals[h] < 0.0);
+          cslot[crow] = cs;
+        }
+        new_acc += (unsigned long long)__popcll(__ballot(is_new));
+        stage_put<kStage>(st_ev[wib], sn, is_new, slot32, put_ev, &ctr->n_eval);
+      } else {
+        const uint64_t mslots = shfl64(es, j);
+        bool is_new = false;
+        OutRec rec = {0, 0};
+        if (valid) {
+          const uint32_t cs = cslot[crow];
+          if (cs != 0xffffffffu) {
+            const bool sc = !(vt[cs].f < 0.0);
             const bool sa = (me & IP_SIGN_BIT) != 0;
+            int32_t v[D], c[D];
+            uint32_t R;
+            eunpack<D>(L, me, v, &R);
+            coface_vertex<D>(v, R, r, c);
             // exactly one of (a,c), (b,c) changes sign: the one whose other
             // end has the sign c does not have (Sec. V-A, two edges of a
             // triangle cross the manifold)
             int32_t other[D];
             bool so;
+            uint64_t oslot;
             if (sc != sa) {
 #pragma unroll
               for (int q = 0; q < D; ++q) other[q] = v[q];
               so = sa;
+              oslot = mslots & 0xffffffffull;
             } else {
 #pragma unroll
               for (int q = 0; q < D; ++q) other[q] = v[q] + (int32_t)((R >> q) & 1u);
               so = !sa;
+              oslot = mslots >> 32;
             }
             int32_t vm[D];
             uint32_t mask;
             const bool other_min = edge_canon<D>(other, c, vm, &mask);
-            const uint64_t key = ekey<D>(L, vm, mask);
-            uint64_t slot;
-            int ins = ht_insert(et_keys, et_mask, key, &slot);
-            if (ins == 1) {
+            const uint64_t smin = other_min ? oslot : (uint64_t)cs, smax = other_min ? (uint64_t)cs : oslot;
+            if (mark_edge(vt, smin, mask)) {
               is_new = true;
-              payload = key | ((other_min ? so : sc) ? IP_SIGN_BIT : 0ull);
-            } else if (ins < 0) {
-              atomicOr(&ctr->et_fail, 1u);
+              rec.key = ekey<D>(L, vm, mask) | ((other_min ? so : sc) ? IP_SIGN_BIT : 0ull);
+              rec.slots = smin | (smax << 32);
             }
           }
         }
-      }
-      // wave-aggregated append
-      const uint64_t bal = __ballot(is_new);
-      if (bal) {
-        const int nb = __popcll(bal);
-        const int leader = __ffsll((long long)bal) - 1;
-        unsigned long long b0 = 0;
-        if (lane == leader) b0 = atomicAdd(EDGES ? &ctr->n_out : &ctr->n_eval, (unsigned long long)nb);
-        b0 = shfl64(b0, leader);
-        if (is_new) {
-          const unsigned long long pos = b0 + (unsigned long long)__popcll(bal & below);
-          if (EDGES)
-            out[pos] = payload;
-          else
-            eval_list[pos] = (uint32_t)payload;
-        }
-        new_acc += (unsigned long long)nb;
+        stage_put<kStage>(st_out[wib], sn, is_new, rec, put_out, &ctr->n_out);
       }
     }
   }
-  if (lane == 0) {
-    if (!EDGES) {
-      if (cof_acc) atomicAdd(&ctr->n_cof, cof_acc);
-      if (new_acc) atomicAdd(&ctr->vt_count, new_acc);
-    }
+  if (EDGES)
+    stage_flush(st_out[wib], sn, put_out, &ctr->n_out);
+  else
+    stage_flush(st_ev[wib], sn, put_ev, &ctr->n_eval);
+  if (!EDGES && lane == 0) {
+    if (cof_acc) atomicAdd(&ctr->n_cof, cof_acc);
+    if (new_acc) atomicAdd(&ctr->vt_count, new_acc);
   }
 }
 
-// Sec. V-B intersection points: t = f_a/(f_a - f_b), p = x_a + t (x_b - x_a).
+// Intersection point of edge (a, b), a the smaller endpoint (Sec. V-B):
+// t = f_a / (f_a - f_b), p = x_a + t (x_b - x_a).  With certification on
+// (FP32 mode), ba / bb bound |f - F| at the ends (-1: canonical FP64 value,
+// bound B64), and the call returns false when the a-priori bound on the
+// distance to the point computed from canonical FP64 values exceeds half the
+// FP32 tolerance, 1e-5 relative (|dt| <= (da + db + 2 B64) / (|fa| + |fb| -
+// da - db - 2 B64) since f_a and f_b have opposite signs).
 template <int D>
-__global__ void points_kernel(LatDev L, uint64_t *keys, uint64_t n, const uint64_t *vt_keys,
-                              const double *vt_vals, uint64_t vt_mask, double *pts, int64_t ld) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t key = keys[i] & ~IP_SIGN_BIT;
-    keys[i] = key;
+__device__ __forceinline__ bool edge_point(const LatDev &L, const int32_t *a, const int32_t *b, double fa, double fb,
+                                           bool cert, float ba, float bb, double B64, double *p) {
+  double xa[D], xb[D];
+  lat_coords<D>(L, a, xa);
+  lat_coords<D>(L, b, xb);
+  const double t = fa / (fa - fb);
+#pragma unroll
+  for (int j = 0; j < D; ++j) p[j] = fma(t, xb[j] - xa[j], xa[j]);
+  if (!cert || (ba < 0.0f && bb < 0.0f)) return true;
+  const double da = ba < 0.0f ? B64 : (double)ba, db = bb < 0.0f ? B64 : (double)bb;
+  const double num = da + db + 2.0 * B64;
+  const double den = fabs(fa) + fabs(fb) - num;
+  if (!(den > 0.0)) return false;
+  double dx = 0.0, pn = 1.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    dx = fmax(dx, fabs(xb[j] - xa[j]));
+    pn = fmax(pn, fabs(p[j]));
+  }
+  return (num / den) * dx + 1e-15 * pn <= 0.5e-5 * pn;
+}
+
+// Record an edge whose point must be recomputed from FP64 values: its index
+// goes to redo, the ends that hold FP32 values go to fb.
+__device__ __forceinline__ void need_fp64(uint64_t i, uint64_t sa, uint64_t sb, const float *vb, uint64_t *redo,
+                                          uint32_t *fb, Counters *ctr) {
+  redo[atomicAdd(&ctr->n_aux, 1ull)] = i;
+  if (vb[sa] >= 0.0f) fb[atomicAdd(&ctr->n_fb, 1ull)] = (uint32_t)sa;
+  if (vb[sb] >= 0.0f) fb[atomicAdd(&ctr->n_fb, 1ull)] = (uint32_t)sb;
+}
+
+// Points of the traced edges, f read from the slots carried by the edges.
+// REDO = false: all edges (also clears the sign bits into keys);
+// REDO = true : the edges listed in redo, after their ends went to FP64.
+template <int D, bool REDO>
+__global__ void points_kernel(LatDev L, const OutRec *out, uint64_t n, const VEnt *vt, uint64_t *keys, double *pts,
+                              int64_t ld, bool cert, const float *vb, double B64, uint64_t *redo, uint32_t *fb,
+                              Counters *ctr) {
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = REDO ? redo[q] : q;
+    const OutRec o = out[i];
+    const uint64_t key = o.key & ~IP_SIGN_BIT;
+    if (!REDO) keys[i] = key;
     int32_t a[D], b[D];
     uint32_t R;
     eunpack<D>(L, key, a, &R);
 #pragma unroll
     for (int j = 0; j < D; ++j) b[j] = a[j] + (int32_t)((R >> j) & 1u);
-    int64_t ha = ht_find(vt_keys, vt_mask, vpack<D>(L, a));
-    int64_t hb = ht_find(vt_keys, vt_mask, vpack<D>(L, b));
-    double fa = ha >= 0 ? vt_vals[ha] : NAN;
-    double fb = hb >= 0 ? vt_vals[hb] : NAN;
-    double xa[D], xb[D];
-    lat_coords<D>(L, a, xa);
-    lat_coords<D>(L, b, xb);
-    double t = fa / (fa - fb);
+    const uint64_t sa = o.slots & 0xffffffffull, sb = o.slots >> 32;
+    double p[D];
+    const bool ok = edge_point<D>(L, a, b, vt[sa].f, vt[sb].f, cert && !REDO, cert ? vb[sa] : -1.0f,
+                                  cert ? vb[sb] : -1.0f, B64, p);
 #pragma unroll
-    for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = fma(t, xb[j] - xa[j], xa[j]);
+    for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = p[j];
+    if (!ok) need_fp64(i, sa, sb, vb, redo, fb, ctr);
   }
 }
 
-__global__ void vt_rehash_kernel(const uint64_t *ok, const double *ov, uint64_t ocap, uint64_t *nk, double *nv,
+__global__ void vt_rehash_kernel(const VEnt *old, const float *ovb, uint64_t ocap, VEnt *nt, float *nvb,
                                  uint64_t nmask, Counters *ctr) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ocap; i += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t k = ok[i];
-    if (k == IP_EMPTY_KEY) continue;
+    const VEnt e = old[i];
+    if (e.key == IP_EMPTY_KEY) continue;
     uint64_t slot;
-    int r = ht_insert(nk, nmask, k, &slot);
-    if (r >= 0)
-      nv[slot] = ov[i];
-    else
+    if (vt_insert(nt, nmask, e.key, &slot) >= 0) {
+      nt[slot].f = e.f;
+      nt[slot].m[0] = e.m[0];
+      nt[slot].m[1] = e.m[1];
+      if (nvb) nvb[slot] = ovb[i];
+    } else {
       atomicOr(&ctr->vt_fail, 1u);
+    }
   }
 }
 
-__global__ void vt_scan_pending_kernel(const uint64_t *keys, const double *vals, uint64_t cap, uint32_t *list,
-                                       Counters *ctr) {
+__global__ void vt_scan_pending_kernel(const VEnt *vt, uint64_t cap, uint32_t *list, Counters *ctr) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
-    if (keys[i] == IP_EMPTY_KEY) continue;
-    uint64_t bits = __double_as_longlong(vals[i]);
-    if (bits == IP_UNEVAL_BITS) {
+    if (vt[i].key == IP_EMPTY_KEY) continue;
+    if ((uint64_t)__double_as_longlong(vt[i].f) == IP_UNEVAL_BITS) {
       unsigned long long idx = atomicAdd(&ctr->n_eval, 1ull);
       list[idx] = (uint32_t)i;
     }
   }
 }
 
-__global__ void et_rebuild_kernel(const uint64_t *out, uint64_t n, uint64_t *et, uint64_t mask, Counters *ctr) {
+// After VT moved, point the traced edges at the new slots of their ends.
+template <int D>
+__global__ void remap_slots_kernel(LatDev L, OutRec *out, uint64_t n, const VEnt *vt, uint64_t vt_mask,
+                                   Counters *ctr) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    int32_t a[D], b[D];
+    uint32_t R;
+    eunpack<D>(L, out[i].key, a, &R);
+#pragma unroll
+    for (int j = 0; j < D; ++j) b[j] = a[j] + (int32_t)((R >> j) & 1u);
+    const int64_t sa = vt_find(vt, vt_mask, vpack<D>(L, a));
+    const int64_t sb = vt_find(vt, vt_mask, vpack<D>(L, b));
+    if (sa < 0 || sb < 0) atomicOr(&ctr->vt_fail, 2u);
+    out[i].slots = (uint64_t)(sa < 0 ? 0 : sa) | ((uint64_t)(sb < 0 ? 0 : sb) << 32);
+  }
+}
+
+__global__ void et_rebuild_keys_kernel(const uint64_t *keys, uint64_t n, uint64_t *et, uint64_t mask, Counters *ctr) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t slot;
-    if (ht_insert(et, mask, out[i] & ~IP_SIGN_BIT, &slot) < 0) atomicOr(&ctr->et_fail, 1u);
+    if (ht_insert(et, mask, keys[i], &slot) < 0) atomicOr(&ctr->et_fail, 1u);
   }
 }
 
@@ -329,22 +418,6 @@ uint64_t pow2_at_least(uint64_t x) {
 // ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
-struct Run {
-  ip_ctx *ctx;
-  const ip_problem *p;
-  LatDev L;
-  uint64_t *vt_keys = nullptr;
-  double *vt_vals = nullptr;
-  uint64_t vt_cap = 0;
-  uint64_t *et_keys = nullptr;
-  uint64_t et_cap = 0;
-  uint32_t *eval = nullptr;
-  uint64_t eval_cap = 0;
-  uint64_t *out = nullptr;
-  uint64_t out_cap = 0;
-  int regrows = 0;
-};
-
 // Accumulates the stream time between two event records (read after the
 // next synchronisation of the stream).
 struct Timer {
@@ -381,6 +454,24 @@ struct Timer {
   }
 };
 
+struct Run {
+  ip_ctx *ctx;
+  const ip_problem *p;
+  LatDev L;
+  VEnt *vt = nullptr;
+  uint64_t vt_cap = 0;
+  uint32_t *eval = nullptr;
+  OutRec *out = nullptr;
+  uint64_t out_cap = 0;
+  uint32_t *cslot = nullptr;
+  int regrows = 0;
+  bool cert = false;      // FP32 certified evaluation (else canonical FP64)
+  float *vb = nullptr;    // per-slot bound of the stored f (cert only)
+  uint32_t *fb = nullptr; // FP64 fallback list
+  uint64_t fb_cap = 0;
+  int64_t n_fallback = 0;
+};
+
 int read_ctr(ip_ctx *ctx) {
   IP_TRY_HIP(ctx, hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream));
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -400,6 +491,13 @@ int fill(ip_ctx *ctx, void *p, uint64_t n, uint64_t v) {
   return IP_OK;
 }
 
+int fill_vt(ip_ctx *ctx, VEnt *p, uint64_t n) {
+  if (n == 0) return IP_OK;
+  hipLaunchKernelGGL(fill_vent_kernel, dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, p, n);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
+}
+
 int alloc(ip_ctx *ctx, void **p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);
   if (e != hipSuccess) {
@@ -413,72 +511,67 @@ int alloc(ip_ctx *ctx, void **p, size_t bytes) {
 // Vertex table of capacity cap (power of two), reusing the context buffers.
 int vt_init(Run &s, uint64_t cap) {
   ip_ctx *ctx = s.ctx;
-  IP_TRY(ip_ensure(ctx, ctx->vt_keys, cap * 8));
-  IP_TRY(ip_ensure(ctx, ctx->vt_vals, cap * 8));
+  IP_TRY(ip_ensure(ctx, ctx->vt_keys, cap * sizeof(VEnt)));
   IP_TRY(ip_ensure(ctx, ctx->eval_list, cap * 4));
-  s.vt_keys = (uint64_t *)ctx->vt_keys.p;
-  s.vt_vals = (double *)ctx->vt_vals.p;
+  s.vt = (VEnt *)ctx->vt_keys.p;
   s.eval = (uint32_t *)ctx->eval_list.p;
   s.vt_cap = cap;
-  s.eval_cap = cap;
-  IP_TRY(fill(ctx, s.vt_keys, cap, IP_EMPTY_KEY));
-  IP_TRY(fill(ctx, s.vt_vals, cap, IP_UNEVAL_BITS));
+  IP_TRY(fill_vt(ctx, s.vt, cap));
+  if (s.cert) {
+    IP_TRY(ip_ensure(ctx, ctx->vt_vals, cap * 4));
+    IP_TRY(ip_ensure(ctx, ctx->fb_list, cap * 4));
+    s.vb = (float *)ctx->vt_vals.p;
+    s.fb = (uint32_t *)ctx->fb_list.p;
+    s.fb_cap = ctx->fb_list.bytes / 4;
+  }
   return IP_OK;
 }
 
-int et_init(Run &s, uint64_t cap) {
+template <int D>
+int remap_out(Run &s, uint64_t n_out) {
+  if (n_out == 0) return IP_OK;
   ip_ctx *ctx = s.ctx;
-  IP_TRY(ip_ensure(ctx, ctx->et_keys, cap * 8));
-  s.et_keys = (uint64_t *)ctx->et_keys.p;
-  s.et_cap = cap;
-  IP_TRY(fill(ctx, s.et_keys, cap, IP_EMPTY_KEY));
+  hipLaunchKernelGGL((remap_slots_kernel<D>), dim3(grid_for(n_out)), dim3(kBlock), 0, ctx->stream, s.L, s.out, n_out,
+                     s.vt, s.vt_cap - 1, ctx->ctr_dev);
+  IP_TRY_HIP(ctx, hipGetLastError());
   return IP_OK;
 }
 
-// Grow VT to new_cap: rehash into fresh buffers and rebuild the pending list.
-int vt_grow(Run &s, uint64_t new_cap) {
+// Grow VT to new_cap: rehash into a fresh table, re-point the first n_out
+// traced edges, rebuild the pending-evaluation list.
+template <int D>
+int vt_grow(Run &s, uint64_t new_cap, uint64_t n_out) {
   ip_ctx *ctx = s.ctx;
-  void *nk = nullptr, *nv = nullptr, *nl = nullptr;
-  IP_TRY(alloc(ctx, &nk, new_cap * 8));
-  IP_TRY(alloc(ctx, &nv, new_cap * 8));
+  if (new_cap > (1ull << 32)) return ip_fail(ctx, IP_ENOMEM, "vertex table above 2^32 entries");
+  void *nt = nullptr, *nl = nullptr, *nvb = nullptr;
+  IP_TRY(alloc(ctx, &nt, new_cap * sizeof(VEnt)));
   IP_TRY(alloc(ctx, &nl, new_cap * 4));
-  IP_TRY(fill(ctx, nk, new_cap, IP_EMPTY_KEY));
-  IP_TRY(fill(ctx, nv, new_cap, IP_UNEVAL_BITS));
-  hipLaunchKernelGGL(vt_rehash_kernel, dim3(grid_for(s.vt_cap)), dim3(kBlock), 0, ctx->stream, s.vt_keys,
-                     s.vt_vals, s.vt_cap, (uint64_t *)nk, (double *)nv, new_cap - 1, ctx->ctr_dev);
+  if (s.cert) IP_TRY(alloc(ctx, &nvb, new_cap * 4));
+  IP_TRY(fill_vt(ctx, (VEnt *)nt, new_cap));
+  hipLaunchKernelGGL(vt_rehash_kernel, dim3(grid_for(s.vt_cap)), dim3(kBlock), 0, ctx->stream, s.vt,
+                     (const float *)s.vb, s.vt_cap, (VEnt *)nt, (float *)nvb, new_cap - 1, ctx->ctr_dev);
   IP_TRY_HIP(ctx, hipGetLastError());
   IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
   hipLaunchKernelGGL(vt_scan_pending_kernel, dim3(grid_for(new_cap)), dim3(kBlock), 0, ctx->stream,
-                     (const uint64_t *)nk, (const double *)nv, new_cap, (uint32_t *)nl, ctx->ctr_dev);
+                     (const VEnt *)nt, new_cap, (uint32_t *)nl, ctx->ctr_dev);
   IP_TRY_HIP(ctx, hipGetLastError());
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
   (void)hipFree(ctx->vt_keys.p);
-  (void)hipFree(ctx->vt_vals.p);
   (void)hipFree(ctx->eval_list.p);
-  ctx->vt_keys = {nk, new_cap * 8};
-  ctx->vt_vals = {nv, new_cap * 8};
+  ctx->vt_keys = {nt, new_cap * sizeof(VEnt)};
   ctx->eval_list = {nl, new_cap * 4};
-  s.vt_keys = (uint64_t *)nk;
-  s.vt_vals = (double *)nv;
+  s.vt = (VEnt *)nt;
   s.eval = (uint32_t *)nl;
-  s.vt_cap = s.eval_cap = new_cap;
-  ++s.regrows;
-  return IP_OK;
-}
-
-int et_grow(Run &s, uint64_t new_cap, uint64_t n_out) {
-  ip_ctx *ctx = s.ctx;
-  void *nk = nullptr;
-  IP_TRY(alloc(ctx, &nk, new_cap * 8));
-  IP_TRY(fill(ctx, nk, new_cap, IP_EMPTY_KEY));
-  hipLaunchKernelGGL(et_rebuild_kernel, dim3(grid_for(n_out)), dim3(kBlock), 0, ctx->stream, s.out, n_out,
-                     (uint64_t *)nk, new_cap - 1, ctx->ctr_dev);
-  IP_TRY_HIP(ctx, hipGetLastError());
-  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  (void)hipFree(ctx->et_keys.p);
-  ctx->et_keys = {nk, new_cap * 8};
-  s.et_keys = (uint64_t *)nk;
-  s.et_cap = new_cap;
+  s.vt_cap = new_cap;
+  if (s.cert) {
+    (void)hipFree(ctx->vt_vals.p);
+    ctx->vt_vals = {nvb, new_cap * 4};
+    s.vb = (float *)nvb;
+    IP_TRY(ip_ensure(ctx, ctx->fb_list, new_cap * 4));
+    s.fb = (uint32_t *)ctx->fb_list.p;
+    s.fb_cap = ctx->fb_list.bytes / 4;
+  }
+  IP_TRY(remap_out<D>(s, n_out));
   ++s.regrows;
   return IP_OK;
 }
@@ -488,37 +581,43 @@ int out_reserve(Run &s, uint64_t need, uint64_t n_used) {
   ip_ctx *ctx = s.ctx;
   uint64_t cap = std::max<uint64_t>(need, s.out_cap * 2);
   void *nb = nullptr;
-  IP_TRY(alloc(ctx, &nb, cap * 8));
+  IP_TRY(alloc(ctx, &nb, cap * sizeof(OutRec)));
   if (n_used)
-    IP_TRY_HIP(ctx, hipMemcpyAsync(nb, s.out, n_used * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    IP_TRY_HIP(ctx, hipMemcpyAsync(nb, s.out, n_used * sizeof(OutRec), hipMemcpyDeviceToDevice, ctx->stream));
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (s.out) (void)hipFree(s.out);
-  s.out = (uint64_t *)nb;
+  s.out = (OutRec *)nb;
   s.out_cap = cap;
   return IP_OK;
 }
 
-// Evaluate the pending vertices listed in s.eval[0 .. n).
-int eval_pending(Run &s, uint64_t n) {
-  return launch_feval64(s.ctx, s.p, s.L, s.eval, n, s.vt_keys, s.vt_vals);
-}
-
-template <int D>
-int level_pass1(Run &s, uint64_t lo, uint64_t hi) {
+int cslot_reserve(Run &s, uint64_t need) {
   ip_ctx *ctx = s.ctx;
-  unsigned grid = grid_for((hi - lo) * 4, 8192);
-  hipLaunchKernelGGL((expand_kernel<D, false>), dim3(grid), dim3(kBlock), 0, ctx->stream, s.L, s.out, lo, hi,
-                     s.vt_keys, s.vt_vals, s.vt_cap - 1, s.eval, s.et_keys, s.et_cap - 1, s.out, ctx->ctr_dev);
-  IP_TRY_HIP(ctx, hipGetLastError());
+  IP_TRY(ip_ensure(ctx, ctx->vt_aux, std::max<uint64_t>(need, 1024) * 4));
+  s.cslot = (uint32_t *)ctx->vt_aux.p;
   return IP_OK;
 }
 
-template <int D>
-int level_pass2(Run &s, uint64_t lo, uint64_t hi) {
+// f at the listed pending vertices: canonical FP64, or FP32 certified with
+// canonical FP64 for the vertices the bound cannot settle.
+int eval_pending(Run &s, uint64_t n) {
+  if (!s.cert) return launch_feval64(s.ctx, s.p, s.L, s.eval, n, s.vt);
+  ip_ctx *ctx = s.ctx;
+  if (n == 0) return IP_OK;
+  IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_fb));
+  IP_TRY(launch_feval32(ctx, s.p, s.L, s.eval, n, s.vt, s.vb, s.fb, &ctx->ctr_dev->n_fb));
+  IP_TRY(read_ctr(ctx));
+  const uint64_t nfb = ctx->ctr_host->n_fb;
+  s.n_fallback += (int64_t)nfb;
+  return launch_feval64(ctx, s.p, s.L, s.fb, nfb, s.vt);
+}
+
+template <int D, bool EDGES>
+int level_pass(Run &s, uint64_t lo, uint64_t hi) {
   ip_ctx *ctx = s.ctx;
   unsigned grid = grid_for((hi - lo) * 4, 8192);
-  hipLaunchKernelGGL((expand_kernel<D, true>), dim3(grid), dim3(kBlock), 0, ctx->stream, s.L, s.out, lo, hi,
-                     s.vt_keys, s.vt_vals, s.vt_cap - 1, s.eval, s.et_keys, s.et_cap - 1, s.out, ctx->ctr_dev);
+  hipLaunchKernelGGL((expand_kernel<D, EDGES>), dim3(grid), dim3(kBlock), 0, ctx->stream, s.L, s.out, lo, hi, s.vt,
+                     s.vt_cap - 1, s.cslot, s.eval, ctx->ctr_dev);
   IP_TRY_HIP(ctx, hipGetLastError());
   return IP_OK;
 }
@@ -527,6 +626,7 @@ int level_pass2(Run &s, uint64_t lo, uint64_t hi) {
 // s.out[0 .. *n_out) holds the traced edges and VT holds f at their ends.
 template <int D>
 int trace_direct(Run &s, ip_stats &st, uint64_t *n_out_ret) {
+  constexpr uint64_t MAXC = (1u << D) - 2;
   ip_ctx *ctx = s.ctx;
   const ip_problem *p = s.p;
   Counters *c = ctx->ctr_host;
@@ -534,54 +634,49 @@ int trace_direct(Run &s, ip_stats &st, uint64_t *n_out_ret) {
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
   // locate
   const unsigned sg = (unsigned)((p->n_seeds + 127) / 128);
-  for (;;) {
-    hipLaunchKernelGGL((seed_vertices_kernel<D>), dim3(sg), dim3(128), 0, ctx->stream, s.L, p->seeds_dev,
-                       p->n_seeds, s.vt_keys, s.vt_cap - 1, s.eval, ctx->ctr_dev);
+  for (int guard = 0;; ++guard) {
+    if (guard > 40) return ip_fail(ctx, IP_ENOMEM, "vertex table cannot grow");
+    hipLaunchKernelGGL((seed_vertices_kernel<D>), dim3(sg), dim3(128), 0, ctx->stream, s.L, p->seeds_dev, p->n_seeds,
+                       s.vt, s.vt_cap - 1, s.eval, ctx->ctr_dev);
     IP_TRY_HIP(ctx, hipGetLastError());
     IP_TRY(read_ctr(ctx));
     if (!c->vt_fail) break;
     IP_TRY(zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->vt_fail));
-    IP_TRY(vt_grow(s, s.vt_cap * 4));
+    IP_TRY(vt_grow<D>(s, s.vt_cap * 4, 0));
   }
   IP_TRY(tf.start(ctx, &st.ms_feval));
   IP_TRY(eval_pending(s, c->n_eval));
   IP_TRY(tf.stop(ctx));
   IP_TRY(out_reserve(s, (uint64_t)p->n_seeds * (D + 1) * D / 2 + 1024, 0));
-  for (;;) {
-    hipLaunchKernelGGL((seed_edges_kernel<D>), dim3(sg), dim3(128), 0, ctx->stream, s.L, p->seeds_dev,
-                       p->n_seeds, s.vt_keys, s.vt_vals, s.vt_cap - 1, s.et_keys, s.et_cap - 1, s.out,
-                       ctx->ctr_dev);
-    IP_TRY_HIP(ctx, hipGetLastError());
-    IP_TRY(read_ctr(ctx));
-    if (!c->et_fail) break;
-    IP_TRY(zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->et_fail));
-    IP_TRY(et_grow(s, s.et_cap * 4, c->n_out));
-  }
+  hipLaunchKernelGGL((seed_edges_kernel<D>), dim3(sg), dim3(128), 0, ctx->stream, s.L, p->seeds_dev, p->n_seeds, s.vt,
+                     s.vt_cap - 1, s.out, ctx->ctr_dev);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  IP_TRY(read_ctr(ctx));
   uint64_t lo = 0, hi = c->n_out;
   int levels = 0;
   uint64_t cof_total = 0;
   while (hi > lo) {
     ++levels;
-    // pass 1: new vertices
+    IP_TRY(cslot_reserve(s, ((hi - lo + 63) / 64) * 64 * MAXC));
+    // pass 1: third vertices
     IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
     IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
     IP_TRY(tx.start(ctx, &st.ms_expand));
-    IP_TRY(level_pass1<D>(s, lo, hi));
+    IP_TRY((level_pass<D, false>(s, lo, hi)));
     IP_TRY(tx.stop(ctx));
     IP_TRY(read_ctr(ctx));
     int guard = 0;
     while (c->vt_fail || c->vt_count * 2 > s.vt_cap) {
       if (++guard > 40) return ip_fail(ctx, IP_ENOMEM, "vertex table cannot grow");
-      const bool failed = c->vt_fail != 0;
       IP_TRY(zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->vt_fail));
-      IP_TRY(vt_grow(s, pow2_at_least(c->vt_count * 4)));
-      if (failed) {
-        // the replay finds the inserted vertices and lists the missing ones;
-        // the rebuilt pending list already holds everything unevaluated
-        IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
-        IP_TRY(level_pass1<D>(s, lo, hi));
-      }
+      IP_TRY(vt_grow<D>(s, pow2_at_least(c->vt_count * 4), hi));
+      // slots moved: replay pass 1 so CSL points into the new table; it
+      // finds the inserted vertices and lists the missing ones after the
+      // rebuilt pending list
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
+      IP_TRY((level_pass<D, false>(s, lo, hi)));
       IP_TRY(read_ctr(ctx));
+      if (c->vt_fail & 2u) return ip_fail(ctx, IP_EDEVICE, "internal: traced edge lost its vertex");
     }
     cof_total += c->n_cof;
     IP_TRY(tf.start(ctx, &st.ms_feval));
@@ -589,19 +684,10 @@ int trace_direct(Run &s, ip_stats &st, uint64_t *n_out_ret) {
     IP_TRY(tf.stop(ctx));
     // pass 2: new edges; OUT must hold one new edge per coface at most
     IP_TRY(out_reserve(s, hi + c->n_cof + 1, hi));
-    if ((c->n_out + c->n_cof) * 2 > s.et_cap) IP_TRY(et_grow(s, pow2_at_least((c->n_out + c->n_cof) * 2), hi));
     IP_TRY(tx.start(ctx, &st.ms_expand));
-    IP_TRY(level_pass2<D>(s, lo, hi));
+    IP_TRY((level_pass<D, true>(s, lo, hi)));
     IP_TRY(tx.stop(ctx));
     IP_TRY(read_ctr(ctx));
-    guard = 0;
-    while (c->et_fail) {
-      if (++guard > 40) return ip_fail(ctx, IP_ENOMEM, "edge table cannot grow");
-      IP_TRY(zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->et_fail));
-      IP_TRY(et_grow(s, s.et_cap * 4, c->n_out));
-      IP_TRY(level_pass2<D>(s, lo, hi));
-      IP_TRY(read_ctr(ctx));
-    }
     lo = hi;
     hi = c->n_out;
   }
@@ -679,10 +765,10 @@ __device__ __forceinline__ int n_cofacesn(uint32_t R) {
   return ifact(nR) * ifact(D + 1 - nR);
 }
 
-__global__ void count_ncof_kernel(const uint64_t *edges, uint64_t n, int D, int B, unsigned long long *total) {
+__global__ void count_ncof_kernel(const OutRec *edges, uint64_t n, int D, int B, unsigned long long *total) {
   unsigned long long acc = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t R = (uint32_t)((edges[i] & ~IP_SIGN_BIT) >> (D * B)) & ((1u << D) - 1u);
+    uint32_t R = (uint32_t)((edges[i].key & ~IP_SIGN_BIT) >> (D * B)) & ((1u << D) - 1u);
     int nR = __popc(R);
     acc += (unsigned long long)(ifact(nR) * ifact(D + 1 - nR));
   }
@@ -692,7 +778,7 @@ __global__ void count_ncof_kernel(const uint64_t *edges, uint64_t n, int D, int 
 // Sec. V-B: n-simplex cofaces of the coarse intersecting edges, hashed to
 // remove duplicates; the winners are listed in discovery order.
 template <int D>
-__global__ __launch_bounds__(kBlock) void sigma_kernel(LatDev Lc, int LB, const uint64_t *__restrict__ edges,
+__global__ __launch_bounds__(kBlock) void sigma_kernel(LatDev Lc, int LB, const OutRec *__restrict__ edges,
                                                        uint64_t n, uint64_t *sig_tab, uint64_t sig_mask,
                                                        uint64_t *sig_list, Counters *ctr) {
   const int lane = threadIdx.x & 63;
@@ -705,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void sigma_kernel(LatDev Lc, int LB, const 
     uint64_t e = 0;
     int cnt = 0;
     if (ei < n) {
-      e = edges[ei];
+      e = edges[ei].key;
       cnt = n_cofacesn<D>((uint32_t)((e & ~IP_SIGN_BIT) >> (D * Lc.B)) & ((1u << D) - 1u));
     }
     int incl = cnt;
@@ -811,7 +897,7 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void batch_vertices_kernel(LatDev Lf, LatDev Lc, int LB, int k,
                                                                 const uint64_t *__restrict__ sig, uint64_t nb,
                                                                 const uint64_t *__restrict__ tpts, int NP,
-                                                                uint64_t *vt_keys, uint64_t vt_mask,
+                                                                VEnt *vt, uint64_t vt_mask,
                                                                 uint32_t *eval_list, uint32_t *pslot,
                                                                 Counters *ctr) {
   const int lane = threadIdx.x & 63;
@@ -833,7 +919,7 @@ __global__ __launch_bounds__(kBlock) void batch_vertices_kernel(LatDev Lf, LatDe
       lat_coords<D>(Lf, y, x);
       uint32_t ps = 0xffffffffu;
       if (lat_in_box<D>(Lf, x)) {
-        int ins = ht_insert(vt_keys, vt_mask, vpack<D>(Lf, y), &slot);
+        int ins = vt_insert(vt, vt_mask, vpack<D>(Lf, y), &slot);
         if (ins >= 0) {
           ps = (uint32_t)slot;
           is_new = ins == 1;
@@ -863,7 +949,7 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(LatDev Lf, LatDev L
                                                              const uint64_t *__restrict__ tpts, int NP,
                                                              const uint32_t *__restrict__ tedge, int NE,
                                                              const uint32_t *__restrict__ pslot,
-                                                             const double *__restrict__ vt_vals, uint64_t *et_keys,
+                                                             const VEnt *__restrict__ vt, uint64_t *et_keys,
                                                              uint64_t et_mask, uint64_t *out, Counters *ctr) {
   const int lane = threadIdx.x & 63;
   const uint64_t total = nb * (uint64_t)NE;
@@ -883,7 +969,7 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(LatDev Lf, LatDev L
       const uint32_t Rl = te >> 24;
       const uint32_t sa = pslot[s * NP + a], sb = pslot[s * NP + b];
       if (sa != 0xffffffffu && sb != 0xffffffffu) {
-        const bool pa = !(vt_vals[sa] < 0.0), pb = !(vt_vals[sb] < 0.0);
+        const bool pa = !(vt[sa].f < 0.0), pb = !(vt[sb].f < 0.0);
         if (pa != pb) {
           ++hits;
           int32_t v[D], w[D], y[D];
@@ -914,34 +1000,29 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(LatDev Lf, LatDev L
   if (hits) atomicAdd(&ctr->n_cof, hits);
 }
 
-// Intersection points of the edges out[lo .. hi), endpoints looked up in the
-// batch vertex table.
-template <int D>
-__global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo, uint64_t hi, const uint64_t *vt_keys,
-                                    const double *vt_vals, uint64_t vt_mask, double *pts, int64_t ld) {
-  for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (uint64_t)gridDim.x * blockDim.x) {
+// Intersection points of the edges keys[lo .. hi), endpoints looked up in the
+// batch vertex table.  REDO: the output indices listed in redo[0 .. hi).
+template <int D, bool REDO>
+__global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo, uint64_t hi, const VEnt *vt,
+                                    uint64_t vt_mask, double *pts, int64_t ld, bool cert, const float *vb, double B64,
+                                    uint64_t *redo, uint32_t *fb, Counters *ctr) {
+  for (uint64_t q = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < hi; q += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = REDO ? redo[q] : q;
     int32_t a[D], b[D];
     uint32_t R;
     eunpack<D>(L, keys[i], a, &R);
 #pragma unroll
     for (int j = 0; j < D; ++j) b[j] = a[j] + (int32_t)((R >> j) & 1u);
-    int64_t ha = ht_find(vt_keys, vt_mask, vpack<D>(L, a));
-    int64_t hb = ht_find(vt_keys, vt_mask, vpack<D>(L, b));
-    double fa = ha >= 0 ? vt_vals[ha] : NAN;
-    double fb = hb >= 0 ? vt_vals[hb] : NAN;
-    double xa[D], xb[D];
-    lat_coords<D>(L, a, xa);
-    lat_coords<D>(L, b, xb);
-    double t = fa / (fa - fb);
+    const int64_t ha = vt_find(vt, vt_mask, vpack<D>(L, a));
+    const int64_t hb = vt_find(vt, vt_mask, vpack<D>(L, b));
+    const double fa = ha >= 0 ? vt[ha].f : NAN;
+    const double fb_ = hb >= 0 ? vt[hb].f : NAN;
+    double p[D];
+    const bool c = cert && !REDO && ha >= 0 && hb >= 0;
+    const bool ok = edge_point<D>(L, a, b, fa, fb_, c, c ? vb[ha] : -1.0f, c ? vb[hb] : -1.0f, B64, p);
 #pragma unroll
-    for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = fma(t, xb[j] - xa[j], xa[j]);
-  }
-}
-
-__global__ void et_rebuild_keys_kernel(const uint64_t *keys, uint64_t n, uint64_t *et, uint64_t mask, Counters *ctr) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t slot;
-    if (ht_insert(et, mask, keys[i], &slot) < 0) atomicOr(&ctr->et_fail, 1u);
+    for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = p[j];
+    if (!ok) need_fp64(i, (uint64_t)ha, (uint64_t)hb, vb, redo, fb, ctr);
   }
 }
 
@@ -998,8 +1079,46 @@ int lehmer_bits(int d) {
   return b < 1 ? 1 : b;
 }
 
+// Batch-mode output: the global set of fine edge keys (ET, open addressing)
+// and the list of keys in insertion order; the list's capacity equals the
+// set's, since every key in the set was appended exactly once.
+struct BatchOut {
+  uint64_t *et = nullptr;
+  uint64_t et_cap = 0;
+  uint64_t *keys = nullptr;
+  ~BatchOut() {
+    if (et) (void)hipFree(et);
+    if (keys) (void)hipFree(keys);
+  }
+  uint64_t *release() {
+    uint64_t *k = keys;
+    keys = nullptr;
+    return k;
+  }
+  // Grow both to cap (power of two), keeping the first n keys.
+  int reserve(ip_ctx *ctx, uint64_t cap, uint64_t n) {
+    void *ne = nullptr, *nk = nullptr;
+    IP_TRY(alloc(ctx, &ne, cap * 8));
+    IP_TRY(alloc(ctx, &nk, cap * 8));
+    IP_TRY(fill(ctx, ne, cap, IP_EMPTY_KEY));
+    if (n) {
+      IP_TRY_HIP(ctx, hipMemcpyAsync(nk, keys, n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+      hipLaunchKernelGGL(et_rebuild_keys_kernel, dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, (const uint64_t *)nk,
+                         n, (uint64_t *)ne, cap - 1, ctx->ctr_dev);
+      IP_TRY_HIP(ctx, hipGetLastError());
+    }
+    IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (et) (void)hipFree(et);
+    if (keys) (void)hipFree(keys);
+    et = (uint64_t *)ne;
+    keys = (uint64_t *)nk;
+    et_cap = cap;
+    return IP_OK;
+  }
+};
+
 template <int D>
-int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res) {
+int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip_cells *res) {
   ip_stats &st = res->st;
   const int k = p->k;
   const int LB = lehmer_bits(D);
@@ -1013,8 +1132,8 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res
   s.ctx = ctx;
   s.p = p;
   s.L = p->coarse;
+  s.cert = cert;
   IP_TRY(vt_init(s, 1ull << 16));
-  IP_TRY(et_init(s, 1ull << 16));
   uint64_t nc = 0;
   {
     int rc = trace_direct<D>(s, st, &nc);
@@ -1023,7 +1142,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res
       return rc;
     }
   }
-  uint64_t *coarse_edges = s.out;
+  OutRec *coarse_edges = s.out;
   s.out = nullptr;
   s.out_cap = 0;
   auto free_coarse = [&]() {
@@ -1083,19 +1202,24 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res
   f.p = p;
   f.L = p->fine;
   const uint64_t vcap = pow2_at_least(B * (uint64_t)NP * 2);
-  IP_TRY(ip_ensure(ctx, ctx->vt_keys, vcap * 8));
-  IP_TRY(ip_ensure(ctx, ctx->vt_vals, vcap * 8));
+  IP_TRY(ip_ensure(ctx, ctx->vt_keys, vcap * sizeof(VEnt)));
   IP_TRY(ip_ensure(ctx, ctx->eval_list, vcap * 4));
   IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * (uint64_t)NP * 4));
-  f.vt_keys = (uint64_t *)ctx->vt_keys.p;
-  f.vt_vals = (double *)ctx->vt_vals.p;
+  f.vt = (VEnt *)ctx->vt_keys.p;
   f.eval = (uint32_t *)ctx->eval_list.p;
-  f.vt_cap = f.eval_cap = vcap;
+  f.vt_cap = vcap;
+  f.cert = cert;
+  if (cert) {
+    IP_TRY(ip_ensure(ctx, ctx->vt_vals, vcap * 4));
+    IP_TRY(ip_ensure(ctx, ctx->fb_list, vcap * 4));
+    f.vb = (float *)ctx->vt_vals.p;
+    f.fb = (uint32_t *)ctx->fb_list.p;
+    f.fb_cap = vcap;
+  }
   uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
-  // global fine edge set + output keys (capacity tied to the set's)
-  uint64_t et_cap = 1ull << 20;
-  IP_TRY(et_init(f, et_cap));
-  IP_TRY(out_reserve(f, et_cap, 0));
+  // global fine edge set (ET) + output keys, whose capacity follows ET's
+  BatchOut g;
+  IP_TRY(g.reserve(ctx, 1ull << 20, 0));
   double *pts = nullptr;
   uint64_t pts_ld = 0;
   uint64_t n_out = 0;
@@ -1108,12 +1232,11 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res
     const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
     const uint64_t *sig = (const uint64_t *)sig_list + b0;
     ++batches;
-    IP_TRY(fill(ctx, f.vt_keys, vcap, IP_EMPTY_KEY));
-    IP_TRY(fill(ctx, f.vt_vals, vcap, IP_UNEVAL_BITS));
+    IP_TRY(fill_vt(ctx, f.vt, vcap));
     IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
     IP_TRY(tx.start(ctx, &st.ms_expand));
     hipLaunchKernelGGL((batch_vertices_kernel<D>), dim3(grid_for(nb * NP)), dim3(kBlock), 0, ctx->stream, p->fine,
-                       p->coarse, LB, k, sig, nb, (const uint64_t *)tpts, NP, f.vt_keys, vcap - 1, f.eval, pslot,
+                       p->coarse, LB, k, sig, nb, (const uint64_t *)tpts, NP, f.vt, vcap - 1, f.eval, pslot,
                        ctx->ctr_dev);
     IP_TRY_HIP(ctx, hipGetLastError());
     IP_TRY(tx.stop(ctx));
@@ -1133,31 +1256,17 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res
     uint64_t n_keys = n_out;
     int guard = 0;
     for (;;) {
-      if (n_keys * 2 > f.et_cap || c->et_fail) {
+      if (n_keys * 2 > g.et_cap || c->et_fail) {
         if (++guard > 40) return ip_fail(ctx, IP_ENOMEM, "edge table cannot grow");
-        const uint64_t ncap = pow2_at_least(std::max<uint64_t>(n_keys * 4, f.et_cap * 2));
-        IP_TRY(out_reserve(f, ncap, n_keys));
-        void *nk = nullptr;
-        IP_TRY(alloc(ctx, &nk, ncap * 8));
-        IP_TRY(fill(ctx, nk, ncap, IP_EMPTY_KEY));
         IP_TRY(zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->et_fail));
-        if (n_keys) {
-          hipLaunchKernelGGL(et_rebuild_keys_kernel, dim3(grid_for(n_keys)), dim3(kBlock), 0, ctx->stream, f.out,
-                             n_keys, (uint64_t *)nk, ncap - 1, ctx->ctr_dev);
-          IP_TRY_HIP(ctx, hipGetLastError());
-        }
-        IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        (void)hipFree(ctx->et_keys.p);
-        ctx->et_keys = {nk, ncap * 8};
-        f.et_keys = (uint64_t *)nk;
-        f.et_cap = ncap;
+        IP_TRY(g.reserve(ctx, pow2_at_least(std::max<uint64_t>(n_keys * 4, g.et_cap * 2)), n_keys));
         ++f.regrows;
       }
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
       IP_TRY(tx.start(ctx, &st.ms_expand));
       hipLaunchKernelGGL((batch_edges_kernel<D>), dim3(grid_for(nb * NE)), dim3(kBlock), 0, ctx->stream, p->fine,
                          p->coarse, LB, k, sig, nb, (const uint64_t *)tpts, NP, (const uint32_t *)tedge, NE, pslot,
-                         f.vt_vals, f.et_keys, f.et_cap - 1, f.out, ctx->ctr_dev);
+                         f.vt, g.et, g.et_cap - 1, g.keys, ctx->ctr_dev);
       IP_TRY_HIP(ctx, hipGetLastError());
       IP_TRY(tx.stop(ctx));
       IP_TRY(read_ctr(ctx));
@@ -1182,11 +1291,34 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res
       pts_ld = nld;
     }
     if (hi > lo) {
+      uint64_t *redo = nullptr;
+      if (cert) {
+        IP_TRY(ip_ensure(ctx, ctx->scratch, (hi - lo) * 8));
+        IP_TRY(ip_ensure(ctx, ctx->fb_list, std::max<uint64_t>(vcap, 2 * (hi - lo) + 64) * 4));
+        f.fb = (uint32_t *)ctx->fb_list.p;
+        redo = (uint64_t *)ctx->scratch.p;
+        IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
+        IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_fb));
+      }
       IP_TRY(tp.start(ctx, &st.ms_points));
-      hipLaunchKernelGGL((batch_points_kernel<D>), dim3(grid_for(hi - lo)), dim3(kBlock), 0, ctx->stream, p->fine, f.out,
-                         lo, hi, f.vt_keys, f.vt_vals, vcap - 1, pts, (int64_t)pts_ld);
+      hipLaunchKernelGGL((batch_points_kernel<D, false>), dim3(grid_for(hi - lo)), dim3(kBlock), 0, ctx->stream,
+                         p->fine, g.keys, lo, hi, f.vt, vcap - 1, pts, (int64_t)pts_ld, cert, (const float *)f.vb,
+                         p->poly.B64, redo, f.fb, ctx->ctr_dev);
       IP_TRY_HIP(ctx, hipGetLastError());
       IP_TRY(tp.stop(ctx));
+      if (cert) {
+        IP_TRY(read_ctr(ctx));
+        const uint64_t nredo = ctx->ctr_host->n_aux, nfb = ctx->ctr_host->n_fb;
+        if (nredo) {
+          IP_TRY(launch_feval64(ctx, p, p->fine, f.fb, nfb, f.vt));
+          IP_TRY(launch_set_vb(ctx, f.fb, nfb, f.vb, -1.0f));
+          hipLaunchKernelGGL((batch_points_kernel<D, true>), dim3(grid_for(nredo)), dim3(kBlock), 0, ctx->stream,
+                             p->fine, g.keys, (uint64_t)0, nredo, f.vt, vcap - 1, pts, (int64_t)pts_ld, true,
+                             (const float *)f.vb, p->poly.B64, redo, f.fb, ctx->ctr_dev);
+          IP_TRY_HIP(ctx, hipGetLastError());
+          f.n_fallback += (int64_t)nfb;
+        }
+      }
     }
     n_out = hi;
   }
@@ -1197,7 +1329,6 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res
   (void)hipFree(tedge);
   (void)hipFree(sig_list);
   if (rc != IP_OK) {
-    if (f.out) (void)hipFree(f.out);
     if (pts) (void)hipFree(pts);
     return rc;
   }
@@ -1206,60 +1337,94 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, ip_cells *res
   res->B = p->fine.B;
   for (int j = 0; j < 8; ++j) res->vmin[j] = p->fine.vmin[j];
   res->n = (int64_t)n_out;
-  res->keys = f.out;
+  res->keys = g.release();
   res->pts = pts;
   res->ld = (int64_t)(pts_ld ? pts_ld : 1);
   st.n_cells = (int64_t)n_out;
   st.n_batches = batches;
   st.regrows += s.regrows + f.regrows;
+  st.n_fallback = s.n_fallback + f.n_fallback;
+  return IP_OK;
+}
+
+// Points of OUT[0 .. n) into keys / pts; in FP32 mode the edges whose point
+// the bound cannot certify get FP64 values at their ends and are redone.
+template <int D>
+int direct_points(Run &s, uint64_t n, uint64_t *keys, double *pts, ip_stats &st) {
+  ip_ctx *ctx = s.ctx;
+  uint64_t *redo = nullptr;
+  if (s.cert) {
+    IP_TRY(ip_ensure(ctx, ctx->scratch, n * 8));
+    IP_TRY(ip_ensure(ctx, ctx->fb_list, (2 * n + 64) * 4));
+    s.fb = (uint32_t *)ctx->fb_list.p;
+    redo = (uint64_t *)ctx->scratch.p;
+    IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
+    IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_fb));
+  }
+  Timer tp;
+  IP_TRY(tp.start(ctx, &st.ms_points));
+  hipLaunchKernelGGL((points_kernel<D, false>), dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, s.L, s.out, n, s.vt,
+                     keys, pts, (int64_t)n, s.cert, (const float *)s.vb, s.p->poly.B64, redo, s.fb, ctx->ctr_dev);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  IP_TRY(tp.stop(ctx));
+  if (s.cert) {
+    IP_TRY(read_ctr(ctx));
+    const uint64_t nredo = ctx->ctr_host->n_aux, nfb = ctx->ctr_host->n_fb;
+    if (nredo) {
+      IP_TRY(launch_feval64(ctx, s.p, s.L, s.fb, nfb, s.vt));
+      IP_TRY(launch_set_vb(ctx, s.fb, nfb, s.vb, -1.0f));
+      hipLaunchKernelGGL((points_kernel<D, true>), dim3(grid_for(nredo)), dim3(kBlock), 0, ctx->stream, s.L, s.out,
+                         nredo, s.vt, keys, pts, (int64_t)n, true, (const float *)s.vb, s.p->poly.B64, redo, s.fb,
+                         ctx->ctr_dev);
+      IP_TRY_HIP(ctx, hipGetLastError());
+      s.n_fallback += (int64_t)nfb;
+    }
+  }
+  IP_TRY(tp.flush(ctx));
   return IP_OK;
 }
 
 template <int D>
 int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_cells *res) {
-  (void)budget;
-  (void)prec;
+  const bool cert = prec == IP_FP32_CERTIFY && p->poly.ok;
+  if (p->k != 1) return trace_batch<D>(ctx, p, budget, cert, res);
   Run s;
   s.ctx = ctx;
   s.p = p;
   s.L = p->fine;
-  if (p->k != 1) return trace_batch<D>(ctx, p, budget, res);
-  const uint64_t vt0 = std::max<uint64_t>(1ull << 20, ctx->vt_keys.bytes / 8);
-  const uint64_t et0 = std::max<uint64_t>(1ull << 20, ctx->et_keys.bytes / 8);
-  IP_TRY(vt_init(s, pow2_at_least(vt0) == vt0 ? vt0 : pow2_at_least(vt0) / 2));
-  IP_TRY(et_init(s, pow2_at_least(et0) == et0 ? et0 : pow2_at_least(et0) / 2));
+  s.cert = cert;
+  // start from the largest table the context already holds
+  uint64_t vt0 = 1ull << 20;
+  while (vt0 * 2 * sizeof(VEnt) <= ctx->vt_keys.bytes) vt0 *= 2;
+  IP_TRY(vt_init(s, vt0));
   ip_stats &st = res->st;
   uint64_t n = 0;
   int rc = trace_direct<D>(s, st, &n);
-  if (rc != IP_OK) {
-    if (s.out) (void)hipFree(s.out);
-    return rc;
-  }
-  // intersection points
+  uint64_t *keys = nullptr;
   double *pts = nullptr;
-  rc = alloc(ctx, (void **)&pts, sizeof(double) * (size_t)(n ? n : 1) * D);
-  if (rc != IP_OK) {
-    if (s.out) (void)hipFree(s.out);
-    return rc;
+  if (rc == IP_OK) rc = alloc(ctx, (void **)&keys, sizeof(uint64_t) * (size_t)(n ? n : 1));
+  if (rc == IP_OK) rc = alloc(ctx, (void **)&pts, sizeof(double) * (size_t)(n ? n : 1) * D);
+  if (rc == IP_OK && n) rc = direct_points<D>(s, n, keys, pts, st);
+  if (s.out) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(s.out);
   }
-  if (n) {
-    Timer tp;
-    IP_TRY(tp.start(ctx, &st.ms_points));
-    hipLaunchKernelGGL((points_kernel<D>), dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, s.L, s.out, n,
-                       s.vt_keys, s.vt_vals, s.vt_cap - 1, pts, (int64_t)n);
-    IP_TRY_HIP(ctx, hipGetLastError());
-    IP_TRY(tp.stop(ctx));
-    IP_TRY(tp.flush(ctx));
+  if (rc != IP_OK) {
+    if (keys) (void)hipFree(keys);
+    if (pts) (void)hipFree(pts);
+    return rc;
   }
   res->d = D;
   res->B = s.L.B;
   for (int j = 0; j < 8; ++j) res->vmin[j] = s.L.vmin[j];
   res->n = (int64_t)n;
-  res->keys = s.out;
+  res->keys = keys;
   res->pts = pts;
   res->ld = (int64_t)n;
   st.n_cells = (int64_t)n;
   st.regrows += s.regrows;
+  // FP32 requested but the degree has no FP32 form: every vertex was FP64
+  st.n_fallback = s.cert ? s.n_fallback : (prec == IP_FP32_CERTIFY ? st.n_vertices : 0);
   return IP_OK;
 }
 
@@ -1268,7 +1433,6 @@ int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_
 int ip_trace_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, uint32_t flags,
                   ip_cells *out) {
   (void)flags;
-  if (prec != IP_FP64) return ip_fail(ctx, IP_EINVAL, "precision mode not available");
   switch (p->d) {
     case 2: return trace_T<2>(ctx, p, budget, prec, out);
     case 3: return trace_T<3>(ctx, p, budget, prec, out);

@@ -342,3 +342,31 @@ def config_c3(seed=0, eps=0.002, k=4) -> Workload:
     w = cubic_case(6, 2000, 0.06, eps, seed=seed, k=k, scene=sc)
     w.name = f"d6_S2000_p3_lam0.06_k{k}"
     return w
+
+
+def config_c5(seed=0, coef0=1500.0, lam=0.08, eps=3e-4):
+    """Precision stress: d=5, 1000 SVs, degree 3, a large kernel offset coef0
+    whose constant part coef0^3 sum(alpha) is cancelled by the bias, so that
+    sum_i |alpha_i t_i^3| exceeds |f| by about 1e6 near the zero set."""
+    rng = np.random.default_rng(seed + 500)
+    d = 5
+    dom = box(d)
+    fm = random_manifold(d, 1000, 3, rng, dom, alpha="normal", coef0=coef0)
+    fm.bias = quantile_bias(fm, dom, rng, eps)
+    lat = make_lattice(d, lam, rng)
+    seeds = bisection_seeds(fm, dom, rng, 8)
+    return Workload(f"d5_S1000_p3_lam{lam}_stress", fm, lat, dom, seeds, 1)
+
+
+def dyadic_sphere_case(d=3, R2=1.0, step=0.125, half=1.6):
+    """||x||^2 - R2 on the lattice x = step * v (identity frame): with a
+    dyadic step, f is exactly 0.0 at every vertex on the sphere, which
+    exercises the sign rule s = !(f < 0) and the FP64 fallback."""
+    dom = box(d, half)
+    fm = sphere_manifold(d, math.sqrt(R2))
+    fm.bias = -R2
+    M = np.eye(d) * step
+    lat = Lattice(M=M, Minv=np.eye(d) / step, o=np.zeros(d), lam=step)
+    u = np.ones(d) / np.sqrt(d)
+    seeds = np.ascontiguousarray((math.sqrt(R2) * u)[None, :])
+    return Workload(f"dyadic_sphere_d{d}", fm, lat, dom, seeds)

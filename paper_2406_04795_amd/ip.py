@@ -61,6 +61,22 @@ class ip_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ip_request(C.Structure):
+    _fields_ = [("f", C.POINTER(ip_fparams)), ("sp", C.POINTER(ip_space)), ("seeds", _dp),
+                ("n_seeds", C.c_int64), ("coarse_k", C.c_int32), ("precision", C.c_int32),
+                ("scene", C.POINTER(ip_scene)), ("batch_budget", C.c_uint64),
+                ("mem_bytes", C.c_uint64), ("flags", C.c_uint32)]
+
+
+class ip_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("d", C.c_int32), ("stats", ip_stats),
+                ("n_cells", C.c_int64), ("n_free", C.c_int64), ("digest", C.c_uint64 * 2),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("free_pts", _dp), ("cells", C.c_void_p), ("error", C.c_char * 160)]
+
+
+IP_KEEP_CELLS = 1
+
 _P = C.POINTER
 _sig = {
     "ip_create": (C.c_int, [_P(_vp), C.c_int, _vp]),
@@ -79,6 +95,13 @@ _sig = {
     "ip_check_cells": (C.c_int, [_vp, _vp, _P(ip_scene), _P(C.c_int64)]),
     "ip_cells_download_check": (C.c_int, [_vp, _vp, C.POINTER(C.c_uint8), _dp]),
     "ip_feval": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, _vp, _vp]),
+    "ip_server_create": (C.c_int, [_P(_vp), C.c_int, C.c_uint64, C.c_int32]),
+    "ip_server_submit": (C.c_int, [_vp, _P(ip_request), _P(C.c_uint64)]),
+    "ip_server_poll": (C.c_int, [_vp, C.c_uint64, _P(_P(ip_result))]),
+    "ip_server_wait": (C.c_int, [_vp, C.c_uint64, _P(_P(ip_result))]),
+    "ip_result_free": (None, [_P(ip_result)]),
+    "ip_server_destroy": (None, [_vp]),
+    "ip_server_clock": (C.c_double, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -287,3 +310,66 @@ class Cells:
         if self.h:
             ip_cells_free(self.h)
             self.h = None
+
+
+# --------------------------------------------------------------------------
+# Serving loop
+# --------------------------------------------------------------------------
+def ip_server_create(device=0, pool_bytes=0, max_slots=4):
+    h = _vp()
+    _chk(None, _lib.ip_server_create(C.byref(h), device, pool_bytes, max_slots))
+    return h
+
+
+def ip_server_submit(server, wl, precision=IP_FP64, scene=None, budget=0, mem_bytes=0, flags=0,
+                     coarse_k=None):
+    """Queue workload wl (inputs.Workload); returns the request id."""
+    keep = []
+    f = wl.f
+    fp = ip_fparams(f.d, f.p, f.S, f.gamma, f.coef0, f.bias, _d(keep, f.sv), _d(keep, f.alpha))
+    sp = ip_space(f.d, _d(keep, wl.lat.M), _d(keep, wl.lat.Minv), _d(keep, wl.lat.o),
+                  _d(keep, wl.dom.lo), _d(keep, wl.dom.hi))
+    seeds = np.ascontiguousarray(wl.seeds, dtype=np.float64)
+    sc = C.pointer(_scene_struct(scene, keep)) if scene is not None else None
+    req = ip_request(C.pointer(fp), C.pointer(sp), seeds.ctypes.data_as(_dp), seeds.shape[0],
+                     wl.k if coarse_k is None else coarse_k, precision, sc, budget, mem_bytes, flags)
+    rid = C.c_uint64()
+    _chk(None, _lib.ip_server_submit(server, C.byref(req), C.byref(rid)))
+    return rid.value
+
+
+def _take_result(rp):
+    r = rp.contents
+    out = {"status": r.status, "d": r.d, "stats": r.stats.as_dict(), "n_cells": r.n_cells,
+           "n_free": r.n_free, "digest": (r.digest[0], r.digest[1]), "t_submit": r.t_submit,
+           "t_start": r.t_start, "t_done": r.t_done, "error": r.error.decode(errors="replace")}
+    if r.free_pts and r.n_free > 0:
+        out["free_pts"] = np.ctypeslib.as_array(r.free_pts, shape=(r.n_free * r.d,)).reshape(
+            r.n_free, r.d).copy()
+    if r.cells:
+        out["cells"] = ip_cells_download(None, _vp(r.cells), r.d)
+    _lib.ip_result_free(rp)
+    return out
+
+
+def ip_server_poll(server, rid):
+    rp = _P(ip_result)()
+    rc = _lib.ip_server_poll(server, rid, C.byref(rp))
+    if rc == IP_EAGAIN:
+        return None
+    _chk(None, rc)
+    return _take_result(rp)
+
+
+def ip_server_wait(server, rid):
+    rp = _P(ip_result)()
+    _chk(None, _lib.ip_server_wait(server, rid, C.byref(rp)))
+    return _take_result(rp)
+
+
+def ip_server_destroy(server):
+    _lib.ip_server_destroy(server)
+
+
+def ip_server_clock(server) -> float:
+    return _lib.ip_server_clock(server)

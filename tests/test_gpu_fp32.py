@@ -1,0 +1,105 @@
+"""GPU parity of the FP32-certified precision mode.
+
+The traced set must equal the FP64 oracle's exactly (every sign decision the
+FP32 bound cannot settle is taken by the canonical FP64 evaluation).  Points
+must lie within 1e-5 relative of the oracle's (1e-12 where both ends were
+re-evaluated in FP64, which the bound check requests whenever the FP32
+values could move the point by more than half the tolerance).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2406_04795_amd import inputs as I
+from test_gpu_trace import BATCH_CASES, CASES, trace
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ip():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    from paper_2406_04795_amd import ip as _ip
+    return _ip
+
+
+@pytest.fixture(scope="module")
+def ctx(ip):
+    c = ip.Context(0)
+    yield c
+    c.close()
+
+
+def _check_points(gpts, opts):
+    scale = np.maximum(np.abs(opts).max(1, keepdims=True), 1.0)
+    err = np.abs(gpts - opts) / scale
+    assert err.max() <= 1e-5, err.max()
+
+
+STRESS = {
+    "stress_d5": lambda: I.config_c5(lam=0.35, eps=3e-3),
+    "dyadic_sphere_d3": I.dyadic_sphere_case,
+}
+
+
+@pytest.mark.parametrize("name", list(CASES) + list(STRESS))
+def test_fp32_trace_equals_fp64_oracle(ip, ctx, name):
+    wl = (CASES.get(name) or STRESS[name])()
+    print(f"fp32 case {name}", flush=True)
+    ov, om = O.trace_direct(wl)
+    gv, gm, gpts, st = trace(ip, ctx, wl, precision=ip.IP_FP32_CERTIFY)
+    assert len(gv) == len(ov) and np.array_equal(gv, ov) and np.array_equal(gm, om)
+    opts, _ = O.points(wl, ov, om)
+    _check_points(gpts, opts)
+    print(f"  cells {st['n_cells']} vertices {st['n_vertices']} fp64 fallbacks {st['n_fallback']}")
+    if name in STRESS:
+        assert st["n_fallback"] > 0
+
+
+@pytest.mark.parametrize("name", ["sphere_d3_k3", "cubic_d4_k4", "cubic_d6_k2"])
+def test_fp32_batch_equals_fp64_oracle(ip, ctx, name):
+    make, k = BATCH_CASES[name]
+    wl = make()
+    wl.k = k
+    ov, om, ns = O.trace_batch(wl, k=k)
+    gv, gm, gpts, st = trace(ip, ctx, wl, precision=ip.IP_FP32_CERTIFY)
+    assert np.array_equal(gv, ov) and np.array_equal(gm, om)
+    opts, _ = O.points(wl, ov, om)
+    _check_points(gpts, opts)
+
+
+@pytest.mark.parametrize("which", ["random_d6", "stress_d5"])
+def test_fp32_values_within_bound(ip, ctx, which):
+    import torch
+    rng = np.random.default_rng(21)
+    if which == "random_d6":
+        d = 6
+        dom = I.box(d)
+        fm = I.random_manifold(d, 2000, 3, rng, dom)
+        fm.bias = -2.5
+        lat = I.make_lattice(d, 0.06, rng)
+    else:
+        w = I.config_c5(lam=0.35, eps=3e-3)
+        fm, lat, dom, d = w.f, w.lat, w.dom, 5
+    wl = I.Workload("fe", fm, lat, dom, np.zeros((1, d)))
+    n = 4 * 4096 + 13
+    # vertices inside the box (the bound is valid there)
+    Y = rng.uniform(dom.lo * 0.95, dom.hi * 0.95, size=(n, d))
+    V = np.floor((Y - lat.o) @ lat.Minv.T).astype(np.int32)
+    want = O.feval(fm, lat, V)
+    prob = ip.Problem(ctx, wl)
+    try:
+        vd = torch.from_numpy(V).cuda()
+        fd = torch.empty(n, dtype=torch.float64, device="cuda")
+        bd = torch.empty(n, dtype=torch.float64, device="cuda")
+        ip.ip_feval(ctx.h, prob.h, vd.data_ptr(), n, ip.IP_FP32_CERTIFY, fd.data_ptr(), bd.data_ptr())
+        torch.cuda.synchronize()
+        got, bnd = fd.cpu().numpy(), bd.cpu().numpy()
+    finally:
+        prob.close()
+    exact = bnd == 0
+    assert np.array_equal(got[exact].view(np.uint64), want[exact].view(np.uint64))
+    assert (np.abs(got - want) <= bnd).all()
+    assert np.array_equal(got < 0, want < 0)
+    assert exact.mean() < 0.5

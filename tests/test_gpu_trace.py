@@ -214,3 +214,60 @@ def test_argument_errors(ip, ctx):
         assert e.value.code == ip.IP_EINVAL
     finally:
         p.close()
+
+
+# --------------------------------------------------------------------------
+# Batch triangulation (Sec. V-B)
+# --------------------------------------------------------------------------
+BATCH_CASES = {
+    "sphere_d3_k3": (lambda: I.sphere_case(3, 1.0, 0.05), 3),
+    "c1_quadric_d3_k2": (I.config_c1, 2),
+    "cubic_d4_k4": (lambda: I.cubic_case(4, 200, 0.08, 0.01, seed=3, n_seeds=4), 4),
+    "cubic_d6_k4": (lambda: I.cubic_case(6, 2000, 0.4, 0.002, seed=2, n_seeds=4), 4),
+    "cubic_d6_k2": (lambda: I.cubic_case(6, 2000, 0.6, 0.002, seed=2, n_seeds=4), 2),
+    "sphere_d7_k2": (lambda: I.sphere_case(7, 1.0, 0.6), 2),
+}
+
+
+@pytest.mark.parametrize("name", list(BATCH_CASES))
+def test_batch_trace_matches_oracle(ip, ctx, name):
+    make, k = BATCH_CASES[name]
+    wl = make()
+    wl.k = k
+    print(f"batch case {name}", flush=True)
+    ov, om, ns = O.trace_batch(wl, k=k)
+    gv, gm, gpts, st = trace(ip, ctx, wl)
+    assert len(ov) > 0
+    assert st["n_sigma"] == ns
+    assert len(gv) == len(ov), (len(gv), len(ov))
+    assert np.array_equal(gv, ov) and np.array_equal(gm, om)
+    opts, _ = O.points(wl, ov, om)
+    assert np.array_equal(gpts.view(np.uint64), opts.view(np.uint64))
+
+
+def test_batch_budget_invariance(ip, ctx):
+    make, k = BATCH_CASES["cubic_d4_k4"]
+    wl = make()
+    wl.k = k
+    big = trace(ip, ctx, wl)
+    # a budget of a few coarse simplices forces many small batches
+    small = trace(ip, ctx, wl, budget=200 * 1024)
+    assert small[3]["n_batches"] > 10 * big[3]["n_batches"]
+    assert np.array_equal(big[0], small[0]) and np.array_equal(big[1], small[1])
+    assert np.array_equal(big[2].view(np.uint64), small[2].view(np.uint64))
+
+
+def test_batch_k1_equals_direct(ip, ctx):
+    wl = I.config_c1()
+    a = trace(ip, ctx, wl)
+    ov, om, _ = O.trace_batch(wl, k=1)
+    assert np.array_equal(a[0], ov) and np.array_equal(a[1], om)
+
+
+def test_batch_budget_too_small(ip, ctx):
+    make, k = BATCH_CASES["sphere_d3_k3"]
+    wl = make()
+    wl.k = k
+    with pytest.raises(ip.IPError) as e:
+        trace(ip, ctx, wl, budget=64)
+    assert e.value.code == ip.IP_ENOMEM
