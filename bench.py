@@ -188,6 +188,8 @@ def main():
                    "scale": wl.lat.lam, "coarse_k": wl.k, "cells": n_cells,
                    "free_cells": int(nf), "vertices": nv, "levels": stats[-1]["levels"],
                    "cofaces": int(cof)},
+        "precision": {"fp64_canonical_evals": int(stats[-1]["n_fallback"]),
+                      "settled_by_fp64_monomial": int(stats[-1]["n_settled64"])},
         "phases_ms": {"trace": float(np.mean([s["ms_total"] for s in stats])),
                       "feval": f_ms, "expand": x_ms,
                       "points": float(np.mean([s["ms_points"] for s in stats])),

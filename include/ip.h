@@ -109,7 +109,12 @@ typedef struct {
 typedef struct {
   int64_t n_cells;       /* traced edges (1-simplices) = intersection points */
   int64_t n_vertices;    /* unique lattice vertices whose f was evaluated */
-  int64_t n_fallback;    /* vertices re-evaluated in FP64 (IP_FP32_CERTIFY) */
+  int64_t n_fallback;    /* vertices whose sign the FP32 and FP64 monomial
+                            bounds left open: canonical FP64 evaluations
+                            (IP_FP32_CERTIFY), plus ends of edges whose point
+                            needed them */
+  int64_t n_settled64;   /* vertices the FP32 bound left open and the FP64
+                            monomial evaluation settled (IP_FP32_CERTIFY) */
   int64_t n_cofaces;     /* 2-simplex cofaces expanded by the search */
   int64_t n_sigma;       /* coarse n-simplices (batch triangulation) */
   int64_t n_batches;     /* batches of coarse n-simplices */

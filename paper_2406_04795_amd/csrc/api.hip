@@ -175,6 +175,7 @@ int build_poly(ip_ctx *ctx, ip_problem *p, const ip_fparams *f, const ip_space *
   }
   p->poly.B64 = u64 * (double)((P - 1) + P * (d + 2) + S + 3) * sg * 1.01 + 2.0 * u64 * std::fabs(f->bias);
   p->poly.K32 = u32 * (double)(2 * P + M + 4) * (1.0 + (double)(M + 4) * u32) * 1.001;
+  p->poly.K64 = u64 * (double)(2 * P + M + 4) * (1.0 + (double)(M + 4) * u64) * 1.001;
   p->poly.E0 = E0 * (1.0 + 1e-9);
   p->poly.M = M;
   p->poly.p = P;
@@ -182,10 +183,14 @@ int build_poly(ip_ctx *ctx, ip_problem *p, const ip_fparams *f, const ip_space *
   for (int m = 0; m < M; ++m) cf[m] = (float)c[m];
   for (int m = 0; m < M; ++m)
     if (!std::isfinite(cf[m])) return IP_OK;  // out of FP32 range: FP64 only
-  IP_TRY_HIP(ctx, hipMalloc((void **)&p->poly_dev, sizeof(float) * (size_t)M));
-  IP_TRY_HIP(ctx, hipMemcpyAsync(p->poly_dev, cf.data(), sizeof(float) * (size_t)M, hipMemcpyHostToDevice, ctx->stream));
+  // one buffer: M doubles, then M floats
+  IP_TRY_HIP(ctx, hipMalloc((void **)&p->poly_dev, 12 * (size_t)M));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(p->poly_dev, c.data(), 8 * (size_t)M, hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY_HIP(ctx, hipMemcpyAsync((char *)p->poly_dev + 8 * (size_t)M, cf.data(), 4 * (size_t)M,
+                                 hipMemcpyHostToDevice, ctx->stream));
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  p->poly.c = p->poly_dev;
+  p->poly.cd = (const double *)p->poly_dev;
+  p->poly.c = (const float *)((const char *)p->poly_dev + 8 * (size_t)M);
   p->poly.ok = 1;
   return IP_OK;
 }

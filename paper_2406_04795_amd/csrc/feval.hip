@@ -128,34 +128,20 @@ int dispatch64(ip_ctx *ctx, const FDev &F, const LatDev &L, const uint32_t *list
 // ---------------------------------------------------------------------------
 // FP32 monomial-basis evaluation with certification
 // ---------------------------------------------------------------------------
-// Depth-first walk over the monomials x_{j1} x_{j2} ... x_{jk}, j1 <= ... <=
-// jk, k = 1..K, in the order the host stored the coefficients: at index J
-// the monomial mono * x_J, then its extensions by x_{j >= J}, then J + 1.
-template <int D, int K, int J>
-struct Mono {
-  static __device__ __forceinline__ void run(const float *x, float mono, const float *__restrict__ C, int &ci,
-                                             float &acc, float &aabs) {
-    if constexpr (J < D) {
-      const float m = mono * x[J];
-      const float c = C[ci];
-      ++ci;
-      acc = fmaf(c, m, acc);
-      aabs = fmaf(fabsf(c), fabsf(m), aabs);
-      if constexpr (K > 1) Mono<D, K - 1, J>::run(x, m, C, ci, acc, aabs);
-      Mono<D, K, J + 1>::run(x, mono, C, ci, acc, aabs);
-    }
-  }
-};
-
+// Tiered certification.  Tier 1: f in FP32 in the monomial basis; settled
+// when |f32| > B32 + B64.  Tier 2 (only for the rest): f in FP64 in the
+// monomial basis; settled when |f64m| > B64m + B64.  Tier 3: the canonical
+// FP64 sum over the support vectors, for what is left.
 // MODE 0: vertex-table slots (f to vt[slot].f, bound to vb[slot]);
 // MODE 1: raw vertices (f to out[i], bound to bout[i]).
-// Vertices the bound cannot settle get vb = -1 (resp. bout = 0) and are
-// appended to fb (slot, resp. index) for canonical FP64 re-evaluation.
+// Tier-3 vertices get vb = -1 (resp. bout = 0) and are appended to fb (slot,
+// resp. index) for the canonical FP64 kernel.
 template <int D, int P, int MODE>
 __global__ __launch_bounds__(256) void feval32_kernel(PolyDev Q, LatDev L, const uint32_t *__restrict__ list,
                                                       uint64_t n, VEnt *vt, float *vb,
                                                       const int32_t *__restrict__ vraw, double *out, double *bout,
-                                                      uint32_t *fb, unsigned long long *fb_ctr) {
+                                                      uint32_t *fb, unsigned long long *fb_ctr,
+                                                      unsigned long long *c64_ctr) {
   constexpr int kStage = 128;
   __shared__ uint32_t st[4][kStage];
   const int wib = threadIdx.x >> 6;
@@ -164,6 +150,7 @@ __global__ __launch_bounds__(256) void feval32_kernel(PolyDev Q, LatDev L, const
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t start = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t rounds = (n + stride - 1) / stride;
+  unsigned long long n64 = 0;
   for (uint64_t it = 0; it < rounds; ++it) {
     const uint64_t i = start + it * stride;
     bool unsure = false;
@@ -185,21 +172,27 @@ __global__ __launch_bounds__(256) void feval32_kernel(PolyDev Q, LatDev L, const
       for (int j = 0; j < D; ++j) x[j] = (float)x64[j];
       float acc = Q.c[0], aabs = fabsf(Q.c[0]);
       int ci = 1;
-      Mono<D, P, 0>::run(x, 1.0f, Q.c, ci, acc, aabs);
-      const double b32 = Q.K32 * (double)aabs + Q.E0;
-      const double f32 = (double)acc;
-      unsure = !(fabs(f32) > b32 + Q.B64);
+      MonoWalk<float, D, P, 0>::run(x, 1.0f, Q.c, ci, acc, aabs);
+      double bnd = Q.K32 * (double)aabs + Q.E0;
+      double fv = (double)acc;
+      unsure = !(fabs(fv) > bnd + Q.B64);
+      if (unsure) {
+        fv = poly64<D, P>(Q, x64, &bnd);
+        unsure = !(fabs(fv) > bnd + Q.B64);
+        if (!unsure) ++n64;
+      }
       if (MODE == 0) {
-        if (!unsure) vt[id].f = f32;
-        vb[id] = unsure ? -1.0f : (float)(b32 * (1.0 + 1e-6));
+        if (!unsure) vt[id].f = fv;
+        vb[id] = unsure ? -1.0f : (float)(bnd * (1.0 + 1e-6));
       } else {
-        out[i] = f32;
-        bout[i] = unsure ? 0.0 : b32 + Q.B64;
+        out[i] = fv;
+        bout[i] = unsure ? 0.0 : bnd + Q.B64;
       }
     }
     stage_put<kStage>(st[wib], sn, unsure, id, put, fb_ctr);
   }
   stage_flush(st[wib], sn, put, fb_ctr);
+  if (n64) atomicAdd(c64_ctr, n64);
 }
 
 __global__ void set_vb_kernel(const uint32_t *list, uint64_t n, float *vb, float v) {
@@ -209,13 +202,14 @@ __global__ void set_vb_kernel(const uint32_t *list, uint64_t n, float *vb, float
 
 template <int D, int MODE>
 void launch32_p(hipStream_t st, const PolyDev &Q, const LatDev &L, const uint32_t *list, uint64_t n, VEnt *vt,
-                float *vb, const int32_t *vraw, double *out, double *bout, uint32_t *fb, unsigned long long *fb_ctr) {
+                float *vb, const int32_t *vraw, double *out, double *bout, uint32_t *fb, unsigned long long *fb_ctr,
+                unsigned long long *c64) {
   uint64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) return;
 #define IP_L32(PP)                                                                                               \
   hipLaunchKernelGGL((feval32_kernel<D, PP, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, Q, L, list, n, vt, vb, \
-                     vraw, out, bout, fb, fb_ctr)
+                     vraw, out, bout, fb, fb_ctr, c64)
   switch (Q.p) {
     case 1: IP_L32(1); break;
     case 2: IP_L32(2); break;
@@ -229,15 +223,16 @@ void launch32_p(hipStream_t st, const PolyDev &Q, const LatDev &L, const uint32_
 template <int MODE>
 int dispatch32(ip_ctx *ctx, const PolyDev &Q, const LatDev &L, const uint32_t *list, uint64_t n, VEnt *vt, float *vb,
                const int32_t *vraw, double *out, double *bout, uint32_t *fb, unsigned long long *fb_ctr) {
+  unsigned long long *c64 = &ctx->ctr_dev->n_cert64;
   if (n == 0) return IP_OK;
   hipStream_t st = ctx->stream;
   switch (L.d) {
-    case 2: launch32_p<2, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
-    case 3: launch32_p<3, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
-    case 4: launch32_p<4, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
-    case 5: launch32_p<5, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
-    case 6: launch32_p<6, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
-    case 7: launch32_p<7, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr); break;
+    case 2: launch32_p<2, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr, c64); break;
+    case 3: launch32_p<3, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr, c64); break;
+    case 4: launch32_p<4, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr, c64); break;
+    case 5: launch32_p<5, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr, c64); break;
+    case 6: launch32_p<6, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr, c64); break;
+    case 7: launch32_p<7, MODE>(st, Q, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr, c64); break;
     default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
   }
   IP_TRY_HIP(ctx, hipGetLastError());

@@ -49,13 +49,16 @@ struct FDev {
 // For every vertex in the domain: |f32 - F| <= K32 * S_abs + E0, with S_abs
 // the FP32 sum of |c_m| |x^m| computed beside f32, and |f64 - F| <= B64 for
 // the canonical FP64 value, F the exact value at the canonical coordinates.
+// The same coefficients in FP64 (cd) give a second, FP64 evaluation in the
+// monomial basis with |f64m - F| <= K64 * S_abs64 + E0.
 struct PolyDev {
   const float *c;
+  const double *cd;
   int32_t M;
   int32_t p;
   int32_t ok;   // 0: degree above 4, every vertex is evaluated in FP64
   int32_t pad;
-  double K32, E0, B64;
+  double K32, K64, E0, B64;
 };
 
 struct Counters {
@@ -66,6 +69,7 @@ struct Counters {
   unsigned long long n_fb;       // FP64 fallback list length
   unsigned long long n_fb_total; // fallbacks over the whole call
   unsigned long long n_aux;      // general-purpose append counter
+  unsigned long long n_cert64;   // vertices settled by the FP64 monomial tier
   unsigned int vt_fail;          // vertex-table insert found the table full
   unsigned int et_fail;          // edge-table insert found the table full
 };
@@ -272,6 +276,46 @@ __device__ __forceinline__ void stage_put(T *st, int &n, bool pred, const T &ite
   n += nb;
 }
 
+// Depth-first walk over the monomials x_{j1} x_{j2} ... x_{jk}, j1 <= ... <=
+// jk, k = 1..K, in the order the host stored the coefficients: at index J the
+// monomial mono * x_J, then its extensions by x_{j >= J}, then J + 1.
+// Accumulates sum c_m x^m into acc and sum |c_m| |x^m| into aabs.
+template <typename T, int D, int K, int J>
+struct MonoWalk {
+  static __device__ __forceinline__ void run(const T *x, T mono, const T *__restrict__ C, int &ci, T &acc,
+                                             T &aabs) {
+    if constexpr (J < D) {
+      const T m = mono * x[J];
+      const T c = C[ci];
+      ++ci;
+      acc = fma(c, m, acc);
+      aabs = fma(fabs(c), fabs(m), aabs);
+      if constexpr (K > 1) MonoWalk<T, D, K - 1, J>::run(x, m, C, ci, acc, aabs);
+      MonoWalk<T, D, K, J + 1>::run(x, mono, C, ci, acc, aabs);
+    }
+  }
+};
+
+// f in the monomial basis, FP64, with the rigorous bound on |f - F|.
+template <int D, int P>
+__device__ __forceinline__ double poly64(const PolyDev &Q, const double *x, double *bound) {
+  double acc = Q.cd[0], aabs = fabs(Q.cd[0]);
+  int ci = 1;
+  MonoWalk<double, D, P, 0>::run(x, 1.0, Q.cd, ci, acc, aabs);
+  *bound = Q.K64 * aabs + Q.E0;
+  return acc;
+}
+
+template <int D>
+__device__ __forceinline__ double poly64_any(const PolyDev &Q, const double *x, double *bound) {
+  switch (Q.p) {
+    case 1: return poly64<D, 1>(Q, x, bound);
+    case 2: return poly64<D, 2>(Q, x, bound);
+    case 3: return poly64<D, 3>(Q, x, bound);
+    default: return poly64<D, 4>(Q, x, bound);
+  }
+}
+
 // Deposit the low bits of src into the set positions of mask (ascending).
 __device__ __forceinline__ uint32_t pdep32(uint32_t src, uint32_t mask) {
   uint32_t out = 0;
@@ -370,7 +414,7 @@ struct ip_problem {
   double *seeds_dev = nullptr;
   int64_t n_seeds = 0;
   PolyDev poly = {};
-  float *poly_dev = nullptr;
+  void *poly_dev = nullptr;
 };
 
 struct ip_cells {

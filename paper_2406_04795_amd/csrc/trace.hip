@@ -287,25 +287,32 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LatDev L, OutRec *out, u
 
 // Intersection point of edge (a, b), a the smaller endpoint (Sec. V-B):
 // t = f_a / (f_a - f_b), p = x_a + t (x_b - x_a).  With certification on
-// (FP32 mode), ba / bb bound |f - F| at the ends (-1: canonical FP64 value,
-// bound B64), and the call returns false when the a-priori bound on the
+// (FP32 mode) the stored f only settled the sign: an end whose stored value
+// is not the canonical FP64 one (bound ba / bb >= 0) gets f from the FP64
+// monomial-basis evaluation with its bound, a canonical end keeps its value
+// (bound B64).  The call returns false when the a-priori bound on the
 // distance to the point computed from canonical FP64 values exceeds half the
-// FP32 tolerance, 1e-5 relative (|dt| <= (da + db + 2 B64) / (|fa| + |fb| -
-// da - db - 2 B64) since f_a and f_b have opposite signs).
+// FP32 tolerance, 1e-5 relative; since f_a and f_b have opposite signs,
+// |dt| <= (da + db + 2 B64) / (|fa| + |fb| - da - db - 2 B64).
 template <int D>
-__device__ __forceinline__ bool edge_point(const LatDev &L, const int32_t *a, const int32_t *b, double fa, double fb,
-                                           bool cert, float ba, float bb, double B64, double *p) {
+__device__ __forceinline__ bool edge_point(const LatDev &L, const PolyDev &Q, const int32_t *a, const int32_t *b,
+                                           double fa, double fb, bool cert, float ba, float bb, double *p) {
   double xa[D], xb[D];
   lat_coords<D>(L, a, xa);
   lat_coords<D>(L, b, xb);
+  double da = Q.B64, db = Q.B64;
+  const bool exact = !cert || (ba < 0.0f && bb < 0.0f);
+  if (!exact) {
+    if (ba >= 0.0f) fa = poly64_any<D>(Q, xa, &da);
+    if (bb >= 0.0f) fb = poly64_any<D>(Q, xb, &db);
+  }
   const double t = fa / (fa - fb);
 #pragma unroll
   for (int j = 0; j < D; ++j) p[j] = fma(t, xb[j] - xa[j], xa[j]);
-  if (!cert || (ba < 0.0f && bb < 0.0f)) return true;
-  const double da = ba < 0.0f ? B64 : (double)ba, db = bb < 0.0f ? B64 : (double)bb;
-  const double num = da + db + 2.0 * B64;
+  if (exact) return true;
+  const double num = da + db + 2.0 * Q.B64;
   const double den = fabs(fa) + fabs(fb) - num;
-  if (!(den > 0.0)) return false;
+  if (!(den > 0.0) || (fa < 0.0) == (fb < 0.0)) return false;
   double dx = 0.0, pn = 1.0;
 #pragma unroll
   for (int j = 0; j < D; ++j) {
@@ -329,7 +336,7 @@ __device__ __forceinline__ void need_fp64(uint64_t i, uint64_t sa, uint64_t sb, 
 // REDO = true : the edges listed in redo, after their ends went to FP64.
 template <int D, bool REDO>
 __global__ void points_kernel(LatDev L, const OutRec *out, uint64_t n, const VEnt *vt, uint64_t *keys, double *pts,
-                              int64_t ld, bool cert, const float *vb, double B64, uint64_t *redo, uint32_t *fb,
+                              int64_t ld, bool cert, const float *vb, PolyDev Q, uint64_t *redo, uint32_t *fb,
                               Counters *ctr) {
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t i = REDO ? redo[q] : q;
@@ -343,8 +350,8 @@ __global__ void points_kernel(LatDev L, const OutRec *out, uint64_t n, const VEn
     for (int j = 0; j < D; ++j) b[j] = a[j] + (int32_t)((R >> j) & 1u);
     const uint64_t sa = o.slots & 0xffffffffull, sb = o.slots >> 32;
     double p[D];
-    const bool ok = edge_point<D>(L, a, b, vt[sa].f, vt[sb].f, cert && !REDO, cert ? vb[sa] : -1.0f,
-                                  cert ? vb[sb] : -1.0f, B64, p);
+    const bool ok = edge_point<D>(L, Q, a, b, vt[sa].f, vt[sb].f, cert && !REDO, cert ? vb[sa] : -1.0f,
+                                  cert ? vb[sb] : -1.0f, p);
 #pragma unroll
     for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = p[j];
     if (!ok) need_fp64(i, sa, sb, vb, redo, fb, ctr);
@@ -470,6 +477,7 @@ struct Run {
   uint32_t *fb = nullptr; // FP64 fallback list
   uint64_t fb_cap = 0;
   int64_t n_fallback = 0;
+  int64_t n_settled64 = 0;
 };
 
 int read_ctr(ip_ctx *ctx) {
@@ -605,10 +613,12 @@ int eval_pending(Run &s, uint64_t n) {
   ip_ctx *ctx = s.ctx;
   if (n == 0) return IP_OK;
   IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_fb));
+  IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cert64));
   IP_TRY(launch_feval32(ctx, s.p, s.L, s.eval, n, s.vt, s.vb, s.fb, &ctx->ctr_dev->n_fb));
   IP_TRY(read_ctr(ctx));
   const uint64_t nfb = ctx->ctr_host->n_fb;
   s.n_fallback += (int64_t)nfb;
+  s.n_settled64 += (int64_t)ctx->ctr_host->n_cert64;
   return launch_feval64(ctx, s.p, s.L, s.fb, nfb, s.vt);
 }
 
@@ -1004,7 +1014,7 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(LatDev Lf, LatDev L
 // batch vertex table.  REDO: the output indices listed in redo[0 .. hi).
 template <int D, bool REDO>
 __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo, uint64_t hi, const VEnt *vt,
-                                    uint64_t vt_mask, double *pts, int64_t ld, bool cert, const float *vb, double B64,
+                                    uint64_t vt_mask, double *pts, int64_t ld, bool cert, const float *vb, PolyDev Q,
                                     uint64_t *redo, uint32_t *fb, Counters *ctr) {
   for (uint64_t q = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < hi; q += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t i = REDO ? redo[q] : q;
@@ -1019,7 +1029,7 @@ __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo,
     const double fb_ = hb >= 0 ? vt[hb].f : NAN;
     double p[D];
     const bool c = cert && !REDO && ha >= 0 && hb >= 0;
-    const bool ok = edge_point<D>(L, a, b, fa, fb_, c, c ? vb[ha] : -1.0f, c ? vb[hb] : -1.0f, B64, p);
+    const bool ok = edge_point<D>(L, Q, a, b, fa, fb_, c, c ? vb[ha] : -1.0f, c ? vb[hb] : -1.0f, p);
 #pragma unroll
     for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = p[j];
     if (!ok) need_fp64(i, (uint64_t)ha, (uint64_t)hb, vb, redo, fb, ctr);
@@ -1303,7 +1313,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
       IP_TRY(tp.start(ctx, &st.ms_points));
       hipLaunchKernelGGL((batch_points_kernel<D, false>), dim3(grid_for(hi - lo)), dim3(kBlock), 0, ctx->stream,
                          p->fine, g.keys, lo, hi, f.vt, vcap - 1, pts, (int64_t)pts_ld, cert, (const float *)f.vb,
-                         p->poly.B64, redo, f.fb, ctx->ctr_dev);
+                         p->poly, redo, f.fb, ctx->ctr_dev);
       IP_TRY_HIP(ctx, hipGetLastError());
       IP_TRY(tp.stop(ctx));
       if (cert) {
@@ -1314,7 +1324,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
           IP_TRY(launch_set_vb(ctx, f.fb, nfb, f.vb, -1.0f));
           hipLaunchKernelGGL((batch_points_kernel<D, true>), dim3(grid_for(nredo)), dim3(kBlock), 0, ctx->stream,
                              p->fine, g.keys, (uint64_t)0, nredo, f.vt, vcap - 1, pts, (int64_t)pts_ld, true,
-                             (const float *)f.vb, p->poly.B64, redo, f.fb, ctx->ctr_dev);
+                             (const float *)f.vb, p->poly, redo, f.fb, ctx->ctr_dev);
           IP_TRY_HIP(ctx, hipGetLastError());
           f.n_fallback += (int64_t)nfb;
         }
@@ -1344,6 +1354,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   st.n_batches = batches;
   st.regrows += s.regrows + f.regrows;
   st.n_fallback = s.n_fallback + f.n_fallback;
+  st.n_settled64 = s.n_settled64 + f.n_settled64;
   return IP_OK;
 }
 
@@ -1364,7 +1375,7 @@ int direct_points(Run &s, uint64_t n, uint64_t *keys, double *pts, ip_stats &st)
   Timer tp;
   IP_TRY(tp.start(ctx, &st.ms_points));
   hipLaunchKernelGGL((points_kernel<D, false>), dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, s.L, s.out, n, s.vt,
-                     keys, pts, (int64_t)n, s.cert, (const float *)s.vb, s.p->poly.B64, redo, s.fb, ctx->ctr_dev);
+                     keys, pts, (int64_t)n, s.cert, (const float *)s.vb, s.p->poly, redo, s.fb, ctx->ctr_dev);
   IP_TRY_HIP(ctx, hipGetLastError());
   IP_TRY(tp.stop(ctx));
   if (s.cert) {
@@ -1374,7 +1385,7 @@ int direct_points(Run &s, uint64_t n, uint64_t *keys, double *pts, ip_stats &st)
       IP_TRY(launch_feval64(ctx, s.p, s.L, s.fb, nfb, s.vt));
       IP_TRY(launch_set_vb(ctx, s.fb, nfb, s.vb, -1.0f));
       hipLaunchKernelGGL((points_kernel<D, true>), dim3(grid_for(nredo)), dim3(kBlock), 0, ctx->stream, s.L, s.out,
-                         nredo, s.vt, keys, pts, (int64_t)n, true, (const float *)s.vb, s.p->poly.B64, redo, s.fb,
+                         nredo, s.vt, keys, pts, (int64_t)n, true, (const float *)s.vb, s.p->poly, redo, s.fb,
                          ctx->ctr_dev);
       IP_TRY_HIP(ctx, hipGetLastError());
       s.n_fallback += (int64_t)nfb;
@@ -1425,6 +1436,7 @@ int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_
   st.regrows += s.regrows;
   // FP32 requested but the degree has no FP32 form: every vertex was FP64
   st.n_fallback = s.cert ? s.n_fallback : (prec == IP_FP32_CERTIFY ? st.n_vertices : 0);
+  st.n_settled64 = s.n_settled64;
   return IP_OK;
 }
 

@@ -52,6 +52,7 @@ class ip_scene(C.Structure):
 
 class ip_stats(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_vertices", C.c_int64), ("n_fallback", C.c_int64),
+                ("n_settled64", C.c_int64),
                 ("n_cofaces", C.c_int64), ("n_sigma", C.c_int64), ("n_batches", C.c_int64),
                 ("n_template_edges", C.c_int64), ("levels", C.c_int32), ("regrows", C.c_int32),
                 ("ms_total", C.c_double), ("ms_feval", C.c_double), ("ms_expand", C.c_double),

@@ -52,8 +52,11 @@ def test_fp32_trace_equals_fp64_oracle(ip, ctx, name):
     assert len(gv) == len(ov) and np.array_equal(gv, ov) and np.array_equal(gm, om)
     opts, _ = O.points(wl, ov, om)
     _check_points(gpts, opts)
-    print(f"  cells {st['n_cells']} vertices {st['n_vertices']} fp64 fallbacks {st['n_fallback']}")
-    if name in STRESS:
+    print(f"  cells {st['n_cells']} vertices {st['n_vertices']} fp64-basis {st['n_settled64']} "
+          f"canonical fallbacks {st['n_fallback']}")
+    if name == "dyadic_sphere_d3":
+        # f is exactly 0.0 at some vertices: no bound can settle those signs,
+        # the canonical FP64 evaluation must (s = !(f < 0) gives +)
         assert st["n_fallback"] > 0
 
 
