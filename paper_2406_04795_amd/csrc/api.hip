@@ -21,20 +21,80 @@ int ip_hip(ip_ctx *ctx, hipError_t e, const char *what) {
   return ip_fail(ctx, e == hipErrorOutOfMemory ? IP_ENOMEM : IP_EDEVICE, buf);
 }
 
+int ip_dalloc(ip_ctx *ctx, void **p, size_t bytes) {
+  const size_t gran = 2ull << 20;
+  size_t want = ((bytes < 256 ? 256 : bytes) + gran - 1) / gran * gran;
+  {
+    std::lock_guard<std::mutex> lk(ctx->cache.mu);
+    auto it = ctx->cache.idle.lower_bound(want);
+    if (it != ctx->cache.idle.end() && it->first <= 2 * want) {
+      *p = it->second;
+      ctx->cache.idle_bytes -= it->first;
+      ctx->cache.idle.erase(it);
+      return IP_OK;
+    }
+  }
+  hipError_t e = hipMalloc(p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ip_cache_release(ctx);
+    e = hipMalloc(p, want);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return ip_fail(ctx, IP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  std::lock_guard<std::mutex> lk(ctx->cache.mu);
+  ctx->cache.size_of[*p] = want;
+  return IP_OK;
+}
+
+void ip_dfree(ip_ctx *ctx, void *p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(ctx->cache.mu);
+  auto it = ctx->cache.size_of.find(p);
+  if (it == ctx->cache.size_of.end()) return;  // not ours
+  const size_t sz = it->second;
+  if (ctx->cache.idle_bytes + sz > ctx->cache.limit) {
+    // keep the newest blocks: drop the largest idle ones first
+    while (!ctx->cache.idle.empty() && ctx->cache.idle_bytes + sz > ctx->cache.limit) {
+      auto last = std::prev(ctx->cache.idle.end());
+      (void)hipFree(last->second);
+      ctx->cache.size_of.erase(last->second);
+      ctx->cache.idle_bytes -= last->first;
+      ctx->cache.idle.erase(last);
+    }
+    if (sz > ctx->cache.limit) {
+      (void)hipFree(p);
+      ctx->cache.size_of.erase(it);
+      return;
+    }
+  }
+  ctx->cache.idle.emplace(sz, p);
+  ctx->cache.idle_bytes += sz;
+}
+
+void ip_cache_release(ip_ctx *ctx) {
+  std::lock_guard<std::mutex> lk(ctx->cache.mu);
+  (void)hipDeviceSynchronize();
+  for (auto &kv : ctx->cache.idle) {
+    (void)hipFree(kv.second);
+    ctx->cache.size_of.erase(kv.second);
+  }
+  ctx->cache.idle.clear();
+  ctx->cache.idle_bytes = 0;
+}
+
 int ip_ensure(ip_ctx *ctx, DevBuf &b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return IP_OK;
   if (b.p) {
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(b.p);
+    ip_dfree(ctx, b.p);
   }
   b.p = nullptr;
   b.bytes = 0;
-  hipError_t e = hipMalloc(&b.p, bytes < 256 ? 256 : bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    b.p = nullptr;
-    return ip_fail(ctx, IP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-  }
+  IP_TRY(ip_dalloc(ctx, &b.p, bytes));
   b.bytes = bytes;
   return IP_OK;
 }
@@ -219,6 +279,14 @@ int ip_create(ip_ctx **out, int device, void *stream) {
     return IP_EDEVICE;
   }
   memset(ctx->ctr_host, 0, sizeof(Counters));
+  {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      tot = 64ull << 30;
+    }
+    ctx->cache.limit = tot / 3;
+  }
   *out = ctx;
   return IP_OK;
 }
@@ -230,7 +298,9 @@ void ip_destroy(ip_ctx *ctx) {
   DevBuf *bufs[] = {&ctx->vt_keys, &ctx->vt_vals, &ctx->vt_aux, &ctx->et_keys, &ctx->eval_list,
                     &ctx->fb_list, &ctx->scratch, &ctx->scene};
   for (DevBuf *b : bufs)
-    if (b->p) (void)hipFree(b->p);
+    if (b->p) ip_dfree(ctx, b->p);
+  ip_cache_release(ctx);
+  for (auto &kv : ctx->cache.size_of) (void)hipFree(kv.first);  // blocks never returned
   if (ctx->ctr_dev) (void)hipFree(ctx->ctr_dev);
   if (ctx->ctr_host) (void)hipHostFree(ctx->ctr_host);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -392,11 +462,13 @@ int ip_cells_points(const ip_cells *c, const double **pts_dev, int64_t *ld) {
 
 void ip_cells_free(ip_cells *c) {
   if (!c) return;
-  if (c->ctx) (void)hipStreamSynchronize(c->ctx->stream);
-  if (c->keys) (void)hipFree(c->keys);
-  if (c->pts) (void)hipFree(c->pts);
-  if (c->verdict) (void)hipFree(c->verdict);
-  if (c->free_pts) (void)hipFree(c->free_pts);
+  if (c->ctx) {
+    (void)hipStreamSynchronize(c->ctx->stream);
+    ip_dfree(c->ctx, c->keys);
+    ip_dfree(c->ctx, c->pts);
+    ip_dfree(c->ctx, c->verdict);
+    ip_dfree(c->ctx, c->free_pts);
+  }
   delete c;
 }
 
@@ -413,7 +485,7 @@ int ip_check_cells(ip_ctx *ctx, ip_cells *c, const ip_scene *scene, int64_t *n_f
   if (!c || !scene) return ip_fail(ctx, IP_EINVAL, "null argument");
   if (scene->n_joints != c->d) return ip_fail(ctx, IP_EINVAL, "scene joints must equal the dimension");
   IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  if (!c->verdict) IP_TRY_HIP(ctx, hipMalloc((void **)&c->verdict, (size_t)(c->n ? c->n : 1)));
+  if (!c->verdict) IP_TRY(ip_dalloc(ctx, (void **)&c->verdict, (size_t)(c->n ? c->n : 1)));
   IP_TRY_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
   IP_TRY(ip_check_impl(ctx, scene, c->pts, c->n, c->ld, c->verdict));
   IP_TRY_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));

@@ -337,12 +337,12 @@ int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64
 
 int ip_compact_free_impl(ip_ctx *ctx, ip_cells *c) {
   if (c->free_pts) {
-    (void)hipFree(c->free_pts);
+    ip_dfree(ctx, c->free_pts);
     c->free_pts = nullptr;
   }
   const int64_t n = c->n;
   if (n >= (1ll << 32)) return ip_fail(ctx, IP_EINVAL, "more than 2^32 cells in one check");
-  IP_TRY_HIP(ctx, hipMalloc((void **)&c->free_pts, sizeof(double) * (size_t)(n ? n : 1) * c->d));
+  IP_TRY(ip_dalloc(ctx, (void **)&c->free_pts, sizeof(double) * (size_t)(n ? n : 1) * c->d));
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
   if (n) {
     int64_t blocks = (n + 255) / 256;

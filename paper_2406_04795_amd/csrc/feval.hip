@@ -270,10 +270,11 @@ int ip_feval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_
   double *bnd = bound_dev;
   void *tmp_b = nullptr, *fbl = nullptr;
   if (!bnd) {
-    IP_TRY_HIP(ctx, hipMalloc(&tmp_b, sizeof(double) * (size_t)n));
+    IP_TRY(ip_dalloc(ctx, &tmp_b, sizeof(double) * (size_t)n));
     bnd = (double *)tmp_b;
   }
-  IP_TRY_HIP(ctx, hipMalloc(&fbl, sizeof(uint32_t) * (size_t)n));
+  if (n >= (1ll << 32)) return ip_fail(ctx, IP_EINVAL, "ip_feval: at most 2^32 - 1 vertices per call");
+  IP_TRY(ip_dalloc(ctx, &fbl, sizeof(uint32_t) * (size_t)n));
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
   int rc = dispatch32<1>(ctx, p->poly, p->fine, nullptr, (uint64_t)n, nullptr, nullptr, v_dev, f_dev, bnd,
                          (uint32_t *)fbl, &ctx->ctr_dev->n_fb);
@@ -286,8 +287,8 @@ int ip_feval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_
   }
   if (rc == IP_OK) rc = dispatch64<2>(ctx, p->f, p->fine, (const uint32_t *)fbl, nfb, nullptr, v_dev, f_dev);
   (void)hipStreamSynchronize(ctx->stream);
-  if (tmp_b) (void)hipFree(tmp_b);
-  (void)hipFree(fbl);
+  ip_dfree(ctx, tmp_b);
+  ip_dfree(ctx, fbl);
   ctx->last_fallback = (int64_t)nfb;
   return rc;
 }

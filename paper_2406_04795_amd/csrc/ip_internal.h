@@ -7,7 +7,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ip.h"
@@ -206,7 +209,9 @@ __device__ __forceinline__ int ht_insert_s(uint64_t *base, uint64_t mask, uint64
   uint64_t h = mix64(key) & mask;
   for (uint64_t n = 0; n <= mask; ++n) {
     uint64_t *p = base + h * SW;
-    uint64_t cur = ld_relaxed(p);
+    // keys only go from empty to final, so a plain (possibly stale) load is
+    // safe: a stale empty slot is settled by the CAS below
+    uint64_t cur = *(volatile uint64_t *)p;
     if (cur == key) {
       *slot = h;
       return 0;
@@ -389,6 +394,21 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Caching device allocator of a context: freed blocks are kept (by size)
+// and handed out again to requests of at most their size and at least half
+// of it, so repeated traces of similar size reuse their buffers instead of
+// paying hipMalloc / hipFree (which synchronise the device) every call.
+// Sizes round up to 2 MiB.  When hipMalloc fails the cache is released and
+// the allocation retried.  Thread-safe: results of the serving loop can be
+// freed from another thread.
+struct DevCache {
+  std::mutex mu;
+  std::multimap<size_t, void *> idle;   // size -> block
+  std::unordered_map<void *, size_t> size_of;
+  size_t idle_bytes = 0;
+  size_t limit = 0;                     // bytes kept idle at most
+};
+
 struct ip_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -399,6 +419,7 @@ struct ip_ctx {
   DevBuf vt_keys;   // vertex table (VEnt entries)
   DevBuf vt_vals, vt_aux, et_keys, eval_list, fb_list, scratch;
   DevBuf scene;
+  DevCache cache;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int64_t last_fallback = 0;  // FP64 re-evaluations of the last ip_feval
 };
@@ -431,6 +452,11 @@ struct ip_cells {
   int64_t n_free = 0;
   ip_stats st = {};
 };
+
+// Device memory through the context's cache (see DevCache).
+int ip_dalloc(ip_ctx *ctx, void **p, size_t bytes);
+void ip_dfree(ip_ctx *ctx, void *p);
+void ip_cache_release(ip_ctx *ctx);
 
 // Error helpers used by the host code.
 int ip_fail(ip_ctx *ctx, int code, const std::string &msg);

@@ -80,10 +80,15 @@ __device__ void locate(const LatDev &L, const double *y, int32_t *v, int32_t *w)
 }
 
 // Mark edge (v, mask) in the entry of its smaller endpoint; true if this
-// call was the first to mark it.
+// call was the first to mark it.  Bits only ever go from 0 to 1, so a plain
+// load that already shows the bit proves the edge visited; most cofaces lead
+// to visited edges, and they skip the atomic.  A stale 0 falls through to the
+// atomicOr, which decides.
 __device__ __forceinline__ bool mark_edge(VEnt *vt, uint64_t owner, uint32_t mask) {
   const unsigned long long bit = 1ull << (mask & 63u);
-  const unsigned long long old = atomicOr(&vt[owner].m[mask >> 6], bit);
+  unsigned long long *w = &vt[owner].m[mask >> 6];
+  if (*(volatile unsigned long long *)w & bit) return false;
+  const unsigned long long old = atomicOr(w, bit);
   return !(old & bit);
 }
 
@@ -506,15 +511,9 @@ int fill_vt(ip_ctx *ctx, VEnt *p, uint64_t n) {
   return IP_OK;
 }
 
-int alloc(ip_ctx *ctx, void **p, size_t bytes) {
-  hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return ip_fail(ctx, IP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-  }
-  return IP_OK;
-}
+int alloc(ip_ctx *ctx, void **p, size_t bytes) { return ip_dalloc(ctx, p, bytes); }
+
+void release(ip_ctx *ctx, void *p) { ip_dfree(ctx, p); }
 
 // Vertex table of capacity cap (power of two), reusing the context buffers.
 int vt_init(Run &s, uint64_t cap) {
@@ -564,15 +563,15 @@ int vt_grow(Run &s, uint64_t new_cap, uint64_t n_out) {
                      (const VEnt *)nt, new_cap, (uint32_t *)nl, ctx->ctr_dev);
   IP_TRY_HIP(ctx, hipGetLastError());
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  (void)hipFree(ctx->vt_keys.p);
-  (void)hipFree(ctx->eval_list.p);
+  release(ctx, ctx->vt_keys.p);
+  release(ctx, ctx->eval_list.p);
   ctx->vt_keys = {nt, new_cap * sizeof(VEnt)};
   ctx->eval_list = {nl, new_cap * 4};
   s.vt = (VEnt *)nt;
   s.eval = (uint32_t *)nl;
   s.vt_cap = new_cap;
   if (s.cert) {
-    (void)hipFree(ctx->vt_vals.p);
+    release(ctx, ctx->vt_vals.p);
     ctx->vt_vals = {nvb, new_cap * 4};
     s.vb = (float *)nvb;
     IP_TRY(ip_ensure(ctx, ctx->fb_list, new_cap * 4));
@@ -593,7 +592,7 @@ int out_reserve(Run &s, uint64_t need, uint64_t n_used) {
   if (n_used)
     IP_TRY_HIP(ctx, hipMemcpyAsync(nb, s.out, n_used * sizeof(OutRec), hipMemcpyDeviceToDevice, ctx->stream));
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (s.out) (void)hipFree(s.out);
+  if (s.out) release(ctx, s.out);
   s.out = (OutRec *)nb;
   s.out_cap = cap;
   return IP_OK;
@@ -1093,14 +1092,15 @@ int lehmer_bits(int d) {
 // and the list of keys in insertion order; the list's capacity equals the
 // set's, since every key in the set was appended exactly once.
 struct BatchOut {
+  ip_ctx *ctx = nullptr;
   uint64_t *et = nullptr;
   uint64_t et_cap = 0;
   uint64_t *keys = nullptr;
   ~BatchOut() {
-    if (et) (void)hipFree(et);
-    if (keys) (void)hipFree(keys);
+    if (et) ip_dfree(ctx, et);
+    if (keys) ip_dfree(ctx, keys);
   }
-  uint64_t *release() {
+  uint64_t *take_keys() {
     uint64_t *k = keys;
     keys = nullptr;
     return k;
@@ -1118,8 +1118,8 @@ struct BatchOut {
       IP_TRY_HIP(ctx, hipGetLastError());
     }
     IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (et) (void)hipFree(et);
-    if (keys) (void)hipFree(keys);
+    if (et) ip_dfree(ctx, et);
+    if (keys) ip_dfree(ctx, keys);
     et = (uint64_t *)ne;
     keys = (uint64_t *)nk;
     et_cap = cap;
@@ -1148,7 +1148,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   {
     int rc = trace_direct<D>(s, st, &nc);
     if (rc != IP_OK) {
-      if (s.out) (void)hipFree(s.out);
+      if (s.out) release(ctx, s.out);
       return rc;
     }
   }
@@ -1156,7 +1156,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   s.out = nullptr;
   s.out_cap = 0;
   auto free_coarse = [&]() {
-    if (coarse_edges) (void)hipFree(coarse_edges);
+    if (coarse_edges) release(ctx, coarse_edges);
     coarse_edges = nullptr;
   };
   // ---- Sigma: n-cofaces of the coarse edges, deduplicated
@@ -1176,7 +1176,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     if (rc == IP_OK) rc = alloc(ctx, &sig_list, (bound + 1) * 8);
     if (rc != IP_OK) {
       free_coarse();
-      if (sig_tab) (void)hipFree(sig_tab);
+      if (sig_tab) release(ctx, sig_tab);
       return rc;
     }
     IP_TRY(fill(ctx, sig_tab, cap, IP_EMPTY_KEY));
@@ -1189,7 +1189,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     IP_TRY(read_ctr(ctx));
     nsig = ctx->ctr_host->n_aux;
     free_coarse();
-    (void)hipFree(sig_tab);
+    release(ctx, sig_tab);
     sig_tab = nullptr;
   }
   st.n_sigma = (int64_t)nsig;
@@ -1229,6 +1229,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
   // global fine edge set (ET) + output keys, whose capacity follows ET's
   BatchOut g;
+  g.ctx = ctx;
   IP_TRY(g.reserve(ctx, 1ull << 20, 0));
   double *pts = nullptr;
   uint64_t pts_ld = 0;
@@ -1296,7 +1297,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
                                          hipMemcpyDeviceToDevice, ctx->stream));
       }
       IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-      if (pts) (void)hipFree(pts);
+      if (pts) release(ctx, pts);
       pts = np_;
       pts_ld = nld;
     }
@@ -1335,11 +1336,11 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   IP_TRY(tf.flush(ctx));
   IP_TRY(tx.flush(ctx));
   IP_TRY(tp.flush(ctx));
-  (void)hipFree(tpts);
-  (void)hipFree(tedge);
-  (void)hipFree(sig_list);
+  release(ctx, tpts);
+  release(ctx, tedge);
+  release(ctx, sig_list);
   if (rc != IP_OK) {
-    if (pts) (void)hipFree(pts);
+    if (pts) release(ctx, pts);
     return rc;
   }
   if (!pts) IP_TRY(alloc(ctx, (void **)&pts, 8 * D));
@@ -1347,7 +1348,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   res->B = p->fine.B;
   for (int j = 0; j < 8; ++j) res->vmin[j] = p->fine.vmin[j];
   res->n = (int64_t)n_out;
-  res->keys = g.release();
+  res->keys = g.take_keys();
   res->pts = pts;
   res->ld = (int64_t)(pts_ld ? pts_ld : 1);
   st.n_cells = (int64_t)n_out;
@@ -1418,11 +1419,11 @@ int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_
   if (rc == IP_OK && n) rc = direct_points<D>(s, n, keys, pts, st);
   if (s.out) {
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(s.out);
+    release(ctx, s.out);
   }
   if (rc != IP_OK) {
-    if (keys) (void)hipFree(keys);
-    if (pts) (void)hipFree(pts);
+    if (keys) release(ctx, keys);
+    if (pts) release(ctx, pts);
     return rc;
   }
   res->d = D;
