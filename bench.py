@@ -1,20 +1,24 @@
-"""Benchmark: trace + collision-check throughput on one MI355X.
+"""Benchmark: trace + collision-check throughput on one MI355X, and proof
+latency in the serving loop.
 
 One step = one whole pass of the hot path on one synthetic proof problem:
-seed location, breadth-first manifold tracing over the Coxeter triangulation
-(f evaluation, coface expansion, hash dedup), intersection points, collision
+seed location, manifold tracing over the Coxeter triangulation (batch
+triangulation for the d=6 workload: coarse trace, n-coface set, template
+subdivision, f evaluation, sign tests, dedup), intersection points, collision
 check of every traced cell and gathering of the free points.  Inputs are
-uploaded before the timed region; nothing is cached between steps (every step
-rebuilds its tables and outputs from the seeds).
+uploaded before the timed region; nothing is cached between steps.
 
-Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
-build runs on one GPU.
+`value` is the FP32-certified path (exact: the traced set equals the FP64
+one); the plain FP64 path is timed beside it on the same GPU.  The serving
+section replays a Poisson stream of mixed proof requests through the
+library's server and reports p50/p99 latency.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -33,14 +37,15 @@ METRIC = "simplices traced/s + cells checked/s at d=6; p50/p99 proof latency in 
 def workload(name: str):
     from paper_2406_04795_amd import inputs as I
     if name == "d6":
-        # 6-DoF arm, 16 obstacles (8 boxes + 8 spheres), f with 2000 SVs of
-        # degree 3, scale 0.06
+        # 6-DoF arm, 16 obstacles (8 boxes + 8 spheres), 2000 SVs of degree 3,
+        # fine scale 0.06, batch triangulation with k = 4
+        return I.config_c3(eps=2e-5, k=4)
+    if name == "d6direct":
         wl = I.config_c3(eps=2e-5, k=1)
         wl.name = "d6_S2000_p3_lam0.06_direct"
         return wl
     if name == "d5":
-        wl = I.config_c2(eps=3e-4)
-        return wl
+        return I.config_c2(eps=3e-4)
     if name == "d3":
         return I.config_c1()
     raise SystemExit(f"unknown config {name}")
@@ -51,28 +56,51 @@ def flops_per_vertex(f) -> int:
     return f.S * (2 * f.d + f.p + 3)
 
 
+def expand_bytes(st, wl) -> float:
+    """Algorithmic HBM bytes of the search / subdivision kernels.
+
+    Direct mode, per 2-coface: pass 1 vertex-table probe (8 B key) and
+    third-vertex slot write (4 B); pass 2 slot read (4 B), f read (8 B) and
+    edge-mask word read (8 B).  Per new vertex one 8 B key CAS; per traced
+    edge a 16 B append and 2 x 16 B frontier reads.
+    Batch mode, per coarse simplex: per template point a vertex-table probe
+    (8 B) and a 4 B slot write; per template edge two 4 B slot reads and two
+    8 B f reads; per traced edge an 8 B edge-set probe and an 8 B append;
+    plus the coarse search (direct-mode bytes of its cofaces)."""
+    if st["n_sigma"] > 0:
+        from math import comb
+        npnt = comb(wl.f.d + wl.k, wl.f.d)
+        return (st["n_sigma"] * npnt * 12 + st["n_template_edges"] * 24 + st["n_cells"] * 16
+                + st["n_cofaces"] * 32)
+    return st["n_cofaces"] * 32 + st["n_vertices"] * 8 + st["n_cells"] * 48
+
+
 def cpu_baseline(wl, budget_s: float = 20.0):
     """The oracle (single thread) on a bounded sample of the same workload:
-    the same manifold, scale and scene, traced inside a sub-box of the domain
-    centred on the first seed, plus the collision check of those cells."""
+    the same manifold, scale, coarse factor and scene, traced inside a sub-box
+    of the domain centred on the first seed, plus points and collision check
+    of those cells."""
     import copy
 
     import oracle as O
     from paper_2406_04795_amd import inputs as I
 
     O.build(force=False)
-    half = 0.12
+    half = 0.15
     while True:
         sub = copy.copy(wl)
         c = wl.seeds[0]
         sub.dom = I.Domain(lo=np.maximum(wl.dom.lo, c - half), hi=np.minimum(wl.dom.hi, c + half))
         sub.seeds = wl.seeds[:1]
         t0 = time.perf_counter()
-        v, m = O.trace_direct(sub)
+        if wl.k > 1:
+            v, m, _ = O.trace_batch(sub)
+        else:
+            v, m = O.trace_direct(sub)
         t_trace = time.perf_counter() - t0
-        # the oracle's point pass re-evaluates f at both ends of every cell,
-        # about 2.5x the trace time; stop growing the sub-box at ~1/8 of budget
-        if t_trace > budget_s / 8 or half > 1.0:
+        # the point pass re-evaluates f at both ends of every cell: stop
+        # growing the sub-box at about 1/6 of the budget
+        if t_trace > budget_s / 6 or half > 1.5:
             break
         half *= 1.25
     t0 = time.perf_counter()
@@ -88,9 +116,79 @@ def cpu_baseline(wl, budget_s: float = 20.0):
         "unit": "simplices/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"same f/scale/scene traced in a sub-box of half-width {half:.3f} around the first "
+        "sample": f"same f/scale/k/scene traced in a sub-box of half-width {half:.3f} around the first "
                   f"seed: {n} cells, trace {t_trace:.2f}s + points {t_pts:.2f}s + check {t_check:.2f}s",
     }
+
+
+def timed_runs(ip, ctx, prob, wl, prec, steps, warmup, budget):
+    import torch
+
+    def step():
+        c = ip.Cells(ctx, prob, budget=budget, precision=prec)
+        nf = c.check(wl.scene)
+        st = c.stats()
+        c.close()
+        return st, nf
+
+    name = "fp32" if prec == ip.IP_FP32_CERTIFY else "fp64"
+    for i in range(warmup):
+        st, nf = step()
+        print(f"[bench] {name} warmup {i}: {st['n_cells']} cells, trace {st['ms_total']:.1f} ms",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(steps):
+        st, nf = step()
+        stats.append(st)
+        print(f"[bench] {name} step {i}: {st['n_cells']} cells, trace {st['ms_total']:.1f} ms, "
+              f"check {st['ms_check']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return stats, nf, elapsed
+
+
+def phase(stats, key):
+    return float(np.mean([s[key] for s in stats]))
+
+
+def serving(ip, reqs, slots, rate, precision, seed=1):
+    """Replay requests with Poisson arrivals (rate per second; 0 = all at
+    once) through a server with `slots` slots; returns per-request results."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=len(reqs)) if rate > 0 else np.zeros(len(reqs))
+    arrivals = np.cumsum(gaps)
+    srv = ip.ip_server_create(0, 0, slots)
+    try:
+        t0 = ip.ip_server_clock(srv)
+        ids = []
+        for wl, ta in zip(reqs, arrivals):
+            while ip.ip_server_clock(srv) - t0 < ta:
+                time.sleep(0.0002)
+            ids.append(ip.ip_server_submit(srv, wl, precision=precision, scene=wl.scene))
+        res = [ip.ip_server_wait(srv, i) for i in ids]
+    finally:
+        ip.ip_server_destroy(srv)
+    bad = [r["error"] for r in res if r["status"] != 0]
+    if bad:
+        raise RuntimeError(f"serving requests failed: {bad[:3]}")
+    return res
+
+
+def latency_summary(res):
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res]) * 1e3
+    t_first = min(r["t_submit"] for r in res)
+    t_last = max(r["t_done"] for r in res)
+    cells = sum(r["n_cells"] for r in res)
+    return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3), "simplices_per_s": cells / (t_last - t_first),
+            "requests": len(res)}
+
+
+def _gen_requests(span):
+    from paper_2406_04795_amd import inputs as I
+    return [I.serving_request(i) for i in range(*span)]
 
 
 def main():
@@ -99,7 +197,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="d6")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"])
+    ap.add_argument("--budget-gib", type=float, default=64.0,
+                    help="batch-triangulation workspace cap per batch (GiB)")
+    ap.add_argument("--serve", type=int, default=256, help="serving requests (0: skip)")
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -107,96 +209,104 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # inputs first, on the CPU: the pool forks before anything touches the GPU
+    wl = workload(args.config)
+    reqs = []
+    if args.serve:
+        from concurrent.futures import ProcessPoolExecutor
+        n = args.serve
+        with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+            chunks = list(ex.map(_gen_requests, [(i, min(n, i + 8)) for i in range(0, n, 8)]))
+        reqs = [r for c in chunks for r in c]
+        print(f"[bench] {len(reqs)} serving requests generated", file=sys.stderr, flush=True)
+
     import torch
 
     from paper_2406_04795_amd import ip
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    wl = workload(args.config)
-    prec = ip.IP_FP64 if args.precision == "fp64" else ip.IP_FP32_CERTIFY
     print(f"[bench] workload {wl.name}: d={wl.f.d} S={wl.f.S} p={wl.f.p} lam={wl.lat.lam} k={wl.k}",
           file=sys.stderr, flush=True)
-
+    budget = int(args.budget_gib * (1 << 30))
     ctx = ip.Context(0)
     prob = ip.Problem(ctx, wl)
-
-    def step():
-        c = ip.Cells(ctx, prob, precision=prec)
-        nf = c.check(wl.scene)
-        st = c.stats()
-        c.close()
-        return st, nf
-
-    for i in range(args.warmup):
-        st, nf = step()
-        print(f"[bench] warmup {i}: {st['n_cells']} cells in {st['ms_total']:.1f} ms", file=sys.stderr,
-              flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for i in range(args.steps):
-        st, nf = step()
-        stats.append(st)
-        print(f"[bench] step {i}: {st['n_cells']} cells, trace {st['ms_total']:.1f} ms, "
-              f"check {st['ms_check']:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    precs = {"both": [ip.IP_FP32_CERTIFY, ip.IP_FP64], "fp32": [ip.IP_FP32_CERTIFY],
+             "fp64": [ip.IP_FP64]}[args.precision]
+    runs = {}
+    for prec in precs:
+        first = prec == precs[0]
+        runs[prec] = timed_runs(ip, ctx, prob, wl, prec, args.steps if first else max(1, args.steps - 1),
+                                args.warmup if first else 0, budget)
     prob.close()
     ctx.close()
 
+    main_prec = precs[0]
+    stats, nf, elapsed = runs[main_prec]
+    n_steps = len(stats)
     n_cells = stats[-1]["n_cells"]
-    value = n_cells * args.steps / elapsed
-    ms_step = elapsed * 1000 / args.steps
+    value = n_cells * n_steps / elapsed
 
-    # dominant kernel class by measured time
-    f_ms = float(np.mean([s["ms_feval"] for s in stats]))
-    x_ms = float(np.mean([s["ms_expand"] for s in stats]))
-    nv = stats[-1]["n_vertices"]
-    fl = flops_per_vertex(wl.f) * nv
-    feval_tfs = fl / (f_ms * 1e-3) / 1e12 if f_ms > 0 else 0.0
-    cof = stats[-1]["n_cofaces"]
-    # algorithmic bytes of the two expansion passes per coface: pass 1 vertex
-    # probe (8 B key), pass 2 vertex probe + value (16 B) and edge-set probe
-    # (8 B); per frontier edge 2 x 8 B key reads; per new vertex / edge one
-    # 8 B CAS write and one 4/8 B list append
-    xbytes = cof * 32 + n_cells * (16 + 16) + nv * 12
-    if f_ms >= x_ms:
-        roof = {"kernel": "feval64", "bound": "alu", "achieved": round(feval_tfs, 3),
-                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(feval_tfs / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                "ms_per_step": round(f_ms, 3)}
+    def summary(prec):
+        st, _, el = runs[prec]
+        s = st[-1]
+        return {"simplices_per_s": s["n_cells"] * len(st) / el, "ms_per_step": el * 1e3 / len(st),
+                "phases_ms": {"trace": phase(st, "ms_total"), "feval": phase(st, "ms_feval"),
+                              "search_subdivide": phase(st, "ms_expand"), "points": phase(st, "ms_points"),
+                              "check": phase(st, "ms_check")},
+                "vertices_evaluated": s["n_vertices"], "fp64_canonical_evals": s["n_fallback"],
+                "settled_by_fp64_monomial": s["n_settled64"]}
+
+    # roofline of the dominant kernel class in the main run
+    x_ms = phase(stats, "ms_expand")
+    f_ms = phase(stats, "ms_feval")
+    if x_ms >= f_ms:
+        gbs = expand_bytes(stats[-1], wl) / (x_ms * 1e-3) / 1e9
+        roof = {"kernel": "batch_vertices+batch_edges" if wl.k > 1 else "expand (2 passes)", "bound": "hbm",
+                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_step": round(x_ms, 3)}
     else:
-        gbs = xbytes / (x_ms * 1e-3) / 1e9
-        roof = {"kernel": "expand", "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "ms_per_step": round(x_ms, 3)}
+        tfs = flops_per_vertex(wl.f) * stats[-1]["n_vertices"] / (f_ms * 1e-3) / 1e12
+        roof = {"kernel": "feval64", "bound": "alu", "achieved": round(tfs, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tfs / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "ms_per_step": round(f_ms, 3)}
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "simplices/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": n_steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": elapsed * 1e3 / n_steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == ip.IP_FP64 else "f32+f64",
+        "dtype": "f32+f64" if main_prec == ip.IP_FP32_CERTIFY else "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "d": wl.f.d, "n_sv": wl.f.S, "degree": wl.f.p,
-                   "scale": wl.lat.lam, "coarse_k": wl.k, "cells": n_cells,
-                   "free_cells": int(nf), "vertices": nv, "levels": stats[-1]["levels"],
-                   "cofaces": int(cof)},
-        "precision": {"fp64_canonical_evals": int(stats[-1]["n_fallback"]),
-                      "settled_by_fp64_monomial": int(stats[-1]["n_settled64"])},
-        "phases_ms": {"trace": float(np.mean([s["ms_total"] for s in stats])),
-                      "feval": f_ms, "expand": x_ms,
-                      "points": float(np.mean([s["ms_points"] for s in stats])),
-                      "check": float(np.mean([s["ms_check"] for s in stats]))},
-        "feval_tflops": round(feval_tfs, 3),
+                   "scale": wl.lat.lam, "coarse_k": wl.k, "batch_budget_gib": args.budget_gib,
+                   "cells": n_cells, "free_cells": int(nf), "coarse_simplices": stats[-1]["n_sigma"],
+                   "batches": stats[-1]["n_batches"], "levels": stats[-1]["levels"]},
         "roofline": roof,
     }
+    for prec in precs:
+        out["fp32_certify" if prec == ip.IP_FP32_CERTIFY else "fp64"] = summary(prec)
+
+    if reqs:
+        # isolated capacity: requests one at a time, back to back
+        iso = serving(ip, reqs[:16], 1, 0.0, ip.IP_FP32_CERTIFY)
+        t_service = float(np.mean([r["t_done"] - r["t_start"] for r in iso]))
+        rate = 0.7 / t_service
+        print(f"[bench] serving: isolated service {t_service * 1e3:.1f} ms, arrival rate {rate:.1f}/s",
+              file=sys.stderr, flush=True)
+        srv = {"requests": len(reqs), "slots": args.slots, "arrival_rate_per_s": round(rate, 2),
+               "isolated_service_ms": round(t_service * 1e3, 3)}
+        for key, slots, prec in (("fp32_certify", args.slots, ip.IP_FP32_CERTIFY),
+                                 ("fp64", args.slots, ip.IP_FP64),
+                                 ("queue_only_fp32", 1, ip.IP_FP32_CERTIFY)):
+            srv[key] = latency_summary(serving(ip, reqs, slots, rate, prec))
+            print(f"[bench] serving {key}: {srv[key]}", file=sys.stderr, flush=True)
+        out["serving"] = srv
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))

@@ -155,11 +155,18 @@ __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Longest probe sequence: a key is never placed further than this from its
+// home slot, so lookups stop there too.  At the loads the host keeps
+// (<= 1/2) sequences are a few slots long; hitting the cap means the table
+// is overloaded, and the insert reports failure at once (the host grows the
+// table and replays the pass) instead of walking the whole table.
+#define IP_MAX_PROBE 4096ull
+
 // Open addressing with linear probing.  Returns 1 when `key` was inserted,
 // 0 when it was present, -1 when the table is full; *slot gets its position.
 __device__ __forceinline__ int ht_insert(uint64_t *keys, uint64_t mask, uint64_t key, uint64_t *slot) {
   uint64_t h = mix64(key) & mask;
-  for (uint64_t n = 0; n <= mask; ++n) {
+  for (uint64_t n = 0; n <= mask && n < IP_MAX_PROBE; ++n) {
     uint64_t cur = ld_relaxed(keys + h);
     if (cur == key) {
       *slot = h;
@@ -185,7 +192,7 @@ __device__ __forceinline__ int ht_insert(uint64_t *keys, uint64_t mask, uint64_t
 // Lookup in a table that no thread modifies during the kernel.
 __device__ __forceinline__ int64_t ht_find(const uint64_t *keys, uint64_t mask, uint64_t key) {
   uint64_t h = mix64(key) & mask;
-  for (uint64_t n = 0; n <= mask; ++n) {
+  for (uint64_t n = 0; n <= mask && n < IP_MAX_PROBE; ++n) {
     uint64_t cur = keys[h];
     if (cur == key) return (int64_t)h;
     if (cur == IP_EMPTY_KEY) return -1;
@@ -207,7 +214,7 @@ struct __attribute__((aligned(32))) VEnt {
 template <int SW>
 __device__ __forceinline__ int ht_insert_s(uint64_t *base, uint64_t mask, uint64_t key, uint64_t *slot) {
   uint64_t h = mix64(key) & mask;
-  for (uint64_t n = 0; n <= mask; ++n) {
+  for (uint64_t n = 0; n <= mask && n < IP_MAX_PROBE; ++n) {
     uint64_t *p = base + h * SW;
     // keys only go from empty to final, so a plain (possibly stale) load is
     // safe: a stale empty slot is settled by the CAS below
@@ -231,7 +238,7 @@ __device__ __forceinline__ int ht_insert_s(uint64_t *base, uint64_t mask, uint64
 template <int SW>
 __device__ __forceinline__ int64_t ht_find_s(const uint64_t *base, uint64_t mask, uint64_t key) {
   uint64_t h = mix64(key) & mask;
-  for (uint64_t n = 0; n <= mask; ++n) {
+  for (uint64_t n = 0; n <= mask && n < IP_MAX_PROBE; ++n) {
     uint64_t cur = base[h * SW];
     if (cur == key) return (int64_t)h;
     if (cur == IP_EMPTY_KEY) return -1;

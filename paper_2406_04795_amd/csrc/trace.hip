@@ -18,6 +18,8 @@
 // VT, re-points OUT's slots and replays pass 1, which is idempotent.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "ip_internal.h"
@@ -484,6 +486,13 @@ struct Run {
   int64_t n_fallback = 0;
   int64_t n_settled64 = 0;
 };
+
+// Progress lines on stderr when the environment sets IP_LOG (diagnostics of
+// long traces; off by default).
+bool log_on() {
+  static const bool on = getenv("IP_LOG") != nullptr;
+  return on;
+}
 
 int read_ctr(ip_ctx *ctx) {
   IP_TRY_HIP(ctx, hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream));
@@ -1193,25 +1202,33 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     sig_tab = nullptr;
   }
   st.n_sigma = (int64_t)nsig;
+  if (log_on())
+    fprintf(stderr, "[ip] coarse trace: %llu edges, %llu coarse n-simplices\n", (unsigned long long)nc,
+            (unsigned long long)nsig);
   // ---- template on the device
   void *tpts = nullptr, *tedge = nullptr;
   IP_TRY(alloc(ctx, &tpts, T.pts.size() * 8));
   IP_TRY(alloc(ctx, &tedge, T.edges.size() * 4));
   IP_TRY_HIP(ctx, hipMemcpyAsync(tpts, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   IP_TRY_HIP(ctx, hipMemcpyAsync(tedge, T.edges.data(), T.edges.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-  // ---- batches: per coarse simplex NP slots, NP vertex-table entries at
-  // load <= 1/2 (16 B key+value each, twice) and NP eval-list entries
-  const uint64_t per_sigma = (uint64_t)NP * (4 + 2 * 16 + 2 * 4);
+  // ---- batches.  Per-batch workspace: the vertex table (power-of-two
+  // capacity, load <= 1/2: 2 NP slots per coarse simplex, each a 32-byte
+  // entry plus 4-byte eval-list, bound and fallback entries) and NP 4-byte
+  // template slots per coarse simplex.  The largest table that fits the
+  // budget fixes the batch size B.
+  const uint64_t slot_bytes = sizeof(VEnt) + 12;
   if (budget == 0) budget = 4ull << 30;
-  if (budget < per_sigma) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
-  uint64_t B = budget / per_sigma;
+  uint64_t vcap_b = 0;
+  for (uint64_t c = 1024; c <= (1ull << 32); c <<= 1)
+    if (c * slot_bytes + (c / 2) * 4 <= budget && c >= 2 * (uint64_t)NP) vcap_b = c;
+  if (vcap_b == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
+  uint64_t B = vcap_b / (2 * (uint64_t)NP);
   if (B > nsig) B = nsig ? nsig : 1;
-  if (B * (uint64_t)NP * 2 > (1ull << 31)) B = (1ull << 31) / ((uint64_t)NP * 2);
   Run f;
   f.ctx = ctx;
   f.p = p;
   f.L = p->fine;
-  const uint64_t vcap = pow2_at_least(B * (uint64_t)NP * 2);
+  const uint64_t vcap = std::min<uint64_t>(vcap_b, pow2_at_least(B * (uint64_t)NP * 2));
   IP_TRY(ip_ensure(ctx, ctx->vt_keys, vcap * sizeof(VEnt)));
   IP_TRY(ip_ensure(ctx, ctx->eval_list, vcap * 4));
   IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * (uint64_t)NP * 4));
@@ -1228,9 +1245,14 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   }
   uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
   // global fine edge set (ET) + output keys, whose capacity follows ET's
+  // fine edges are about coarse edges x k^(d-1): start the set there
   BatchOut g;
   g.ctx = ctx;
-  IP_TRY(g.reserve(ctx, 1ull << 20, 0));
+  {
+    double est = (double)nc;
+    for (int q = 0; q < D - 1; ++q) est *= k;
+    IP_TRY(g.reserve(ctx, pow2_at_least((uint64_t)std::min(est * 2.5, 4.0e9)), 0));
+  }
   double *pts = nullptr;
   uint64_t pts_ld = 0;
   uint64_t n_out = 0;
@@ -1286,6 +1308,9 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     }
     st.n_template_edges += (int64_t)(nb * (uint64_t)NE);
     const uint64_t lo = batch_lo, hi = c->n_out;
+    if (log_on())
+      fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu new vertices, %llu cells so far\n",
+              (long long)batches, (unsigned long long)nb, (unsigned long long)c->n_eval, (unsigned long long)hi);
     if (hi > pts_ld) {
       // grow the SoA point buffer, copying the columns
       const uint64_t nld = std::max<uint64_t>(hi, pts_ld * 2);

@@ -370,3 +370,52 @@ def dyadic_sphere_case(d=3, R2=1.0, step=0.125, half=1.6):
     u = np.ones(d) / np.sqrt(d)
     seeds = np.ascontiguousarray((math.sqrt(R2) * u)[None, :])
     return Workload(f"dyadic_sphere_d{d}", fm, lat, dom, seeds)
+
+
+# --------------------------------------------------------------------------
+# Serving requests: the same manifold family, each request restricted to a
+# sub-box of C-space sized for a target number of cells
+# --------------------------------------------------------------------------
+def _edge_density(d):
+    """Asymptotic crossing-edge density of the Coxeter frame, edges per unit
+    area at unit scale (used only to size inputs)."""
+    kappa = math.gamma(d / 2) / (math.sqrt(math.pi) * math.gamma((d + 1) / 2))
+    s = sum(math.comb(d, r) * math.sqrt(r * (d + 1 - r) / (d + 1)) for r in range(1, d + 1))
+    return kappa * math.sqrt(d + 1) * s
+
+
+def subbox_case(d, S, lam, target_cells, seed=0, p=3, eps=3e-3, k=1, scene=None):
+    """Degree-p kernel, N(0,1) coefficients, bias at the eps-quantile of f0;
+    the domain is the sub-box around the first seed whose half-width w makes
+    a locally flat zero set cross about target_cells edges:
+    N ~ C_d (2w)^(d-1) / lam^(d-1)."""
+    rng = np.random.default_rng(seed)
+    full = box(d)
+    fm = random_manifold(d, S, p, rng, full, alpha="normal")
+    fm.bias = quantile_bias(fm, full, rng, eps, n_probe=4000)
+    seeds = bisection_seeds(fm, full, rng, 1, n_probe=4000, iters=40)
+    w = 0.5 * (target_cells * lam ** (d - 1) / _edge_density(d)) ** (1.0 / (d - 1))
+    c = seeds[0]
+    dom = Domain(lo=np.maximum(full.lo, c - w), hi=np.minimum(full.hi, c + w))
+    lat = make_lattice(d, lam, rng)
+    return Workload(f"subbox_d{d}_S{S}_lam{lam:.3f}", fm, lat, dom, seeds, k, scene)
+
+
+def serving_request(i, seed=0, cells=(1e5, 2e6)):
+    """Proof request i of the serving workload: d in {4,5,6}, S log-uniform
+    in [100, 2000], scale uniform in [0.06, 0.12], degree 3, target size
+    log-uniform in `cells`, its own scene and seed 1000 + i; coarse factor
+    k = 2 for d = 6 below scale 0.09, else direct."""
+    rng = np.random.default_rng((seed, i))
+    d = int(rng.integers(4, 7))
+    S = int(round(math.exp(rng.uniform(math.log(100), math.log(2000)))))
+    lam = float(rng.uniform(0.06, 0.12))
+    target = float(math.exp(rng.uniform(math.log(cells[0]), math.log(cells[1]))))
+    k = 2 if (d == 6 and lam < 0.09) else 1
+    srng = np.random.default_rng(1000 + i)
+    sc = spatial_arm_scene(srng, d, spheres_per_link=2, sphere_r=0.05, n_osph=6, n_obox=4)
+    return subbox_case(d, S, lam, target, seed=1000 + i, k=k, scene=sc)
+
+
+def serving_requests(n=256, seed=0, cells=(1e5, 2e6)):
+    return [serving_request(i, seed, cells) for i in range(n)]
