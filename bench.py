@@ -28,7 +28,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (v_fma_f64), dense
+# MI355X vector ALU: 256 CUs x 64 lanes x 2 flops (fma) x 2.4 GHz = 78.6
+# TFLOP/s for FP64 and for unpacked FP32 (the library is built without
+# packed-FP32 instructions; with them FP32 would double to 157.3)
+VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 METRIC = "simplices traced/s + cells checked/s at d=6; p50/p99 proof latency in loop"
@@ -51,27 +54,39 @@ def workload(name: str):
     raise SystemExit(f"unknown config {name}")
 
 
-def flops_per_vertex(f) -> int:
-    # per support vector: d fma (dot) + 1 fma (gamma, coef0) + (p-1) mul + 1 fma (alpha)
-    return f.S * (2 * f.d + f.p + 3)
+def template_size(d: int, k: int):
+    """Points and edges of the local subdivision template of one coarse
+    simplex (points k >= u_0 >= ... >= u_{d-1} >= 0; edges (u, u + 1_R))."""
+    import itertools
+    pts = [u for u in itertools.product(range(k + 1), repeat=d) if all(u[i] >= u[i + 1] for i in range(d - 1))]
+    ps = set(pts)
+    ne = 0
+    for u in pts:
+        for r in range(1, 1 << d):
+            if tuple(u[i] + ((r >> i) & 1) for i in range(d)) in ps:
+                ne += 1
+    return len(pts), ne
+
+
+def subdivide_flops_per_simplex(wl) -> int:
+    """Algorithmic floating-point operations of the fused subdivision kernel
+    per coarse simplex: for each template point its FP64 lattice coordinates
+    (d^2 fma) and the FP32 monomial-basis value with its bound sum (per
+    non-constant monomial: 1 mul for the monomial, 1 fma for the value, 1 fma
+    for the bound sum)."""
+    from math import comb
+    d, p = wl.f.d, wl.f.p
+    n_mono = comb(d + p, p)
+    npnt, _ = template_size(d, wl.k)
+    return npnt * (2 * d * d + 5 * (n_mono - 1))
 
 
 def expand_bytes(st, wl) -> float:
-    """Algorithmic HBM bytes of the search / subdivision kernels.
-
-    Direct mode, per 2-coface: pass 1 vertex-table probe (8 B key) and
-    third-vertex slot write (4 B); pass 2 slot read (4 B), f read (8 B) and
-    edge-mask word read (8 B).  Per new vertex one 8 B key CAS; per traced
-    edge a 16 B append and 2 x 16 B frontier reads.
-    Batch mode, per coarse simplex: per template point a vertex-table probe
-    (8 B) and a 4 B slot write; per template edge two 4 B slot reads and two
-    8 B f reads; per traced edge an 8 B edge-set probe and an 8 B append;
-    plus the coarse search (direct-mode bytes of its cofaces)."""
-    if st["n_sigma"] > 0:
-        from math import comb
-        npnt = comb(wl.f.d + wl.k, wl.f.d)
-        return (st["n_sigma"] * npnt * 12 + st["n_template_edges"] * 24 + st["n_cells"] * 16
-                + st["n_cofaces"] * 32)
+    """Algorithmic HBM bytes of the direct-mode search kernels, per 2-coface:
+    pass 1 vertex-table probe (8 B key) and third-vertex slot write (4 B);
+    pass 2 slot read (4 B), f read (8 B) and edge-mask word read (8 B).  Per
+    new vertex one 8 B key CAS; per traced edge a 16 B append and 2 x 16 B
+    frontier reads."""
     return st["n_cofaces"] * 32 + st["n_vertices"] * 8 + st["n_cells"] * 48
 
 
@@ -251,25 +266,30 @@ def main():
         st, _, el = runs[prec]
         s = st[-1]
         return {"simplices_per_s": s["n_cells"] * len(st) / el, "ms_per_step": el * 1e3 / len(st),
-                "phases_ms": {"trace": phase(st, "ms_total"), "feval": phase(st, "ms_feval"),
-                              "search_subdivide": phase(st, "ms_expand"), "points": phase(st, "ms_points"),
-                              "check": phase(st, "ms_check")},
+                "phases_ms": {"trace": phase(st, "ms_total"), "search": phase(st, "ms_expand"),
+                              "subdivide": phase(st, "ms_subdivide"), "feval": phase(st, "ms_feval"),
+                              "points": phase(st, "ms_points"), "check": phase(st, "ms_check")},
+                "edge_hits": s["n_edge_hits"],
                 "vertices_evaluated": s["n_vertices"], "fp64_canonical_evals": s["n_fallback"],
                 "settled_by_fp64_monomial": s["n_settled64"]}
 
-    # roofline of the dominant kernel class in the main run
-    x_ms = phase(stats, "ms_expand")
-    f_ms = phase(stats, "ms_feval")
-    if x_ms >= f_ms:
-        gbs = expand_bytes(stats[-1], wl) / (x_ms * 1e-3) / 1e9
-        roof = {"kernel": "batch_vertices+batch_edges" if wl.k > 1 else "expand (2 passes)", "bound": "hbm",
-                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_step": round(x_ms, 3)}
+    # roofline of the dominant kernel of the main run, from the library's HIP
+    # events around its launches on the context's stream
+    if wl.k > 1 and main_prec == ip.IP_FP32_CERTIFY:
+        ms = phase(stats, "ms_subdivide")
+        launches = stats[-1]["subdivide_launches"]
+        flops = subdivide_flops_per_simplex(wl) * stats[-1]["n_sigma"]
+        tfs = flops / (ms * 1e-3) / 1e12
+        roof = {"kernel": "subdivide_kernel (fused, FP32-certified)", "bound": "alu", "achieved": round(tfs, 2),
+                "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tfs / VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None, "ms_per_launch": round(ms / max(1, launches), 3), "launches_per_step": launches,
+                "flops_per_coarse_simplex": subdivide_flops_per_simplex(wl)}
     else:
-        tfs = flops_per_vertex(wl.f) * stats[-1]["n_vertices"] / (f_ms * 1e-3) / 1e12
-        roof = {"kernel": "feval64", "bound": "alu", "achieved": round(tfs, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tfs / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                "ms_per_step": round(f_ms, 3)}
+        x_ms = phase(stats, "ms_expand")
+        gbs = expand_bytes(stats[-1], wl) / (x_ms * 1e-3) / 1e9
+        roof = {"kernel": "expand_kernel (2 passes)", "bound": "hbm", "achieved": round(gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "ms_per_step": round(x_ms, 3)}
     out = {
         "metric": METRIC,
         "value": value,

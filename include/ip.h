@@ -108,7 +108,10 @@ typedef struct {
 
 typedef struct {
   int64_t n_cells;       /* traced edges (1-simplices) = intersection points */
-  int64_t n_vertices;    /* unique lattice vertices whose f was evaluated */
+  int64_t n_vertices;    /* lattice vertices whose f was evaluated: unique
+                            vertices, except in the FP32-certified batch
+                            mode, which evaluates each template point of
+                            each coarse simplex (in the box) once */
   int64_t n_fallback;    /* vertices whose sign the FP32 and FP64 monomial
                             bounds left open: canonical FP64 evaluations
                             (IP_FP32_CERTIFY), plus ends of edges whose point
@@ -126,6 +129,13 @@ typedef struct {
   double ms_expand;      /* time in frontier-expansion kernels */
   double ms_points;      /* time in the intersection-point kernel */
   double ms_check;       /* time in the collision kernel (ip_check_cells) */
+  double ms_subdivide;   /* batch mode: time in the subdivision kernel
+                            (sign codes of the template points of each coarse
+                            simplex, template edge tests, edge-set inserts) */
+  int64_t subdivide_launches; /* launches that ms_subdivide covers */
+  int64_t n_edge_hits;   /* batch mode: intersecting (coarse simplex, template
+                            edge) pairs, duplicates across simplices included */
+  int64_t n_coarse_edges; /* batch mode: intersecting edges of the coarse trace */
 } ip_stats;
 
 /* Create a context on HIP device `device`; work is issued on `hip_stream`
@@ -164,6 +174,17 @@ int ip_cells_download(ip_ctx *ctx, const ip_cells *c, int32_t *v, uint32_t *mask
                       double *pts);
 /* Device view of the intersection points: SoA, pts[j * ld + i]. */
 int ip_cells_points(const ip_cells *c, const double **pts_dev, int64_t *ld);
+/* Order-independent digest of the traced set: digest[0] = sum and
+ * digest[1] = xor, over the cells, of the SplitMix64 finalizer of the packed
+ * edge key (the set is unique, its order is not).  Device-side; two 8-byte
+ * host outputs. */
+int ip_cells_digest(ip_ctx *ctx, const ip_cells *c, uint64_t digest[2]);
+/* Copy rows idx[0 .. n) (host array, each in [0, count)) of the cells to the
+ * host: vertex v (n x d), mask, point (n x d, row-major) and, once
+ * ip_check_cells has run, the verdict.  Any output may be NULL.  An index out
+ * of range, or a verdict request before the check, is IP_EINVAL. */
+int ip_cells_gather(ip_ctx *ctx, const ip_cells *c, const int64_t *idx, int64_t n, int32_t *v, uint32_t *mask,
+                    double *pts, uint8_t *verdict);
 void ip_cells_free(ip_cells *c);
 
 /* Collision verdicts for n configurations (Sec. V-C).  q_dev: device SoA,

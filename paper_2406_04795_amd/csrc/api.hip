@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "ip_internal.h"
 
@@ -457,6 +458,103 @@ int ip_cells_points(const ip_cells *c, const double **pts_dev, int64_t *ld) {
   if (!c || !pts_dev || !ld) return IP_EINVAL;
   *pts_dev = c->pts;
   *ld = c->ld;
+  return IP_OK;
+}
+
+namespace {
+
+// Order-independent digest of the traced edge keys: (sum, xor) of the
+// SplitMix64-finalized keys.
+__global__ void digest_kernel(const uint64_t *keys, int64_t n, unsigned long long *sum, unsigned long long *x) {
+  unsigned long long s = 0, q = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t h = mix64(keys[i]);
+    s += h;
+    q ^= h;
+  }
+  for (int off = 32; off; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    q ^= __shfl_xor(q, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(sum, s);
+    atomicXor(x, q);
+  }
+}
+
+// Rows idx[0 .. n) of the cells: keys, points (row-major n x d), verdicts.
+__global__ void gather_kernel(const uint64_t *keys, const double *pts, int64_t ld, const uint8_t *verdict,
+                              const int64_t *idx, int64_t n, int d, uint64_t *okeys, double *opts, uint8_t *over) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx[r];
+    okeys[r] = keys[i];
+    for (int j = 0; j < d; ++j) opts[r * d + j] = pts[(int64_t)j * ld + i];
+    if (verdict) over[r] = verdict[i];
+  }
+}
+
+}  // namespace
+
+int ip_cells_digest(ip_ctx *ctx, const ip_cells *c, uint64_t digest[2]) {
+  if (!ctx && c) ctx = c->ctx;
+  if (!ctx) return IP_EINVAL;
+  if (!c || !digest) return ip_fail(ctx, IP_EINVAL, "null argument");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+  if (c->n > 0) {
+    hipLaunchKernelGGL(digest_kernel, dim3(1024), dim3(256), 0, ctx->stream, (const uint64_t *)c->keys, c->n,
+                       &ctx->ctr_dev->n_eval, &ctx->ctr_dev->n_aux);
+    IP_TRY_HIP(ctx, hipGetLastError());
+  }
+  IP_TRY_HIP(ctx, hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream));
+  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  digest[0] = ctx->ctr_host->n_eval;
+  digest[1] = ctx->ctr_host->n_aux;
+  return IP_OK;
+}
+
+int ip_cells_gather(ip_ctx *ctx, const ip_cells *c, const int64_t *idx, int64_t n, int32_t *v, uint32_t *mask,
+                    double *pts, uint8_t *verdict) {
+  if (!ctx && c) ctx = c->ctx;
+  if (!ctx) return IP_EINVAL;
+  if (!c || n < 0 || (n > 0 && !idx)) return ip_fail(ctx, IP_EINVAL, "ip_cells_gather: bad arguments");
+  if (verdict && !c->verdict) return ip_fail(ctx, IP_EINVAL, "cells have not been checked");
+  for (int64_t r = 0; r < n; ++r)
+    if (idx[r] < 0 || idx[r] >= c->n) return ip_fail(ctx, IP_EINVAL, "ip_cells_gather: index out of range");
+  if (n == 0) return IP_OK;
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const int d = c->d;
+  const size_t bytes = (size_t)n * (8 + 8 + 8 * (size_t)d + 1);
+  void *buf = nullptr;
+  IP_TRY(ip_dalloc(ctx, &buf, bytes));
+  int64_t *didx = (int64_t *)buf;
+  uint64_t *dkeys = (uint64_t *)(didx + n);
+  double *dpts = (double *)(dkeys + n);
+  uint8_t *dver = (uint8_t *)(dpts + (size_t)n * d);
+  std::vector<uint64_t> keys((size_t)n);
+  std::vector<uint8_t> ver(verdict ? (size_t)n : 0);
+  hipError_t e = hipMemcpyAsync(didx, idx, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0,
+                       ctx->stream, (const uint64_t *)c->keys, (const double *)c->pts, c->ld,
+                       (const uint8_t *)(verdict ? c->verdict : nullptr), (const int64_t *)didx, n, d, dkeys, dpts,
+                       dver);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(keys.data(), dkeys, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess && pts)
+    e = hipMemcpyAsync(pts, dpts, (size_t)n * d * 8, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess && verdict) e = hipMemcpyAsync(verdict, dver, (size_t)n, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  ip_dfree(ctx, buf);
+  if (e != hipSuccess) return ip_hip(ctx, e, "ip_cells_gather");
+  const uint64_t m = (1ull << c->B) - 1ull;
+  for (int64_t r = 0; r < n; ++r) {
+    const uint64_t k = keys[(size_t)r] & ~IP_SIGN_BIT;
+    if (v)
+      for (int j = 0; j < d; ++j) v[r * d + j] = (int32_t)((k >> (j * c->B)) & m) + c->vmin[j];
+    if (mask) mask[r] = (uint32_t)(k >> (d * c->B)) & ((1u << d) - 1u);
+  }
   return IP_OK;
 }
 

@@ -167,20 +167,10 @@ __global__ __launch_bounds__(256) void feval32_kernel(PolyDev Q, LatDev L, const
       }
       double x64[D];
       lat_coords<D>(L, v, x64);
-      float x[D];
-#pragma unroll
-      for (int j = 0; j < D; ++j) x[j] = (float)x64[j];
-      float acc = Q.c[0], aabs = fabsf(Q.c[0]);
-      int ci = 1;
-      MonoWalk<float, D, P, 0>::run(x, 1.0f, Q.c, ci, acc, aabs);
-      double bnd = Q.K32 * (double)aabs + Q.E0;
-      double fv = (double)acc;
-      unsure = !(fabs(fv) > bnd + Q.B64);
-      if (unsure) {
-        fv = poly64<D, P>(Q, x64, &bnd);
-        unsure = !(fabs(fv) > bnd + Q.B64);
-        if (!unsure) ++n64;
-      }
+      double fv, bnd;
+      const int tier = cert_eval<D, P>(Q, x64, &fv, &bnd);
+      unsure = tier == 3;
+      if (tier == 2) ++n64;
       if (MODE == 0) {
         if (!unsure) vt[id].f = fv;
         vb[id] = unsure ? -1.0f : (float)(bnd * (1.0 + 1e-6));
@@ -244,6 +234,11 @@ int dispatch32(ip_ctx *ctx, const PolyDev &Q, const LatDev &L, const uint32_t *l
 int launch_feval64(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n_list,
                    VEnt *vt) {
   return dispatch64<0>(ctx, p->f, L, list, n_list, (const uint64_t *)vt, nullptr, (double *)vt + 1);
+}
+
+int launch_feval64_raw(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const int32_t *v, uint64_t n,
+                       double *out) {
+  return dispatch64<1>(ctx, p->f, L, nullptr, n, nullptr, v, out);
 }
 
 int launch_feval32(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n_list,

@@ -73,6 +73,8 @@ struct Counters {
   unsigned long long n_fb_total; // fallbacks over the whole call
   unsigned long long n_aux;      // general-purpose append counter
   unsigned long long n_cert64;   // vertices settled by the FP64 monomial tier
+  unsigned long long n_pts;      // template points evaluated (fused subdivision)
+  unsigned long long n_unsettled;// template points left to the canonical tier
   unsigned int vt_fail;          // vertex-table insert found the table full
   unsigned int et_fail;          // edge-table insert found the table full
 };
@@ -328,6 +330,26 @@ __device__ __forceinline__ double poly64_any(const PolyDev &Q, const double *x, 
   }
 }
 
+// Tiered certified evaluation at the canonical FP64 coordinates x64.  Tier 1:
+// FP32 in the monomial basis, settled when |f32| > B32 + B64.  Tier 2: FP64
+// in the monomial basis, settled when |f64m| > B64m + B64.  Returns the tier
+// that settled the sign of the canonical FP64 value (f and its bound in *fv,
+// *bnd), or 3 when neither did.
+template <int D, int P>
+__device__ __forceinline__ int cert_eval(const PolyDev &Q, const double *x64, double *fv, double *bnd) {
+  float x[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) x[j] = (float)x64[j];
+  float acc = Q.c[0], aabs = fabsf(Q.c[0]);
+  int ci = 1;
+  MonoWalk<float, D, P, 0>::run(x, 1.0f, Q.c, ci, acc, aabs);
+  *bnd = Q.K32 * (double)aabs + Q.E0;
+  *fv = (double)acc;
+  if (fabs(*fv) > *bnd + Q.B64) return 1;
+  *fv = poly64<D, P>(Q, x64, bnd);
+  return fabs(*fv) > *bnd + Q.B64 ? 2 : 3;
+}
+
 // Deposit the low bits of src into the set positions of mask (ascending).
 __device__ __forceinline__ uint32_t pdep32(uint32_t src, uint32_t mask) {
   uint32_t out = 0;
@@ -501,3 +523,6 @@ int launch_set_vb(ip_ctx *ctx, const uint32_t *list, uint64_t n, float *vb, floa
 // vt: vertex-table entries; the result goes into vt[slot].f.
 int launch_feval64(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list,
                    uint64_t n_list, VEnt *vt);
+// Canonical FP64 f at n raw vertices (int32, row-major n x d) into out[i].
+int launch_feval64_raw(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const int32_t *v, uint64_t n,
+                       double *out);

@@ -19,24 +19,6 @@
 
 namespace {
 
-// Order-independent digest of the traced edge keys.
-__global__ void digest_kernel(const uint64_t *keys, int64_t n, unsigned long long *sum, unsigned long long *x) {
-  unsigned long long s = 0, q = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t h = mix64(keys[i]);
-    s += h;
-    q ^= h;
-  }
-  for (int off = 32; off; off >>= 1) {
-    s += __shfl_xor(s, off, 64);
-    q ^= __shfl_xor(q, off, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(sum, s);
-    atomicXor(x, q);
-  }
-}
-
 // Deep copy of a request's host inputs.
 struct OwnedRequest {
   ip_fparams f;
@@ -134,20 +116,10 @@ struct ip_server {
     if (rc == IP_OK) rc = ip_trace(ctx, p, q.budget, q.prec, 0, &c);
     if (rc == IP_OK && q.has_scene) rc = ip_check_cells(ctx, c, &q.sc, &r->n_free);
     if (rc == IP_OK) {
-      unsigned long long *dg = &ctx->ctr_dev->n_aux;  // two adjacent counters
-      hipError_t e = hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream);
-      if (e == hipSuccess && c->n > 0) {
-        hipLaunchKernelGGL(digest_kernel, dim3(256), dim3(256), 0, ctx->stream, c->keys, c->n, &ctx->ctr_dev->n_eval,
-                           &ctx->ctr_dev->n_aux);
-        e = hipGetLastError();
-      }
-      (void)dg;
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-      if (e != hipSuccess) rc = ip_hip(ctx, e, "server digest");
-      r->digest[0] = ctx->ctr_host->n_eval;
-      r->digest[1] = ctx->ctr_host->n_aux;
+      uint64_t dg[2] = {0, 0};
+      rc = ip_cells_digest(ctx, c, dg);
+      r->digest[0] = dg[0];
+      r->digest[1] = dg[1];
     }
     if (rc == IP_OK) {
       r->n_cells = c->n;

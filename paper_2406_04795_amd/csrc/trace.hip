@@ -18,6 +18,7 @@
 // VT, re-points OUT's slots and replays pass 1, which is idempotent.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -478,7 +479,7 @@ struct Run {
   OutRec *out = nullptr;
   uint64_t out_cap = 0;
   uint32_t *cslot = nullptr;
-  int regrows = 0;
+  int64_t regrows = 0;
   bool cert = false;      // FP32 certified evaluation (else canonical FP64)
   float *vb = nullptr;    // per-slot bound of the stored f (cert only)
   uint32_t *fb = nullptr; // FP64 fallback list
@@ -504,6 +505,13 @@ int zero_field(ip_ctx *ctx, unsigned long long *field) {
   hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, ctx->stream, field);
   IP_TRY_HIP(ctx, hipGetLastError());
   return IP_OK;
+}
+
+// Clears both failure flags, which share one aligned 8-byte word.
+int zero_fail_flags(ip_ctx *ctx) {
+  static_assert(offsetof(Counters, vt_fail) % 8 == 0 && offsetof(Counters, et_fail) == offsetof(Counters, vt_fail) + 4,
+                "failure flags must share one 8-byte word");
+  return zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->vt_fail);
 }
 
 int fill(ip_ctx *ctx, void *p, uint64_t n, uint64_t v) {
@@ -659,7 +667,7 @@ int trace_direct(Run &s, ip_stats &st, uint64_t *n_out_ret) {
     IP_TRY_HIP(ctx, hipGetLastError());
     IP_TRY(read_ctr(ctx));
     if (!c->vt_fail) break;
-    IP_TRY(zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->vt_fail));
+    IP_TRY(zero_fail_flags(ctx));
     IP_TRY(vt_grow<D>(s, s.vt_cap * 4, 0));
   }
   IP_TRY(tf.start(ctx, &st.ms_feval));
@@ -686,7 +694,7 @@ int trace_direct(Run &s, ip_stats &st, uint64_t *n_out_ret) {
     int guard = 0;
     while (c->vt_fail || c->vt_count * 2 > s.vt_cap) {
       if (++guard > 40) return ip_fail(ctx, IP_ENOMEM, "vertex table cannot grow");
-      IP_TRY(zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->vt_fail));
+      IP_TRY(zero_fail_flags(ctx));
       IP_TRY(vt_grow<D>(s, pow2_at_least(c->vt_count * 4), hi));
       // slots moved: replay pass 1 so CSL points into the new table; it
       // finds the inserted vertices and lists the missing ones after the
@@ -958,74 +966,12 @@ __global__ __launch_bounds__(kBlock) void batch_vertices_kernel(LatDev Lf, LatDe
   }
 }
 
-// Fine edges of the subdivision (Sec. V-B, Fig. 6): sign test on the two
-// endpoint values, insertion of the intersecting ones into the global fine
-// edge set; new edges are appended to the output key list.
+// Intersection points of the edges keys[lo .. hi) from the canonical FP64
+// values of their ends, looked up in the batch vertex table.
 template <int D>
-__global__ __launch_bounds__(kBlock) void batch_edges_kernel(LatDev Lf, LatDev Lc, int LB, int k,
-                                                             const uint64_t *__restrict__ sig, uint64_t nb,
-                                                             const uint64_t *__restrict__ tpts, int NP,
-                                                             const uint32_t *__restrict__ tedge, int NE,
-                                                             const uint32_t *__restrict__ pslot,
-                                                             const VEnt *__restrict__ vt, uint64_t *et_keys,
-                                                             uint64_t et_mask, uint64_t *out, Counters *ctr) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t total = nb * (uint64_t)NE;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t start = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t rounds = (total + stride - 1) / stride;
-  unsigned long long hits = 0;
-  for (uint64_t it = 0; it < rounds; ++it) {
-    const uint64_t t = start + it * stride;
-    bool is_new = false;
-    uint64_t key = 0;
-    if (t < total) {
-      const uint64_t s = t / (uint64_t)NE;
-      const int e = (int)(t - s * (uint64_t)NE);
-      const uint32_t te = tedge[e];
-      const int a = (int)(te & 0xfffu), b = (int)((te >> 12) & 0xfffu);
-      const uint32_t Rl = te >> 24;
-      const uint32_t sa = pslot[s * NP + a], sb = pslot[s * NP + b];
-      if (sa != 0xffffffffu && sb != 0xffffffffu) {
-        const bool pa = !(vt[sa].f < 0.0), pb = !(vt[sb].f < 0.0);
-        if (pa != pb) {
-          ++hits;
-          int32_t v[D], w[D], y[D];
-          sig_unpack<D>(Lc, sig[s], LB, v, w);
-          template_point<D>(v, w, k, tpts[a], y);
-          uint32_t Rg = 0;
-#pragma unroll
-          for (int i = 0; i < D; ++i) Rg |= ((Rl >> i) & 1u) << w[i];
-          key = ekey<D>(Lf, y, Rg);
-          uint64_t slot;
-          int ins = ht_insert(et_keys, et_mask, key, &slot);
-          if (ins == 1)
-            is_new = true;
-          else if (ins < 0)
-            atomicOr(&ctr->et_fail, 1u);
-        }
-      }
-    }
-    const uint64_t bal = __ballot(is_new);
-    if (bal) {
-      const int leader = __ffsll((long long)bal) - 1;
-      unsigned long long b0 = 0;
-      if (lane == leader) b0 = atomicAdd(&ctr->n_out, (unsigned long long)__popcll(bal));
-      b0 = shfl64(b0, leader);
-      if (is_new) out[b0 + __popcll(bal & ((1ull << lane) - 1ull))] = key;
-    }
-  }
-  if (hits) atomicAdd(&ctr->n_cof, hits);
-}
-
-// Intersection points of the edges keys[lo .. hi), endpoints looked up in the
-// batch vertex table.  REDO: the output indices listed in redo[0 .. hi).
-template <int D, bool REDO>
 __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo, uint64_t hi, const VEnt *vt,
-                                    uint64_t vt_mask, double *pts, int64_t ld, bool cert, const float *vb, PolyDev Q,
-                                    uint64_t *redo, uint32_t *fb, Counters *ctr) {
-  for (uint64_t q = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < hi; q += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t i = REDO ? redo[q] : q;
+                                    uint64_t vt_mask, double *pts, int64_t ld, PolyDev Q) {
+  for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (uint64_t)gridDim.x * blockDim.x) {
     int32_t a[D], b[D];
     uint32_t R;
     eunpack<D>(L, keys[i], a, &R);
@@ -1034,13 +980,209 @@ __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo,
     const int64_t ha = vt_find(vt, vt_mask, vpack<D>(L, a));
     const int64_t hb = vt_find(vt, vt_mask, vpack<D>(L, b));
     const double fa = ha >= 0 ? vt[ha].f : NAN;
-    const double fb_ = hb >= 0 ? vt[hb].f : NAN;
+    const double fb = hb >= 0 ? vt[hb].f : NAN;
     double p[D];
-    const bool c = cert && !REDO && ha >= 0 && hb >= 0;
-    const bool ok = edge_point<D>(L, Q, a, b, fa, fb_, c, c ? vb[ha] : -1.0f, c ? vb[hb] : -1.0f, p);
+    edge_point<D>(L, Q, a, b, fa, fb, false, -1.0f, -1.0f, p);
 #pragma unroll
     for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = p[j];
-    if (!ok) need_fp64(i, (uint64_t)ha, (uint64_t)hb, vb, redo, fb, ctr);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused subdivision for the FP32-certified mode (Sec. V-B, Fig. 6).
+// One wave per coarse simplex.  The wave decides the sign of f at every
+// template point with the certified monomial-basis evaluation, keeps the
+// signs in LDS, tests every template edge against them and inserts the
+// intersecting fine edges into the global edge set.  There is no vertex
+// table: a point shared by several coarse simplices is evaluated by each of
+// them, which costs fewer cycles than a hash probe into a table of hundreds
+// of millions of vertices.  Sign codes: 0 (f < 0), 1 (f >= 0), 2 (outside
+// the box), 3 (neither certified tier settles the sign).
+// MODE 0: simplices sig[0 .. n); a simplex with a code-3 point is appended
+//         to `defer` and skipped.
+// MODE 1: the deferred simplices: their code-3 points are inserted into the
+//         fallback vertex table fvt (new slots to eval_list).
+// MODE 2: the deferred simplices again, code-3 points taking the sign of the
+//         canonical FP64 value in fvt; then the edge pass.
+// MODE 3: vertex-table path (FP64 mode): the sign of template point p of
+//         simplex s is read from fvt[pslot[s * NP + p]].f (pslot ~0: outside
+//         the box); then the edge pass.
+// Dynamic LDS: template points (NP x 8 B), template edges (NE x 4 B), a sign
+// code byte per template point per wave, and the per-wave append stage.
+// ---------------------------------------------------------------------------
+constexpr int kSubStage = 128;
+
+__host__ __device__ inline size_t sub_lds_bytes(int NP, int NE) {
+  const size_t codes = ((size_t)NP + 7) & ~(size_t)7;
+  return (size_t)(kBlock / 64) * kSubStage * 8 + (size_t)NP * 8 + (size_t)NE * 4 + (size_t)(kBlock / 64) * codes;
+}
+
+template <int D, int P, int MODE>
+__global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc, int LB, int k,
+                                                           const uint64_t *__restrict__ sig,
+                                                           const uint32_t *__restrict__ list, uint64_t n,
+                                                           const uint64_t *__restrict__ tpts, int NP,
+                                                           const uint32_t *__restrict__ tedge, int NE, PolyDev Q,
+                                                           VEnt *fvt, uint64_t fvt_mask, uint32_t *eval_list,
+                                                           const uint32_t *__restrict__ pslot, uint64_t *et_keys,
+                                                           uint64_t et_mask, uint64_t *out, uint32_t *defer,
+                                                           Counters *ctr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wib = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int ncode = (NP + 7) & ~7;
+  uint64_t *stage = (uint64_t *)smem + (size_t)wib * kSubStage;
+  uint64_t *lpts = (uint64_t *)smem + (kBlock / 64) * kSubStage;
+  uint32_t *ledge = (uint32_t *)(lpts + NP);
+  uint8_t *code = (uint8_t *)(ledge + NE) + (size_t)wib * ncode;
+  for (int i = threadIdx.x; i < NP; i += kBlock) lpts[i] = tpts[i];
+  if (MODE != 1)
+    for (int i = threadIdx.x; i < NE; i += kBlock) ledge[i] = tedge[i];
+  __syncthreads();
+  int sn = 0;
+  auto put = [&](unsigned long long pos, uint64_t key) { out[pos] = key; };
+  unsigned long long hits = 0, n64 = 0, npts = 0, nuns = 0;
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const uint64_t n_waves = ((uint64_t)gridDim.x * kBlock) >> 6;
+  for (uint64_t it = wave; it < n; it += n_waves) {
+    const uint64_t s = MODE == 0 ? it : (uint64_t)list[it];
+    int32_t v[D], w[D];
+    sig_unpack<D>(Lc, sig[s], LB, v, w);
+    bool unsettled = false;
+    for (int p0 = 0; p0 < NP; p0 += 64) {
+      const int pt = p0 + lane;
+      uint32_t c = 2;
+      if (MODE == 3) {
+        if (pt < NP) {
+          const uint32_t ps = pslot[s * (uint64_t)NP + pt];
+          if (ps != 0xffffffffu) c = fvt[ps].f < 0.0 ? 0u : 1u;
+          code[pt] = (uint8_t)c;
+        }
+      } else if (pt < NP) {
+        int32_t y[D];
+        template_point<D>(v, w, k, lpts[pt], y);
+        double x[D];
+        lat_coords<D>(Lf, y, x);
+        if (lat_in_box<D>(Lf, x)) {
+          double fv, bnd;
+          const int tier = cert_eval<D, P>(Q, x, &fv, &bnd);
+          if (MODE == 0) ++npts;
+          if (tier < 3) {
+            c = fv < 0.0 ? 0u : 1u;
+            if (MODE == 0 && tier == 2) ++n64;
+          } else if (MODE == 0) {
+            c = 3;
+            ++nuns;
+          } else if (MODE == 1) {
+            uint64_t slot;
+            const int ins = vt_insert(fvt, fvt_mask, vpack<D>(Lf, y), &slot);
+            if (ins == 1)
+              eval_list[atomicAdd(&ctr->n_eval, 1ull)] = (uint32_t)slot;
+            else if (ins < 0)
+              atomicOr(&ctr->vt_fail, 1u);
+          } else {
+            const int64_t h = vt_find(fvt, fvt_mask, vpack<D>(Lf, y));
+            if (h < 0) atomicOr(&ctr->vt_fail, 1u);
+            c = (h >= 0 && !(fvt[h].f < 0.0)) ? 1u : 0u;
+          }
+        }
+        code[pt] = (uint8_t)c;
+      }
+      if (MODE == 0 && __ballot(c == 3)) unsettled = true;
+    }
+    if (MODE == 1) continue;
+    if (MODE == 0 && unsettled) {
+      if (lane == 0) defer[atomicAdd(&ctr->n_aux, 1ull)] = (uint32_t)s;
+      wave_lds_sync();
+      continue;
+    }
+    wave_lds_sync();
+    for (int e0 = 0; e0 < NE; e0 += 64) {
+      const int e = e0 + lane;
+      bool is_new = false;
+      uint64_t key = 0;
+      if (e < NE) {
+        const uint32_t te = ledge[e];
+        const uint32_t ca = code[te & 0xfffu], cb = code[(te >> 12) & 0xfffu];
+        if ((ca ^ cb) == 1u && (ca | cb) == 1u) {
+          ++hits;
+          int32_t y[D];
+          template_point<D>(v, w, k, lpts[te & 0xfffu], y);
+          const uint32_t Rl = te >> 24;
+          uint32_t Rg = 0;
+#pragma unroll
+          for (int i = 0; i < D; ++i) Rg |= ((Rl >> i) & 1u) << w[i];
+          key = ekey<D>(Lf, y, Rg);
+          uint64_t slot;
+          const int ins = ht_insert(et_keys, et_mask, key, &slot);
+          if (ins == 1)
+            is_new = true;
+          else if (ins < 0)
+            atomicOr(&ctr->et_fail, 1u);
+        }
+      }
+      stage_put<kSubStage>(stage, sn, is_new, key, put, &ctr->n_out);
+    }
+    wave_lds_sync();
+  }
+  if (MODE != 1) stage_flush(stage, sn, put, &ctr->n_out);
+  if (hits) atomicAdd(&ctr->n_cof, hits);
+  if (n64) atomicAdd(&ctr->n_cert64, n64);
+  if (npts) atomicAdd(&ctr->n_pts, npts);
+  if (nuns) atomicAdd(&ctr->n_unsettled, nuns);
+}
+
+// Ends of the listed edges as raw vertices: vraw[2r] = a, vraw[2r + 1] = b.
+template <int D>
+__global__ void redo_ends_kernel(LatDev L, const uint64_t *keys, const uint64_t *redo, uint64_t n, int32_t *vraw) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+    int32_t a[D];
+    uint32_t R;
+    eunpack<D>(L, keys[redo[r]], a, &R);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      vraw[(2 * r) * D + j] = a[j];
+      vraw[(2 * r + 1) * D + j] = a[j] + (int32_t)((R >> j) & 1u);
+    }
+  }
+}
+
+// Intersection points of the fused path: f at both ends from the FP64
+// monomial basis with its bound (edge_point); an edge whose point the bound
+// cannot place within tolerance is listed in redo for the canonical FP64
+// evaluation of its ends.
+template <int D>
+__global__ void sub_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo, uint64_t hi, double *pts, int64_t ld,
+                                  PolyDev Q, uint64_t *redo, Counters *ctr) {
+  for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (uint64_t)gridDim.x * blockDim.x) {
+    int32_t a[D], b[D];
+    uint32_t R;
+    eunpack<D>(L, keys[i], a, &R);
+#pragma unroll
+    for (int j = 0; j < D; ++j) b[j] = a[j] + (int32_t)((R >> j) & 1u);
+    double p[D];
+    const bool ok = edge_point<D>(L, Q, a, b, 0.0, 0.0, true, 0.0f, 0.0f, p);
+#pragma unroll
+    for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = p[j];
+    if (!ok) redo[atomicAdd(&ctr->n_aux, 1ull)] = i;
+  }
+}
+
+// The listed edges' points from the canonical FP64 values f[2r], f[2r + 1].
+template <int D>
+__global__ void sub_redo_kernel(LatDev L, const uint64_t *keys, const uint64_t *redo, uint64_t n, const double *f,
+                                double *pts, int64_t ld, PolyDev Q) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = redo[r];
+    int32_t a[D], b[D];
+    uint32_t R;
+    eunpack<D>(L, keys[i], a, &R);
+#pragma unroll
+    for (int j = 0; j < D; ++j) b[j] = a[j] + (int32_t)((R >> j) & 1u);
+    double p[D];
+    edge_point<D>(L, Q, a, b, f[2 * r], f[2 * r + 1], false, -1.0f, -1.0f, p);
+#pragma unroll
+    for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = p[j];
   }
 }
 
@@ -1136,6 +1278,377 @@ struct BatchOut {
   }
 };
 
+// Grows the SoA point buffer (columns of length ld) to hold hi rows, keeping
+// the first lo rows.
+template <int D>
+int grow_points(ip_ctx *ctx, uint64_t lo, uint64_t hi, double *&pts, uint64_t &ld) {
+  if (hi <= ld) return IP_OK;
+  const uint64_t nld = std::max<uint64_t>(hi, ld * 2);
+  double *np_ = nullptr;
+  IP_TRY(alloc(ctx, (void **)&np_, nld * D * 8));
+  if (pts && lo) {
+    for (int j = 0; j < D; ++j)
+      IP_TRY_HIP(ctx, hipMemcpyAsync(np_ + (uint64_t)j * nld, pts + (uint64_t)j * ld, lo * 8, hipMemcpyDeviceToDevice,
+                                     ctx->stream));
+  }
+  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (pts) release(ctx, pts);
+  pts = np_;
+  ld = nld;
+  return IP_OK;
+}
+
+// Runs `launch` (which inserts into the global edge set) until no insert
+// found the set full.  Before the first launch the set is grown to keep its
+// load at most 1/2; after an overflow it is grown from the output keys (which
+// include the partial appends of the failed launch) and the launch replayed,
+// which skips the edges already present.
+template <typename F>
+int with_edge_growth(ip_ctx *ctx, BatchOut &g, int64_t &regrows, F launch) {
+  Counters *c = ctx->ctr_host;
+  IP_TRY(read_ctr(ctx));
+  uint64_t n_keys = c->n_out;
+  bool failed = false;
+  for (int guard = 0;; ++guard) {
+    if (n_keys * 2 > g.et_cap || failed) {
+      if (guard > 40) return ip_fail(ctx, IP_ENOMEM, "edge table cannot grow");
+      IP_TRY(zero_fail_flags(ctx));
+      IP_TRY(g.reserve(ctx, pow2_at_least(std::max<uint64_t>(n_keys * 4, g.et_cap * 2)), n_keys));
+      ++regrows;
+    }
+    IP_TRY(launch());
+    IP_TRY(read_ctr(ctx));
+    if (!c->et_fail) return IP_OK;
+    failed = true;
+    n_keys = c->n_out;
+  }
+}
+
+constexpr size_t kSubLdsMax = 64 * 1024;
+constexpr uint64_t kSubGrid = 4096;
+
+template <int D, int MODE>
+int launch_sub(ip_ctx *ctx, const ip_problem *p, int LB, const uint64_t *sig, const uint32_t *list, uint64_t n,
+               const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, VEnt *fvt, uint64_t fvt_mask,
+               uint32_t *eval, BatchOut &g, uint32_t *defer, const uint32_t *pslot = nullptr) {
+  if (n == 0) return IP_OK;
+  const size_t lds = sub_lds_bytes(NP, NE);
+  const uint64_t blocks = std::min<uint64_t>((n + kBlock / 64 - 1) / (kBlock / 64), kSubGrid);
+#define IP_SUB(PP)                                                                                              \
+  hipLaunchKernelGGL((subdivide_kernel<D, PP, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, ctx->stream, \
+                     p->fine, p->coarse, LB, p->k, sig, list, n, tpts, NP, tedge, NE, p->poly, fvt, fvt_mask, eval, \
+                     pslot, g.et, g.et_cap - 1, g.keys, defer, ctx->ctr_dev)
+  if (MODE == 3) {
+    IP_SUB(1);
+    IP_TRY_HIP(ctx, hipGetLastError());
+    return IP_OK;
+  }
+  switch (p->poly.p) {
+    case 1: IP_SUB(1); break;
+    case 2: IP_SUB(2); break;
+    case 3: IP_SUB(3); break;
+    case 4: IP_SUB(4); break;
+    default: return ip_fail(ctx, IP_EINVAL, "fused subdivision needs a polynomial of degree <= 4");
+  }
+#undef IP_SUB
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
+}
+
+// Device buffer released when the holder goes out of scope.
+struct DevTmp {
+  ip_ctx *ctx;
+  void *p = nullptr;
+  explicit DevTmp(ip_ctx *c) : ctx(c) {}
+  ~DevTmp() {
+    if (p) ip_dfree(ctx, p);
+  }
+  int get(size_t bytes) { return alloc(ctx, &p, bytes); }
+  template <typename T>
+  T *as() const {
+    return (T *)p;
+  }
+};
+
+// Points of the fused path for the output keys [lo, hi): FP64 monomial
+// values with the certified placement check, then the canonical FP64 values
+// at both ends of every edge the check rejects.
+template <int D>
+int sub_points(ip_ctx *ctx, const ip_problem *p, const uint64_t *keys, uint64_t lo, uint64_t hi, double *pts,
+               uint64_t ld, Timer &tp, ip_stats &st, int64_t &n_fallback) {
+  if (hi <= lo) return IP_OK;
+  IP_TRY(ip_ensure(ctx, ctx->scratch, (hi - lo) * 8));
+  uint64_t *redo = (uint64_t *)ctx->scratch.p;
+  IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
+  IP_TRY(tp.start(ctx, &st.ms_points));
+  hipLaunchKernelGGL((sub_points_kernel<D>), dim3(grid_for(hi - lo)), dim3(kBlock), 0, ctx->stream, p->fine, keys, lo,
+                     hi, pts, (int64_t)ld, p->poly, redo, ctx->ctr_dev);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  IP_TRY(tp.stop(ctx));
+  IP_TRY(read_ctr(ctx));
+  const uint64_t nredo = ctx->ctr_host->n_aux;
+  if (nredo == 0) return IP_OK;
+  DevTmp vraw(ctx), fr(ctx);
+  IP_TRY(vraw.get(nredo * 2 * D * 4));
+  IP_TRY(fr.get(nredo * 2 * 8));
+  hipLaunchKernelGGL((redo_ends_kernel<D>), dim3(grid_for(nredo)), dim3(kBlock), 0, ctx->stream, p->fine, keys,
+                     (const uint64_t *)redo, nredo, vraw.as<int32_t>());
+  IP_TRY_HIP(ctx, hipGetLastError());
+  IP_TRY(launch_feval64_raw(ctx, p, p->fine, vraw.as<int32_t>(), 2 * nredo, fr.as<double>()));
+  hipLaunchKernelGGL((sub_redo_kernel<D>), dim3(grid_for(nredo)), dim3(kBlock), 0, ctx->stream, p->fine, keys,
+                     (const uint64_t *)redo, nredo, (const double *)fr.as<double>(), pts, (int64_t)ld, p->poly);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  n_fallback += (int64_t)(2 * nredo);
+  return IP_OK;
+}
+
+// Subdivision of the coarse simplices sig[0 .. nsig) in the FP32-certified
+// mode (subdivide_kernel): no vertex table, so the per-batch workspace is one
+// 4-byte deferred-list entry per coarse simplex, plus the fallback vertex
+// table for the points no certified tier settles (sized from their count).
+// The point buffer is handed back through pts / pts_ld also on failure.
+template <int D>
+int subdivide_fused_run(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_all, uint64_t nsig, uint64_t nc,
+                        int LB, const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, uint64_t budget,
+                        ip_stats &st, ip_cells *res, double *&pts, uint64_t &pts_ld) {
+  const int k = p->k;
+  if (budget == 0) budget = 4ull << 30;
+  uint64_t B = std::min<uint64_t>(budget / 4, 0xffffffffull);
+  if (B == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
+  if (B > nsig) B = nsig ? nsig : 1;
+  IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * 4));
+  uint32_t *defer = (uint32_t *)ctx->vt_aux.p;
+  BatchOut g;
+  g.ctx = ctx;
+  {
+    double est = (double)nc;
+    for (int q = 0; q < D - 1; ++q) est *= k;
+    IP_TRY(g.reserve(ctx, pow2_at_least((uint64_t)std::min(est * 2.5, 4.0e9)), 0));
+  }
+  Counters *c = ctx->ctr_host;
+  IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+  uint64_t n_out = 0;
+  int64_t regrows = 0, n_fallback = 0, n_settled64 = 0, n_pts = 0, batches = 0;
+  Timer tf, tx, tp, ts;
+  for (uint64_t b0 = 0; b0 < nsig; b0 += B) {
+    const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
+    const uint64_t *sig = sig_all + b0;
+    ++batches;
+    IP_TRY(with_edge_growth(ctx, g, regrows, [&]() -> int {
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_unsettled));
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_pts));
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cert64));
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
+      IP_TRY(ts.start(ctx, &st.ms_subdivide));
+      IP_TRY((launch_sub<D, 0>(ctx, p, LB, sig, nullptr, nb, tpts, NP, tedge, NE, nullptr, 0, nullptr, g, defer)));
+      ++st.subdivide_launches;
+      return ts.stop(ctx);
+    }));
+    const uint64_t n_def = c->n_aux, n_uns = c->n_unsettled;
+    n_pts += (int64_t)c->n_pts;
+    n_settled64 += (int64_t)c->n_cert64;
+    st.n_edge_hits += (int64_t)c->n_cof;
+    if (n_def) {
+      // canonical FP64 for the points no certified tier settled
+      const uint64_t fcap = pow2_at_least(2 * n_uns + 1024);
+      IP_TRY(ip_ensure(ctx, ctx->vt_keys, fcap * sizeof(VEnt)));
+      IP_TRY(ip_ensure(ctx, ctx->eval_list, fcap * 4));
+      VEnt *fvt = (VEnt *)ctx->vt_keys.p;
+      uint32_t *eval = (uint32_t *)ctx->eval_list.p;
+      IP_TRY(fill_vt(ctx, fvt, fcap));
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
+      IP_TRY(zero_fail_flags(ctx));
+      IP_TRY(tx.start(ctx, &st.ms_expand));
+      IP_TRY((launch_sub<D, 1>(ctx, p, LB, sig, defer, n_def, tpts, NP, tedge, NE, fvt, fcap - 1, eval, g, nullptr)));
+      IP_TRY(tx.stop(ctx));
+      IP_TRY(read_ctr(ctx));
+      if (c->vt_fail) return ip_fail(ctx, IP_ENOMEM, "fallback vertex table overflow");
+      const uint64_t n_ev = c->n_eval;
+      IP_TRY(tf.start(ctx, &st.ms_feval));
+      IP_TRY(launch_feval64(ctx, p, p->fine, eval, n_ev, fvt));
+      IP_TRY(tf.stop(ctx));
+      n_fallback += (int64_t)n_ev;
+      IP_TRY(with_edge_growth(ctx, g, regrows, [&]() -> int {
+        IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
+        IP_TRY(ts.start(ctx, &st.ms_subdivide));
+        IP_TRY((launch_sub<D, 2>(ctx, p, LB, sig, defer, n_def, tpts, NP, tedge, NE, fvt, fcap - 1, nullptr, g,
+                                 nullptr)));
+        ++st.subdivide_launches;
+        return ts.stop(ctx);
+      }));
+      st.n_edge_hits += (int64_t)c->n_cof;
+      if (c->vt_fail) return ip_fail(ctx, IP_EDEVICE, "fallback vertex missing from its table");
+    }
+    st.n_template_edges += (int64_t)(nb * (uint64_t)NE);
+    const uint64_t lo = n_out, hi = c->n_out;
+    if (log_on())
+      fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu deferred, %llu cells so far\n", (long long)batches,
+              (unsigned long long)nb, (unsigned long long)n_def, (unsigned long long)hi);
+    IP_TRY(grow_points<D>(ctx, lo, hi, pts, pts_ld));
+    IP_TRY(sub_points<D>(ctx, p, g.keys, lo, hi, pts, pts_ld, tp, st, n_fallback));
+    n_out = hi;
+  }
+  IP_TRY(tf.flush(ctx));
+  IP_TRY(tx.flush(ctx));
+  IP_TRY(tp.flush(ctx));
+  IP_TRY(ts.flush(ctx));
+  if (!pts) IP_TRY(alloc(ctx, (void **)&pts, 8 * D));
+  res->d = D;
+  res->B = p->fine.B;
+  for (int j = 0; j < 8; ++j) res->vmin[j] = p->fine.vmin[j];
+  res->n = (int64_t)n_out;
+  res->keys = g.take_keys();
+  res->pts = pts;
+  res->ld = (int64_t)(pts_ld ? pts_ld : 1);
+  pts = nullptr;
+  st.n_cells = (int64_t)n_out;
+  st.n_batches = batches;
+  st.n_vertices += n_pts;
+  st.regrows += regrows;
+  st.n_fallback += n_fallback;
+  st.n_settled64 += n_settled64;
+  return IP_OK;
+}
+
+template <int D>
+int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_all, uint64_t nsig, uint64_t nc, int LB,
+                    const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, uint64_t budget, ip_stats &st,
+                    ip_cells *res) {
+  double *pts = nullptr;
+  uint64_t pts_ld = 0;
+  const int rc = subdivide_fused_run<D>(ctx, p, sig_all, nsig, nc, LB, tpts, NP, tedge, NE, budget, st, res, pts,
+                                        pts_ld);
+  if (pts) {
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx, pts);
+  }
+  return rc;
+}
+
+// Subdivision of the coarse simplices sig[0 .. nsig) with canonical FP64
+// values (FP64 mode): per batch the fine vertices of the template points go
+// into a vertex table (each evaluated once), then subdivide_kernel (MODE 3)
+// reads the signs through the per-simplex template slots.  Per-batch
+// workspace: the vertex table (power-of-two capacity, load <= 1/2, so 2 NP
+// slots per coarse simplex, each a 32-byte entry plus a 4-byte eval-list
+// entry) and NP 4-byte template slots per coarse simplex; the largest table
+// that fits the budget fixes the batch size.
+template <int D>
+int subdivide_table_run(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_all, uint64_t nsig, uint64_t nc,
+                        int LB, const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, uint64_t budget,
+                        ip_stats &st, ip_cells *res, double *&pts, uint64_t &pts_ld) {
+  const int k = p->k;
+  const uint64_t slot_bytes = sizeof(VEnt) + 4;
+  if (budget == 0) budget = 4ull << 30;
+  uint64_t vcap_b = 0;
+  for (uint64_t c = 1024; c <= (1ull << 32); c <<= 1)
+    if (c * slot_bytes + (c / 2) * 4 <= budget && c >= 2 * (uint64_t)NP) vcap_b = c;
+  if (vcap_b == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
+  uint64_t B = vcap_b / (2 * (uint64_t)NP);
+  if (B > nsig) B = nsig ? nsig : 1;
+  Run f;
+  f.ctx = ctx;
+  f.p = p;
+  f.L = p->fine;
+  const uint64_t vcap = std::min<uint64_t>(vcap_b, pow2_at_least(B * (uint64_t)NP * 2));
+  IP_TRY(ip_ensure(ctx, ctx->vt_keys, vcap * sizeof(VEnt)));
+  IP_TRY(ip_ensure(ctx, ctx->eval_list, vcap * 4));
+  IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * (uint64_t)NP * 4));
+  f.vt = (VEnt *)ctx->vt_keys.p;
+  f.eval = (uint32_t *)ctx->eval_list.p;
+  f.vt_cap = vcap;
+  uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
+  BatchOut g;
+  g.ctx = ctx;
+  {
+    // fine edges are about coarse edges x k^(d-1): start the set there
+    double est = (double)nc;
+    for (int q = 0; q < D - 1; ++q) est *= k;
+    IP_TRY(g.reserve(ctx, pow2_at_least((uint64_t)std::min(est * 2.5, 4.0e9)), 0));
+  }
+  uint64_t n_out = 0;
+  Counters *c = ctx->ctr_host;
+  IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+  Timer tf, tx, tp, ts;
+  int64_t batches = 0;
+  for (uint64_t b0 = 0; b0 < nsig; b0 += B) {
+    const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
+    const uint64_t *sig = sig_all + b0;
+    ++batches;
+    IP_TRY(fill_vt(ctx, f.vt, vcap));
+    IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
+    IP_TRY(tx.start(ctx, &st.ms_expand));
+    hipLaunchKernelGGL((batch_vertices_kernel<D>), dim3(grid_for(nb * NP)), dim3(kBlock), 0, ctx->stream, p->fine,
+                       p->coarse, LB, k, sig, nb, tpts, NP, f.vt, vcap - 1, f.eval, pslot, ctx->ctr_dev);
+    IP_TRY_HIP(ctx, hipGetLastError());
+    IP_TRY(tx.stop(ctx));
+    IP_TRY(read_ctr(ctx));
+    if (c->vt_fail) return ip_fail(ctx, IP_ENOMEM, "batch vertex table overflow");
+    const uint64_t n_ev = c->n_eval;
+    IP_TRY(tf.start(ctx, &st.ms_feval));
+    IP_TRY(eval_pending(f, n_ev));
+    IP_TRY(tf.stop(ctx));
+    st.n_vertices += (int64_t)n_ev;
+    IP_TRY(with_edge_growth(ctx, g, f.regrows, [&]() -> int {
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
+      IP_TRY(ts.start(ctx, &st.ms_subdivide));
+      IP_TRY((launch_sub<D, 3>(ctx, p, LB, sig, nullptr, nb, tpts, NP, tedge, NE, f.vt, vcap - 1, nullptr, g, nullptr,
+                               pslot)));
+      ++st.subdivide_launches;
+      return ts.stop(ctx);
+    }));
+    st.n_edge_hits += (int64_t)c->n_cof;
+    st.n_template_edges += (int64_t)(nb * (uint64_t)NE);
+    const uint64_t lo = n_out, hi = c->n_out;
+    if (log_on())
+      fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu new vertices, %llu cells so far\n",
+              (long long)batches, (unsigned long long)nb, (unsigned long long)n_ev, (unsigned long long)hi);
+    IP_TRY(grow_points<D>(ctx, lo, hi, pts, pts_ld));
+    if (hi > lo) {
+      IP_TRY(tp.start(ctx, &st.ms_points));
+      hipLaunchKernelGGL((batch_points_kernel<D>), dim3(grid_for(hi - lo)), dim3(kBlock), 0, ctx->stream, p->fine,
+                         (const uint64_t *)g.keys, lo, hi, (const VEnt *)f.vt, vcap - 1, pts, (int64_t)pts_ld, p->poly);
+      IP_TRY_HIP(ctx, hipGetLastError());
+      IP_TRY(tp.stop(ctx));
+    }
+    n_out = hi;
+  }
+  IP_TRY(tf.flush(ctx));
+  IP_TRY(tx.flush(ctx));
+  IP_TRY(tp.flush(ctx));
+  IP_TRY(ts.flush(ctx));
+  if (!pts) IP_TRY(alloc(ctx, (void **)&pts, 8 * D));
+  res->d = D;
+  res->B = p->fine.B;
+  for (int j = 0; j < 8; ++j) res->vmin[j] = p->fine.vmin[j];
+  res->n = (int64_t)n_out;
+  res->keys = g.take_keys();
+  res->pts = pts;
+  res->ld = (int64_t)(pts_ld ? pts_ld : 1);
+  pts = nullptr;
+  st.n_cells = (int64_t)n_out;
+  st.n_batches = batches;
+  st.regrows += f.regrows;
+  return IP_OK;
+}
+
+template <int D>
+int subdivide_table(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_all, uint64_t nsig, uint64_t nc, int LB,
+                    const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, uint64_t budget, ip_stats &st,
+                    ip_cells *res) {
+  double *pts = nullptr;
+  uint64_t pts_ld = 0;
+  const int rc = subdivide_table_run<D>(ctx, p, sig_all, nsig, nc, LB, tpts, NP, tedge, NE, budget, st, res, pts,
+                                        pts_ld);
+  if (pts) {
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx, pts);
+  }
+  return rc;
+}
+
 template <int D>
 int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip_cells *res) {
   ip_stats &st = res->st;
@@ -1145,7 +1658,8 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     return ip_fail(ctx, IP_ERANGE, "coarse simplex keys do not fit 63 bits for this domain and k");
   Template T = make_template(D, k);
   const int NP = (int)T.pts.size(), NE = (int)T.edges.size();
-  if (NP >= 4096) return ip_fail(ctx, IP_EINVAL, "subdivision template too large (reduce k)");
+  if (sub_lds_bytes(NP, NE) > kSubLdsMax)
+    return ip_fail(ctx, IP_EINVAL, "subdivision template does not fit one workgroup's LDS (reduce k)");
   // ---- coarse trace (Sec. V-B: trace at scale k * lambda)
   Run s;
   s.ctx = ctx;
@@ -1201,187 +1715,32 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     release(ctx, sig_tab);
     sig_tab = nullptr;
   }
+  DevTmp sig_hold(ctx), tpts_hold(ctx), tedge_hold(ctx);
+  sig_hold.p = sig_list;
   st.n_sigma = (int64_t)nsig;
+  st.n_coarse_edges = (int64_t)nc;
   if (log_on())
     fprintf(stderr, "[ip] coarse trace: %llu edges, %llu coarse n-simplices\n", (unsigned long long)nc,
             (unsigned long long)nsig);
   // ---- template on the device
-  void *tpts = nullptr, *tedge = nullptr;
-  IP_TRY(alloc(ctx, &tpts, T.pts.size() * 8));
-  IP_TRY(alloc(ctx, &tedge, T.edges.size() * 4));
+  IP_TRY(tpts_hold.get(T.pts.size() * 8));
+  IP_TRY(tedge_hold.get(T.edges.size() * 4));
+  void *tpts = tpts_hold.p, *tedge = tedge_hold.p;
   IP_TRY_HIP(ctx, hipMemcpyAsync(tpts, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   IP_TRY_HIP(ctx, hipMemcpyAsync(tedge, T.edges.data(), T.edges.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-  // ---- batches.  Per-batch workspace: the vertex table (power-of-two
-  // capacity, load <= 1/2: 2 NP slots per coarse simplex, each a 32-byte
-  // entry plus 4-byte eval-list, bound and fallback entries) and NP 4-byte
-  // template slots per coarse simplex.  The largest table that fits the
-  // budget fixes the batch size B.
-  const uint64_t slot_bytes = sizeof(VEnt) + 12;
-  if (budget == 0) budget = 4ull << 30;
-  uint64_t vcap_b = 0;
-  for (uint64_t c = 1024; c <= (1ull << 32); c <<= 1)
-    if (c * slot_bytes + (c / 2) * 4 <= budget && c >= 2 * (uint64_t)NP) vcap_b = c;
-  if (vcap_b == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
-  uint64_t B = vcap_b / (2 * (uint64_t)NP);
-  if (B > nsig) B = nsig ? nsig : 1;
-  Run f;
-  f.ctx = ctx;
-  f.p = p;
-  f.L = p->fine;
-  const uint64_t vcap = std::min<uint64_t>(vcap_b, pow2_at_least(B * (uint64_t)NP * 2));
-  IP_TRY(ip_ensure(ctx, ctx->vt_keys, vcap * sizeof(VEnt)));
-  IP_TRY(ip_ensure(ctx, ctx->eval_list, vcap * 4));
-  IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * (uint64_t)NP * 4));
-  f.vt = (VEnt *)ctx->vt_keys.p;
-  f.eval = (uint32_t *)ctx->eval_list.p;
-  f.vt_cap = vcap;
-  f.cert = cert;
+  int rc;
   if (cert) {
-    IP_TRY(ip_ensure(ctx, ctx->vt_vals, vcap * 4));
-    IP_TRY(ip_ensure(ctx, ctx->fb_list, vcap * 4));
-    f.vb = (float *)ctx->vt_vals.p;
-    f.fb = (uint32_t *)ctx->fb_list.p;
-    f.fb_cap = vcap;
+    rc = subdivide_fused<D>(ctx, p, (const uint64_t *)sig_list, nsig, nc, LB, (const uint64_t *)tpts, NP,
+                            (const uint32_t *)tedge, NE, budget, st, res);
+  } else {
+    rc = subdivide_table<D>(ctx, p, (const uint64_t *)sig_list, nsig, nc, LB, (const uint64_t *)tpts, NP,
+                            (const uint32_t *)tedge, NE, budget, st, res);
   }
-  uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
-  // global fine edge set (ET) + output keys, whose capacity follows ET's
-  // fine edges are about coarse edges x k^(d-1): start the set there
-  BatchOut g;
-  g.ctx = ctx;
-  {
-    double est = (double)nc;
-    for (int q = 0; q < D - 1; ++q) est *= k;
-    IP_TRY(g.reserve(ctx, pow2_at_least((uint64_t)std::min(est * 2.5, 4.0e9)), 0));
-  }
-  double *pts = nullptr;
-  uint64_t pts_ld = 0;
-  uint64_t n_out = 0;
-  Counters *c = ctx->ctr_host;
-  IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
-  Timer tf, tx, tp;
-  int64_t batches = 0;
-  int rc = IP_OK;
-  for (uint64_t b0 = 0; b0 < nsig && rc == IP_OK; b0 += B) {
-    const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
-    const uint64_t *sig = (const uint64_t *)sig_list + b0;
-    ++batches;
-    IP_TRY(fill_vt(ctx, f.vt, vcap));
-    IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
-    IP_TRY(tx.start(ctx, &st.ms_expand));
-    hipLaunchKernelGGL((batch_vertices_kernel<D>), dim3(grid_for(nb * NP)), dim3(kBlock), 0, ctx->stream, p->fine,
-                       p->coarse, LB, k, sig, nb, (const uint64_t *)tpts, NP, f.vt, vcap - 1, f.eval, pslot,
-                       ctx->ctr_dev);
-    IP_TRY_HIP(ctx, hipGetLastError());
-    IP_TRY(tx.stop(ctx));
-    IP_TRY(read_ctr(ctx));
-    if (c->vt_fail) {
-      rc = ip_fail(ctx, IP_ENOMEM, "batch vertex table overflow");
-      break;
-    }
-    IP_TRY(tf.start(ctx, &st.ms_feval));
-    IP_TRY(eval_pending(f, c->n_eval));
-    IP_TRY(tf.stop(ctx));
-    st.n_vertices += (int64_t)c->n_eval;
-    // keep the fine edge set at load <= 1/2 before the batch; on overflow
-    // grow it from the output keys (which include the partial appends of the
-    // failed launch) and replay the launch, which skips edges already present
-    const uint64_t batch_lo = n_out;
-    uint64_t n_keys = n_out;
-    int guard = 0;
-    for (;;) {
-      if (n_keys * 2 > g.et_cap || c->et_fail) {
-        if (++guard > 40) return ip_fail(ctx, IP_ENOMEM, "edge table cannot grow");
-        IP_TRY(zero_field(ctx, (unsigned long long *)&ctx->ctr_dev->et_fail));
-        IP_TRY(g.reserve(ctx, pow2_at_least(std::max<uint64_t>(n_keys * 4, g.et_cap * 2)), n_keys));
-        ++f.regrows;
-      }
-      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
-      IP_TRY(tx.start(ctx, &st.ms_expand));
-      hipLaunchKernelGGL((batch_edges_kernel<D>), dim3(grid_for(nb * NE)), dim3(kBlock), 0, ctx->stream, p->fine,
-                         p->coarse, LB, k, sig, nb, (const uint64_t *)tpts, NP, (const uint32_t *)tedge, NE, pslot,
-                         f.vt, g.et, g.et_cap - 1, g.keys, ctx->ctr_dev);
-      IP_TRY_HIP(ctx, hipGetLastError());
-      IP_TRY(tx.stop(ctx));
-      IP_TRY(read_ctr(ctx));
-      if (!c->et_fail) break;
-      n_keys = c->n_out;
-    }
-    st.n_template_edges += (int64_t)(nb * (uint64_t)NE);
-    const uint64_t lo = batch_lo, hi = c->n_out;
-    if (log_on())
-      fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu new vertices, %llu cells so far\n",
-              (long long)batches, (unsigned long long)nb, (unsigned long long)c->n_eval, (unsigned long long)hi);
-    if (hi > pts_ld) {
-      // grow the SoA point buffer, copying the columns
-      const uint64_t nld = std::max<uint64_t>(hi, pts_ld * 2);
-      double *np_ = nullptr;
-      IP_TRY(alloc(ctx, (void **)&np_, nld * D * 8));
-      if (pts && lo) {
-        for (int j = 0; j < D; ++j)
-          IP_TRY_HIP(ctx, hipMemcpyAsync(np_ + (uint64_t)j * nld, pts + (uint64_t)j * pts_ld, lo * 8,
-                                         hipMemcpyDeviceToDevice, ctx->stream));
-      }
-      IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-      if (pts) release(ctx, pts);
-      pts = np_;
-      pts_ld = nld;
-    }
-    if (hi > lo) {
-      uint64_t *redo = nullptr;
-      if (cert) {
-        IP_TRY(ip_ensure(ctx, ctx->scratch, (hi - lo) * 8));
-        IP_TRY(ip_ensure(ctx, ctx->fb_list, std::max<uint64_t>(vcap, 2 * (hi - lo) + 64) * 4));
-        f.fb = (uint32_t *)ctx->fb_list.p;
-        redo = (uint64_t *)ctx->scratch.p;
-        IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
-        IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_fb));
-      }
-      IP_TRY(tp.start(ctx, &st.ms_points));
-      hipLaunchKernelGGL((batch_points_kernel<D, false>), dim3(grid_for(hi - lo)), dim3(kBlock), 0, ctx->stream,
-                         p->fine, g.keys, lo, hi, f.vt, vcap - 1, pts, (int64_t)pts_ld, cert, (const float *)f.vb,
-                         p->poly, redo, f.fb, ctx->ctr_dev);
-      IP_TRY_HIP(ctx, hipGetLastError());
-      IP_TRY(tp.stop(ctx));
-      if (cert) {
-        IP_TRY(read_ctr(ctx));
-        const uint64_t nredo = ctx->ctr_host->n_aux, nfb = ctx->ctr_host->n_fb;
-        if (nredo) {
-          IP_TRY(launch_feval64(ctx, p, p->fine, f.fb, nfb, f.vt));
-          IP_TRY(launch_set_vb(ctx, f.fb, nfb, f.vb, -1.0f));
-          hipLaunchKernelGGL((batch_points_kernel<D, true>), dim3(grid_for(nredo)), dim3(kBlock), 0, ctx->stream,
-                             p->fine, g.keys, (uint64_t)0, nredo, f.vt, vcap - 1, pts, (int64_t)pts_ld, true,
-                             (const float *)f.vb, p->poly, redo, f.fb, ctx->ctr_dev);
-          IP_TRY_HIP(ctx, hipGetLastError());
-          f.n_fallback += (int64_t)nfb;
-        }
-      }
-    }
-    n_out = hi;
-  }
-  IP_TRY(tf.flush(ctx));
-  IP_TRY(tx.flush(ctx));
-  IP_TRY(tp.flush(ctx));
-  release(ctx, tpts);
-  release(ctx, tedge);
-  release(ctx, sig_list);
-  if (rc != IP_OK) {
-    if (pts) release(ctx, pts);
-    return rc;
-  }
-  if (!pts) IP_TRY(alloc(ctx, (void **)&pts, 8 * D));
-  res->d = D;
-  res->B = p->fine.B;
-  for (int j = 0; j < 8; ++j) res->vmin[j] = p->fine.vmin[j];
-  res->n = (int64_t)n_out;
-  res->keys = g.take_keys();
-  res->pts = pts;
-  res->ld = (int64_t)(pts_ld ? pts_ld : 1);
-  st.n_cells = (int64_t)n_out;
-  st.n_batches = batches;
-  st.regrows += s.regrows + f.regrows;
-  st.n_fallback = s.n_fallback + f.n_fallback;
-  st.n_settled64 = s.n_settled64 + f.n_settled64;
-  return IP_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  st.regrows += s.regrows;
+  st.n_fallback += s.n_fallback;
+  st.n_settled64 += s.n_settled64;
+  return rc;
 }
 
 // Points of OUT[0 .. n) into keys / pts; in FP32 mode the edges whose point

@@ -56,7 +56,9 @@ class ip_stats(C.Structure):
                 ("n_cofaces", C.c_int64), ("n_sigma", C.c_int64), ("n_batches", C.c_int64),
                 ("n_template_edges", C.c_int64), ("levels", C.c_int32), ("regrows", C.c_int32),
                 ("ms_total", C.c_double), ("ms_feval", C.c_double), ("ms_expand", C.c_double),
-                ("ms_points", C.c_double), ("ms_check", C.c_double)]
+                ("ms_points", C.c_double), ("ms_check", C.c_double), ("ms_subdivide", C.c_double),
+                ("subdivide_launches", C.c_int64), ("n_edge_hits", C.c_int64),
+                ("n_coarse_edges", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +93,9 @@ _sig = {
     "ip_cells_stats": (C.c_int, [_vp, _P(ip_stats)]),
     "ip_cells_download": (C.c_int, [_vp, _vp, _ip, C.POINTER(C.c_uint32), _dp]),
     "ip_cells_points": (C.c_int, [_vp, _P(_vp), _P(C.c_int64)]),
+    "ip_cells_digest": (C.c_int, [_vp, _vp, C.POINTER(C.c_uint64)]),
+    "ip_cells_gather": (C.c_int, [_vp, _vp, C.POINTER(C.c_int64), C.c_int64, _ip, C.POINTER(C.c_uint32), _dp,
+                                  C.POINTER(C.c_uint8)]),
     "ip_cells_free": (None, [_vp]),
     "ip_check": (C.c_int, [_vp, _P(ip_scene), _vp, C.c_int64, C.c_int64, _vp]),
     "ip_check_cells": (C.c_int, [_vp, _vp, _P(ip_scene), _P(C.c_int64)]),
@@ -203,6 +208,27 @@ def ip_cells_download(ctx, cells, d):
     return v, m, p
 
 
+def ip_cells_digest(ctx, cells):
+    out = (C.c_uint64 * 2)()
+    _chk(ctx, _lib.ip_cells_digest(ctx, cells, out))
+    return int(out[0]), int(out[1])
+
+
+def ip_cells_gather(ctx, cells, d, idx, verdict=False):
+    """Rows idx of the cells: (v (n, d) int32, mask (n,), points (n, d),
+    verdicts (n,) uint8 or None)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    n = len(idx)
+    v = np.zeros((n, d), np.int32)
+    m = np.zeros(n, np.uint32)
+    p = np.zeros((n, d), np.float64)
+    vv = np.zeros(n, np.uint8) if verdict else None
+    _chk(ctx, _lib.ip_cells_gather(ctx, cells, idx.ctypes.data_as(C.POINTER(C.c_int64)), n, v.ctypes.data_as(_ip),
+                                   m.ctypes.data_as(C.POINTER(C.c_uint32)), p.ctypes.data_as(_dp),
+                                   vv.ctypes.data_as(C.POINTER(C.c_uint8)) if verdict else None))
+    return v, m, p, vv
+
+
 def ip_cells_points(cells):
     ptr = _vp()
     ld = C.c_int64()
@@ -303,6 +329,12 @@ class Cells:
     def check(self, scene):
         self.n_free = ip_check_cells(self.ctx.h, self.h, scene)
         return self.n_free
+
+    def digest(self):
+        return ip_cells_digest(self.ctx.h, self.h)
+
+    def gather(self, idx, verdict=False):
+        return ip_cells_gather(self.ctx.h, self.h, self.d, idx, verdict)
 
     def download_check(self):
         return ip_cells_download_check(self.ctx.h, self.h, self.d, self.n_free)

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 from paper_2406_04795_amd import inputs as I
-from test_gpu_trace import BATCH_CASES, CASES, trace
+from test_gpu_trace import BATCH_CASES, CASES, oracle_batch, trace
 
 pytestmark = pytest.mark.gpu
 
@@ -60,16 +60,43 @@ def test_fp32_trace_equals_fp64_oracle(ip, ctx, name):
         assert st["n_fallback"] > 0
 
 
-@pytest.mark.parametrize("name", ["sphere_d3_k3", "cubic_d4_k4", "cubic_d6_k2"])
+@pytest.mark.parametrize("name", list(BATCH_CASES))
 def test_fp32_batch_equals_fp64_oracle(ip, ctx, name):
-    make, k = BATCH_CASES[name]
-    wl = make()
-    wl.k = k
-    ov, om, ns = O.trace_batch(wl, k=k)
+    # the fused subdivision: signs of every template point from the certified
+    # tiers, no vertex table
+    print(f"fp32 batch case {name}", flush=True)
+    wl, ov, om, ns, opts = oracle_batch(name)
     gv, gm, gpts, st = trace(ip, ctx, wl, precision=ip.IP_FP32_CERTIFY)
+    assert st["n_sigma"] == ns
+    assert len(gv) == len(ov) and np.array_equal(gv, ov) and np.array_equal(gm, om)
+    _check_points(gpts, opts)
+
+
+def test_fp32_batch_exact_zeros_take_canonical_tier(ip, ctx):
+    # f is exactly 0.0 at fine vertices on the sphere: those template points
+    # defer their coarse simplices to the canonical FP64 pass, and edges with
+    # such an end get their points from canonical values
+    wl = I.dyadic_sphere_case()
+    wl.k = 2
+    ov, om, ns = O.trace_batch(wl, k=2)
+    gv, gm, gpts, st = trace(ip, ctx, wl, precision=ip.IP_FP32_CERTIFY)
+    assert st["n_fallback"] > 0
     assert np.array_equal(gv, ov) and np.array_equal(gm, om)
     opts, _ = O.points(wl, ov, om)
     _check_points(gpts, opts)
+
+
+def test_fp32_batch_budget_invariance(ip, ctx):
+    make, k = BATCH_CASES["cubic_d4_k4"]
+    wl = make()
+    wl.k = k
+    big = trace(ip, ctx, wl, precision=ip.IP_FP32_CERTIFY)
+    # 4 bytes of workspace per coarse simplex: 1024 simplices per batch
+    small = trace(ip, ctx, wl, precision=ip.IP_FP32_CERTIFY, budget=4096)
+    ns = big[3]["n_sigma"]
+    assert small[3]["n_batches"] == (ns + 1023) // 1024 > 1
+    assert np.array_equal(big[0], small[0]) and np.array_equal(big[1], small[1])
+    assert np.array_equal(big[2].view(np.uint64), small[2].view(np.uint64))
 
 
 @pytest.mark.parametrize("which", ["random_d6", "stress_d5"])

@@ -5,6 +5,8 @@ Traced edge sets and collision verdicts must be identical; FP64 values
 on both sides and must agree bit for bit (the stated tolerance for FP64
 points is 1e-12 relative; these tests hold the stronger equality).
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -229,19 +231,27 @@ BATCH_CASES = {
 }
 
 
-@pytest.mark.parametrize("name", list(BATCH_CASES))
-def test_batch_trace_matches_oracle(ip, ctx, name):
+@functools.lru_cache(maxsize=None)
+def oracle_batch(name):
+    """Oracle batch trace and points of BATCH_CASES[name] (computed once per
+    session: the FP64 and FP32 parity tests share them)."""
     make, k = BATCH_CASES[name]
     wl = make()
     wl.k = k
-    print(f"batch case {name}", flush=True)
     ov, om, ns = O.trace_batch(wl, k=k)
+    opts, _ = O.points(wl, ov, om)
+    return wl, ov, om, ns, opts
+
+
+@pytest.mark.parametrize("name", list(BATCH_CASES))
+def test_batch_trace_matches_oracle(ip, ctx, name):
+    print(f"batch case {name}", flush=True)
+    wl, ov, om, ns, opts = oracle_batch(name)
     gv, gm, gpts, st = trace(ip, ctx, wl)
     assert len(ov) > 0
     assert st["n_sigma"] == ns
     assert len(gv) == len(ov), (len(gv), len(ov))
     assert np.array_equal(gv, ov) and np.array_equal(gm, om)
-    opts, _ = O.points(wl, ov, om)
     assert np.array_equal(gpts.view(np.uint64), opts.view(np.uint64))
 
 
