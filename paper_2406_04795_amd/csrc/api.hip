@@ -584,13 +584,7 @@ int ip_check_cells(ip_ctx *ctx, ip_cells *c, const ip_scene *scene, int64_t *n_f
   if (scene->n_joints != c->d) return ip_fail(ctx, IP_EINVAL, "scene joints must equal the dimension");
   IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
   if (!c->verdict) IP_TRY(ip_dalloc(ctx, (void **)&c->verdict, (size_t)(c->n ? c->n : 1)));
-  IP_TRY_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-  IP_TRY(ip_check_impl(ctx, scene, c->pts, c->n, c->ld, c->verdict));
-  IP_TRY_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-  IP_TRY(ip_compact_free_impl(ctx, c));
-  float ms = 0.0f;
-  IP_TRY_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-  c->st.ms_check = ms;
+  IP_TRY(ip_check_gather_impl(ctx, scene, c));
   if (n_free) *n_free = c->n_free;
   return IP_OK;
 }

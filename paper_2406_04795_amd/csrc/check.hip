@@ -173,57 +173,57 @@ __device__ __forceinline__ bool sphere_box(const double *c, double r, const doub
   return true;
 }
 
+// One lane per configuration.  GATHER: the free configurations (verdict 0)
+// are also appended to free_pts (SoA, column stride ld_free) through per-wave
+// LDS staging, one atomic per 128 free points, while their columns are still
+// in cache.
+template <bool GATHER>
 __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__restrict__ q, int64_t n, int64_t ld,
-                                                    uint8_t *__restrict__ verdict) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double T[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
-    bool hit = false;
-    for (int li = 0; li < S.nj && !hit; ++li) {
-      double s, c, A[12], R[12];
-      sincos_own(q[(int64_t)li * ld + i], &s, &c);
-      compose(T, S.joint_T + 12 * li, A);
-      rotation(S.joint_axis[li], s, c, R);
-      compose(A, R, T);
-      for (int a = S.lsph_off[li]; a < S.lsph_off[li + 1] && !hit; ++a) {
-        const double *sp = S.lsph + 4 * a;
-        double cw[3];
-        xform(T, sp, cw);
-        for (int b = 0; b < S.n_osph && !hit; ++b) hit = sphere_sphere(cw, sp[3], S.osph + 4 * b, S.osph[4 * b + 3]);
-        for (int b = 0; b < S.n_obox && !hit; ++b) hit = sphere_box(cw, sp[3], S.obox + 16 * b);
-      }
-      for (int a = S.lcap_off[li]; a < S.lcap_off[li + 1] && !hit; ++a) {
-        const double *cp = S.lcap + 8 * a;
-        double p0[3], p1[3];
-        xform(T, cp, p0);
-        xform(T, cp + 3, p1);
-        for (int b = 0; b < S.n_osph && !hit; ++b) hit = capsule_sphere(p0, p1, cp[6], S.osph + 4 * b, S.osph[4 * b + 3]);
-      }
-    }
-    verdict[i] = hit ? 1 : 0;
-  }
-}
-
-// Gather the free (verdict 0) points: indices staged per wave in LDS, one
-// atomic per 128 free points, then the columns are copied.
-__global__ __launch_bounds__(256) void gather_free_kernel(const uint8_t *verdict, const double *pts, int64_t n,
-                                                          int64_t ld, int d, double *free_pts, int64_t ld_free,
-                                                          unsigned long long *count) {
+                                                    uint8_t *__restrict__ verdict, double *free_pts,
+                                                    int64_t ld_free, unsigned long long *count) {
   constexpr int kStage = 128;
-  __shared__ uint32_t st[4][kStage];
+  __shared__ uint32_t st[GATHER ? 4 : 1][GATHER ? kStage : 1];
   const int wib = threadIdx.x >> 6;
   int sn = 0;
+  const int d = S.nj;
   auto put = [&](unsigned long long pos, uint32_t i) {
-    for (int j = 0; j < d; ++j) free_pts[(int64_t)j * ld_free + (int64_t)pos] = pts[(int64_t)j * ld + (int64_t)i];
+    for (int j = 0; j < d; ++j) free_pts[(int64_t)j * ld_free + (int64_t)pos] = q[(int64_t)j * ld + (int64_t)i];
   };
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t rounds = (n + stride - 1) / stride;
   for (int64_t it = 0; it < rounds; ++it) {
     const int64_t i = start + it * stride;
-    const bool fr = i < n && verdict[i] == 0;
-    stage_put<kStage>(st[wib], sn, fr, (uint32_t)i, put, count);
+    bool hit = false;
+    if (i < n) {
+      double T[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+      for (int li = 0; li < S.nj && !hit; ++li) {
+        double s, c, A[12], R[12];
+        sincos_own(q[(int64_t)li * ld + i], &s, &c);
+        compose(T, S.joint_T + 12 * li, A);
+        rotation(S.joint_axis[li], s, c, R);
+        compose(A, R, T);
+        for (int a = S.lsph_off[li]; a < S.lsph_off[li + 1] && !hit; ++a) {
+          const double *sp = S.lsph + 4 * a;
+          double cw[3];
+          xform(T, sp, cw);
+          for (int b = 0; b < S.n_osph && !hit; ++b) hit = sphere_sphere(cw, sp[3], S.osph + 4 * b, S.osph[4 * b + 3]);
+          for (int b = 0; b < S.n_obox && !hit; ++b) hit = sphere_box(cw, sp[3], S.obox + 16 * b);
+        }
+        for (int a = S.lcap_off[li]; a < S.lcap_off[li + 1] && !hit; ++a) {
+          const double *cp = S.lcap + 8 * a;
+          double p0[3], p1[3];
+          xform(T, cp, p0);
+          xform(T, cp + 3, p1);
+          for (int b = 0; b < S.n_osph && !hit; ++b)
+            hit = capsule_sphere(p0, p1, cp[6], S.osph + 4 * b, S.osph[4 * b + 3]);
+        }
+      }
+      verdict[i] = hit ? 1 : 0;
+    }
+    if (GATHER) stage_put<kStage>(st[wib], sn, i < n && !hit, (uint32_t)i, put, count);
   }
-  stage_flush(st[wib], sn, put, count);
+  if (GATHER) stage_flush(st[wib], sn, put, count);
 }
 
 int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
@@ -330,12 +330,17 @@ int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64
   if (n == 0) return IP_OK;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(check_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, q_dev, n, ld, verdict_dev);
+  hipLaunchKernelGGL(check_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, q_dev, n, ld,
+                     verdict_dev, (double *)nullptr, (int64_t)0, (unsigned long long *)nullptr);
   IP_TRY_HIP(ctx, hipGetLastError());
   return IP_OK;
 }
 
-int ip_compact_free_impl(ip_ctx *ctx, ip_cells *c) {
+// Verdicts of every cell plus the compaction of the free points, in one
+// pass over the points.
+int ip_check_gather_impl(ip_ctx *ctx, const ip_scene *scene, ip_cells *c) {
+  SceneDev S;
+  IP_TRY(upload_scene(ctx, scene, &S));
   if (c->free_pts) {
     ip_dfree(ctx, c->free_pts);
     c->free_pts = nullptr;
@@ -344,15 +349,20 @@ int ip_compact_free_impl(ip_ctx *ctx, ip_cells *c) {
   if (n >= (1ll << 32)) return ip_fail(ctx, IP_EINVAL, "more than 2^32 cells in one check");
   IP_TRY(ip_dalloc(ctx, (void **)&c->free_pts, sizeof(double) * (size_t)(n ? n : 1) * c->d));
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+  IP_TRY_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
   if (n) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(gather_free_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, c->verdict, c->pts, n,
-                       c->ld, c->d, c->free_pts, n, &ctx->ctr_dev->n_aux);
+    hipLaunchKernelGGL(check_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, (const double *)c->pts,
+                       n, c->ld, c->verdict, c->free_pts, n, &ctx->ctr_dev->n_aux);
     IP_TRY_HIP(ctx, hipGetLastError());
   }
+  IP_TRY_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
   IP_TRY_HIP(ctx, hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream));
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  float ms = 0.0f;
+  IP_TRY_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  c->st.ms_check = ms;
   c->n_free = (int64_t)ctx->ctr_host->n_aux;
   return IP_OK;
 }

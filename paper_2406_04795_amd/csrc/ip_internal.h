@@ -510,7 +510,7 @@ int ip_feval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_
                   double *f_dev, double *bound_dev);
 int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n, int64_t ld,
                   uint8_t *verdict_dev);
-int ip_compact_free_impl(ip_ctx *ctx, ip_cells *c);
+int ip_check_gather_impl(ip_ctx *ctx, const ip_scene *scene, ip_cells *c);
 
 // f evaluation of the vertices listed in `list` (slots of the vertex table);
 // results go into vt_vals[slot].  Defined in feval.hip.

@@ -1045,7 +1045,8 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const uint64_t n_waves = ((uint64_t)gridDim.x * kBlock) >> 6;
   for (uint64_t it = wave; it < n; it += n_waves) {
-    const uint64_t s = MODE == 0 ? it : (uint64_t)list[it];
+    // MODE 0 and 3 walk sig[0 .. n); MODE 1 and 2 walk the deferred list
+    const uint64_t s = (MODE == 0 || MODE == 3) ? it : (uint64_t)list[it];
     int32_t v[D], w[D];
     sig_unpack<D>(Lc, sig[s], LB, v, w);
     bool unsettled = false;
