@@ -269,7 +269,7 @@ def main():
                 "phases_ms": {"trace": phase(st, "ms_total"), "search": phase(st, "ms_expand"),
                               "subdivide": phase(st, "ms_subdivide"), "feval": phase(st, "ms_feval"),
                               "points": phase(st, "ms_points"), "check": phase(st, "ms_check")},
-                "edge_hits": s["n_edge_hits"],
+                "edge_hits": s["n_edge_hits"], "edge_set_probes": s["n_shared_probes"],
                 "vertices_evaluated": s["n_vertices"], "fp64_canonical_evals": s["n_fallback"],
                 "settled_by_fp64_monomial": s["n_settled64"]}
 

@@ -136,6 +136,10 @@ typedef struct {
   int64_t n_edge_hits;   /* batch mode: intersecting (coarse simplex, template
                             edge) pairs, duplicates across simplices included */
   int64_t n_coarse_edges; /* batch mode: intersecting edges of the coarse trace */
+  int64_t n_shared_probes; /* batch mode: intersecting template edges on a coarse
+                              face with no traced coarse edge, which go through
+                              the global edge set (all others are emitted once,
+                              by the canonical coarse simplex of their face) */
 } ip_stats;
 
 /* Create a context on HIP device `device`; work is issued on `hip_stream`

@@ -9,6 +9,8 @@
 // written, own sine/cosine: Cody-Waite reduction by pi/2 and Taylor
 // polynomials), so they are reproducible bit for bit on any IEEE-754 FP64
 // implementation that follows the same order.
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -28,6 +30,9 @@ struct SceneDev {
   int32_t n_osph, n_obox;
   const double *osph;         // [cx cy cz r]
   const double *obox;         // [T(12) l(3) pad] (16 doubles)
+  const double *lbound;       // per link [cx cy cz R]: a ball in the link frame
+                              // holding all of the link's geometry (R < 0: none)
+  double eps;                 // margin of the culling test
 };
 
 #define PIO2_A 1.5707963267341256
@@ -173,57 +178,179 @@ __device__ __forceinline__ bool sphere_box(const double *c, double r, const doub
   return true;
 }
 
-// One lane per configuration.  GATHER: the free configurations (verdict 0)
-// are also appended to free_pts (SoA, column stride ld_free) through per-wave
-// LDS staging, one atomic per 128 free points, while their columns are still
-// in cache.
-template <bool GATHER>
+// Culling: can a ball (centre c, radius R) reach obstacle b?  A false
+// answer proves that every sphere or capsule inside the ball misses the
+// obstacle by more than the margin eps, far beyond the rounding of the exact
+// predicates, so skipping their tests leaves every verdict unchanged.
+__device__ __forceinline__ bool ball_near_sphere(const double *c, double R, const double *o) {
+  const double rr = R + o[3];
+  return !(sq3(c[0] - o[0], c[1] - o[1], c[2] - o[2]) > rr * rr);
+}
+
+__device__ __forceinline__ bool ball_near_box(const double *c, double R, const double *B) {
+  const double dx = c[0] - B[3], dy = c[1] - B[7], dz = c[2] - B[11];
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double g = fabs(fma(B[8 + i], dz, fma(B[4 + i], dy, B[i] * dx))) - 0.5 * B[12 + i];
+    if (g > 0.0) s = fma(g, g, s);
+  }
+  return !(s > R * R);
+}
+
+// OR over the wave, returned as a wave-uniform value (so that obstacle
+// indices derived from it address the scene with scalar loads).
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+#pragma unroll
+  for (int off = 32; off; off >>= 1) x |= __shfl_xor(x, off, 64);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// One lane per configuration: forward kinematics link by link; per link,
+// the obstacles its bounding ball can reach (a bit mask per 64 obstacles),
+// and the exact predicates only for those pairs.  Loops run over the scene
+// uniformly across the wave, so the scene is read with scalar loads; the
+// wave stops early once every lane has a hit.
 __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__restrict__ q, int64_t n, int64_t ld,
-                                                    uint8_t *__restrict__ verdict, double *free_pts,
-                                                    int64_t ld_free, unsigned long long *count) {
-  constexpr int kStage = 128;
-  __shared__ uint32_t st[GATHER ? 4 : 1][GATHER ? kStage : 1];
-  const int wib = threadIdx.x >> 6;
-  int sn = 0;
+                                                    uint8_t *__restrict__ verdict) {
   const int d = S.nj;
-  auto put = [&](unsigned long long pos, uint32_t i) {
-    for (int j = 0; j < d; ++j) free_pts[(int64_t)j * ld_free + (int64_t)pos] = q[(int64_t)j * ld + (int64_t)i];
-  };
+  const int nobs = S.n_osph + S.n_obox;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t rounds = (n + stride - 1) / stride;
   for (int64_t it = 0; it < rounds; ++it) {
     const int64_t i = start + it * stride;
-    bool hit = false;
-    if (i < n) {
-      double T[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
-      for (int li = 0; li < S.nj && !hit; ++li) {
-        double s, c, A[12], R[12];
-        sincos_own(q[(int64_t)li * ld + i], &s, &c);
-        compose(T, S.joint_T + 12 * li, A);
-        rotation(S.joint_axis[li], s, c, R);
-        compose(A, R, T);
-        for (int a = S.lsph_off[li]; a < S.lsph_off[li + 1] && !hit; ++a) {
+    const bool valid = i < n;
+    const int64_t ii = valid ? i : n - 1;
+    bool hit = !valid;
+    double T[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+    for (int li = 0; li < d; ++li) {
+      double sn_, cs_, A[12], Rm[12];
+      sincos_own(q[(int64_t)li * ld + ii], &sn_, &cs_);
+      compose(T, S.joint_T + 12 * li, A);
+      rotation(S.joint_axis[li], sn_, cs_, Rm);
+      compose(A, Rm, T);
+      const double *lb = S.lbound + 4 * li;
+      if (!(lb[3] >= 0.0)) continue;
+      double cb[3];
+      xform(T, lb, cb);
+      const double Rb = lb[3] + S.eps;
+      for (int b0 = 0; b0 < nobs; b0 += 64) {
+        const int nb = nobs - b0 < 64 ? nobs - b0 : 64;
+        uint64_t near = 0;
+        for (int b = 0; b < nb; ++b) {
+          const int o = b0 + b;
+          const bool nr = o < S.n_osph ? ball_near_sphere(cb, Rb, S.osph + 4 * o)
+                                       : ball_near_box(cb, Rb, S.obox + 16 * (o - S.n_osph));
+          near |= (uint64_t)nr << b;
+        }
+        if (hit) near = 0;
+        const uint64_t any = wave_or64(near);
+        if (!any) continue;
+        for (int a = S.lsph_off[li]; a < S.lsph_off[li + 1]; ++a) {
           const double *sp = S.lsph + 4 * a;
           double cw[3];
           xform(T, sp, cw);
-          for (int b = 0; b < S.n_osph && !hit; ++b) hit = sphere_sphere(cw, sp[3], S.osph + 4 * b, S.osph[4 * b + 3]);
-          for (int b = 0; b < S.n_obox && !hit; ++b) hit = sphere_box(cw, sp[3], S.obox + 16 * b);
+          for (uint64_t m = any; m; m &= m - 1) {
+            const int b = __ffsll((long long)m) - 1;
+            if (!((near >> b) & 1ull) || hit) continue;
+            const int o = b0 + b;
+            hit = o < S.n_osph ? sphere_sphere(cw, sp[3], S.osph + 4 * o, S.osph[4 * o + 3])
+                               : sphere_box(cw, sp[3], S.obox + 16 * (o - S.n_osph));
+          }
         }
-        for (int a = S.lcap_off[li]; a < S.lcap_off[li + 1] && !hit; ++a) {
+        for (int a = S.lcap_off[li]; a < S.lcap_off[li + 1]; ++a) {
           const double *cp = S.lcap + 8 * a;
           double p0[3], p1[3];
           xform(T, cp, p0);
           xform(T, cp + 3, p1);
-          for (int b = 0; b < S.n_osph && !hit; ++b)
-            hit = capsule_sphere(p0, p1, cp[6], S.osph + 4 * b, S.osph[4 * b + 3]);
+          for (uint64_t m = any; m; m &= m - 1) {
+            const int b = __ffsll((long long)m) - 1;
+            const int o = b0 + b;
+            if (!((near >> b) & 1ull) || hit || o >= S.n_osph) continue;
+            hit = capsule_sphere(p0, p1, cp[6], S.osph + 4 * o, S.osph[4 * o + 3]);
+          }
         }
       }
-      verdict[i] = hit ? 1 : 0;
+      if (__ballot(!hit) == 0) break;
     }
-    if (GATHER) stage_put<kStage>(st[wib], sn, i < n && !hit, (uint32_t)i, put, count);
+    if (valid) verdict[i] = hit ? 1 : 0;
   }
-  if (GATHER) stage_flush(st[wib], sn, put, count);
+}
+
+// Stable compaction of the free (verdict 0) points, by tiles of kTile cells:
+// count per tile, exclusive scan of the counts, then each tile writes its
+// free points in cell order at its offset.
+constexpr int kTile = 4096;
+
+__global__ __launch_bounds__(256) void free_count_kernel(const uint8_t *__restrict__ verdict, int64_t n,
+                                                         uint32_t *__restrict__ cnt) {
+  __shared__ uint32_t part[4];
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  uint32_t c = 0;
+  for (int k = 0; k < kTile / 256; ++k) {
+    const int64_t i = base + k * 256 + threadIdx.x;
+    c += (i < n && verdict[i] == 0) ? 1u : 0u;
+  }
+  for (int off = 32; off; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// Exclusive scan of cnt[0 .. m) into off, total into *total (one block).
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(const uint32_t *__restrict__ cnt, int64_t m,
+                                                          uint64_t *__restrict__ off,
+                                                          unsigned long long *__restrict__ total) {
+  __shared__ unsigned long long wsum[16];
+  __shared__ unsigned long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t b = 0; b < m; b += 1024) {
+    const int64_t i = b + threadIdx.x;
+    const unsigned long long v = i < m ? cnt[i] : 0ull;
+    unsigned long long x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    unsigned long long before = carry;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    if (i < m) off[i] = before + x - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = before + x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void free_scatter_kernel(const uint8_t *__restrict__ verdict,
+                                                           const double *__restrict__ pts, int64_t n, int64_t ld, int d,
+                                                           const uint64_t *__restrict__ off,
+                                                           double *__restrict__ free_pts, int64_t ld_free) {
+  __shared__ uint32_t wcount[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  uint64_t pos0 = off[blockIdx.x];
+  for (int k = 0; k < kTile / 256; ++k) {
+    const int64_t i = base + k * 256 + threadIdx.x;
+    const bool fr = i < n && verdict[i] == 0;
+    const uint64_t bal = __ballot(fr);
+    if (lane == 0) wcount[wv] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint64_t pos = pos0;
+    for (int w = 0; w < wv; ++w) pos += wcount[w];
+    pos += (uint64_t)__popcll(bal & ((1ull << lane) - 1ull));
+    if (fr)
+      for (int j = 0; j < d; ++j) free_pts[(int64_t)j * ld_free + (int64_t)pos] = pts[(int64_t)j * ld + i];
+    pos0 += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    __syncthreads();
+  }
 }
 
 int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
@@ -279,6 +406,48 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
     for (int j = 0; j < 3; ++j) obox[16 * b + 12 + j] = sc->obox_l[3 * b + j];
     obox[16 * b + 15] = 0.0;
   }
+  // per-link bounding balls (link frame): centre at the middle of the
+  // geometry's extent, radius covering every sphere and capsule of the link
+  std::vector<double> lbound(4 * (size_t)nj, 0.0);
+  double scale = 1.0;
+  for (int li = 0; li < nj; ++li) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    bool any = false;
+    auto grow = [&](const double *pp) {
+      for (int j = 0; j < 3; ++j) {
+        lo[j] = std::min(lo[j], pp[j]);
+        hi[j] = std::max(hi[j], pp[j]);
+      }
+      any = true;
+    };
+    for (int a = lsph_off[li]; a < lsph_off[li + 1]; ++a) grow(&lsph[4 * a]);
+    for (int a = lcap_off[li]; a < lcap_off[li + 1]; ++a) {
+      grow(&lcap[8 * a]);
+      grow(&lcap[8 * a + 3]);
+    }
+    if (!any) {
+      lbound[4 * li + 3] = -1.0;
+      continue;
+    }
+    double c[3], R = 0.0;
+    for (int j = 0; j < 3; ++j) c[j] = 0.5 * (lo[j] + hi[j]);
+    auto dist = [&](const double *pp) {
+      return std::sqrt((pp[0] - c[0]) * (pp[0] - c[0]) + (pp[1] - c[1]) * (pp[1] - c[1]) +
+                       (pp[2] - c[2]) * (pp[2] - c[2]));
+    };
+    for (int a = lsph_off[li]; a < lsph_off[li + 1]; ++a) R = std::max(R, dist(&lsph[4 * a]) + lsph[4 * a + 3]);
+    for (int a = lcap_off[li]; a < lcap_off[li + 1]; ++a)
+      R = std::max(R, std::max(dist(&lcap[8 * a]), dist(&lcap[8 * a + 3])) + lcap[8 * a + 6]);
+    for (int j = 0; j < 3; ++j) {
+      lbound[4 * li + j] = c[j];
+      scale = std::max(scale, std::fabs(c[j]) + R);
+    }
+    lbound[4 * li + 3] = R * (1.0 + 1e-12);
+  }
+  for (int i = 0; i < 12 * nj; ++i) scale = std::max(scale, std::fabs(sc->joint_T[i]));
+  for (double x : osph) scale = std::max(scale, std::fabs(x));
+  for (int b = 0; b < sc->n_obox; ++b)
+    for (int j = 0; j < 15; ++j) scale = std::max(scale, std::fabs(obox[16 * b + j]));
   // one contiguous blob: doubles first, then ints
   std::vector<double> blob;
   auto put = [&](const double *p, size_t n) {
@@ -291,6 +460,7 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   size_t o_lc = put(lcap.data(), lcap.size());
   size_t o_os = put(osph.data(), osph.size());
   size_t o_ob = put(obox.data(), obox.size());
+  size_t o_lb = put(lbound.data(), lbound.size());
   size_t n_dbl = blob.size();
   std::vector<int32_t> ints;
   ints.insert(ints.end(), sc->joint_axis, sc->joint_axis + nj);
@@ -318,6 +488,10 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   out->n_obox = sc->n_obox;
   out->osph = db + o_os;
   out->obox = db + o_ob;
+  out->lbound = db + o_lb;
+  // the geometry is summed over at most a few dozen terms of size `scale`
+  // (reach times the chain length): rounding stays below 1e-13 * scale
+  out->eps = 1e-9 * scale * (double)(nj + 1);
   return IP_OK;
 }
 
@@ -330,14 +504,12 @@ int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64
   if (n == 0) return IP_OK;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(check_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, q_dev, n, ld,
-                     verdict_dev, (double *)nullptr, (int64_t)0, (unsigned long long *)nullptr);
+  hipLaunchKernelGGL(check_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, q_dev, n, ld, verdict_dev);
   IP_TRY_HIP(ctx, hipGetLastError());
   return IP_OK;
 }
 
-// Verdicts of every cell plus the compaction of the free points, in one
-// pass over the points.
+// Verdicts of every cell, then the stable compaction of the free points.
 int ip_check_gather_impl(ip_ctx *ctx, const ip_scene *scene, ip_cells *c) {
   SceneDev S;
   IP_TRY(upload_scene(ctx, scene, &S));
@@ -346,20 +518,34 @@ int ip_check_gather_impl(ip_ctx *ctx, const ip_scene *scene, ip_cells *c) {
     c->free_pts = nullptr;
   }
   const int64_t n = c->n;
-  if (n >= (1ll << 32)) return ip_fail(ctx, IP_EINVAL, "more than 2^32 cells in one check");
   IP_TRY(ip_dalloc(ctx, (void **)&c->free_pts, sizeof(double) * (size_t)(n ? n : 1) * c->d));
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  void *tiles = nullptr;
+  IP_TRY(ip_dalloc(ctx, &tiles, (size_t)(ntiles ? ntiles : 1) * 12));
+  uint64_t *off = (uint64_t *)tiles;
+  uint32_t *cnt = (uint32_t *)(off + (ntiles ? ntiles : 1));
   IP_TRY_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
   if (n) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(check_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, (const double *)c->pts,
-                       n, c->ld, c->verdict, c->free_pts, n, &ctx->ctr_dev->n_aux);
-    IP_TRY_HIP(ctx, hipGetLastError());
+    hipLaunchKernelGGL(check_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, (const double *)c->pts, n,
+                       c->ld, c->verdict);
+    hipLaunchKernelGGL(free_count_kernel, dim3((unsigned)ntiles), dim3(256), 0, ctx->stream,
+                       (const uint8_t *)c->verdict, n, cnt);
+    hipLaunchKernelGGL(scan_tiles_kernel, dim3(1), dim3(1024), 0, ctx->stream, (const uint32_t *)cnt, ntiles, off,
+                       &ctx->ctr_dev->n_aux);
+    hipLaunchKernelGGL(free_scatter_kernel, dim3((unsigned)ntiles), dim3(256), 0, ctx->stream,
+                       (const uint8_t *)c->verdict, (const double *)c->pts, n, c->ld, c->d, (const uint64_t *)off,
+                       c->free_pts, n);
   }
-  IP_TRY_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-  IP_TRY_HIP(ctx, hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream));
-  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev1, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  ip_dfree(ctx, tiles);
+  if (e != hipSuccess) return ip_hip(ctx, e, "ip_check_cells");
   float ms = 0.0f;
   IP_TRY_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   c->st.ms_check = ms;

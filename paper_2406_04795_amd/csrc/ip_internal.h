@@ -75,6 +75,8 @@ struct Counters {
   unsigned long long n_cert64;   // vertices settled by the FP64 monomial tier
   unsigned long long n_pts;      // template points evaluated (fused subdivision)
   unsigned long long n_unsettled;// template points left to the canonical tier
+  unsigned long long n_direct;   // owner-emitted fine edges (batch mode)
+  unsigned long long n_shared;   // intersecting template edges sent to the edge set
   unsigned int vt_fail;          // vertex-table insert found the table full
   unsigned int et_fail;          // edge-table insert found the table full
 };

@@ -989,59 +989,92 @@ __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo,
 }
 
 // ---------------------------------------------------------------------------
-// Fused subdivision for the FP32-certified mode (Sec. V-B, Fig. 6).
-// One wave per coarse simplex.  The wave decides the sign of f at every
-// template point with the certified monomial-basis evaluation, keeps the
-// signs in LDS, tests every template edge against them and inserts the
-// intersecting fine edges into the global edge set.  There is no vertex
-// table: a point shared by several coarse simplices is evaluated by each of
-// them, which costs fewer cycles than a hash probe into a table of hundreds
-// of millions of vertices.  Sign codes: 0 (f < 0), 1 (f >= 0), 2 (outside
-// the box), 3 (neither certified tier settles the sign).
-// MODE 0: simplices sig[0 .. n); a simplex with a code-3 point is appended
-//         to `defer` and skipped.
-// MODE 1: the deferred simplices: their code-3 points are inserted into the
-//         fallback vertex table fvt (new slots to eval_list).
-// MODE 2: the deferred simplices again, code-3 points taking the sign of the
-//         canonical FP64 value in fvt; then the edge pass.
-// MODE 3: vertex-table path (FP64 mode): the sign of template point p of
-//         simplex s is read from fvt[pslot[s * NP + p]].f (pslot ~0: outside
-//         the box); then the edge pass.
-// Dynamic LDS: template points (NP x 8 B), template edges (NE x 4 B), a sign
-// code byte per template point per wave, and the per-wave append stage.
+// Subdivision kernel (Sec. V-B, Fig. 6): one wave per coarse simplex.
+//
+// Sign codes.  The wave takes the sign of f at every template point, keeps
+// the signs in LDS as byte codes, then tests every template edge against
+// them.  Codes: 0 (f < 0), 1 (f >= 0), 2 (outside the box), 3 (neither
+// certified tier settles the sign).
+//   MODE 0: FP32-certified signs of sig[0 .. n) (no vertex table: a point
+//           shared by several coarse simplices is evaluated by each of them,
+//           which costs fewer cycles than a probe into a table of 10^8
+//           vertices); a simplex with a code-3 point goes to `defer`.
+//   MODE 1: the deferred simplices: their code-3 points are inserted into
+//           the fallback vertex table fvt (new slots to eval_list).
+//   MODE 2: the deferred simplices again, code-3 points taking the sign of
+//           the canonical FP64 value in fvt; then the edge pass.
+//   MODE 3: FP64 mode: the sign of template point p of simplex s is read
+//           from fvt[pslot[s * NP + p]].f (pslot ~0: outside the box).
+//
+// Ownership.  A fine edge lies in the relative interior of exactly one face
+// tau of the coarse simplex (vertices: the union of the supports of its
+// ends' barycentric coordinates, precomputed per template edge), and every
+// coarse n-simplex containing tau sees it.  If tau contains a traced coarse
+// edge, every n-coface of tau is in Sigma (they are n-cofaces of that edge),
+// so the edge is emitted only by the canonical n-coface of tau: the one
+// whose roots run in ascending order within each block of tau's partition.
+// Those edges go straight to the output list (out_d) with no dedup.  The
+// other intersecting edges go through the global edge set (et_keys), whose
+// new keys are appended to out_s.
+//
+// Dynamic LDS per block: two append stages per wave, the per-wave face masks
+// (traced / canonical, one bit per vertex subset), template points, template
+// edges and their faces, and the per-wave sign codes.
 // ---------------------------------------------------------------------------
 constexpr int kSubStage = 128;
+constexpr int kWaves = kBlock / 64;
 
 __host__ __device__ inline size_t sub_lds_bytes(int NP, int NE) {
   const size_t codes = ((size_t)NP + 7) & ~(size_t)7;
-  return (size_t)(kBlock / 64) * kSubStage * 8 + (size_t)NP * 8 + (size_t)NE * 4 + (size_t)(kBlock / 64) * codes;
+  return (size_t)kWaves * (2 * kSubStage + 8) * 8 + (size_t)NP * 8 + (size_t)NE * 5 + (size_t)kWaves * codes;
 }
+
+struct SubOut {
+  const VEnt *cvt;   // coarse vertex table (visited-edge masks of the coarse trace)
+  uint64_t cvt_mask;
+  uint64_t *et_keys;  // global edge set (edges without an owner)
+  uint64_t et_mask;
+  uint64_t *out_s;    // its keys in insertion order
+  uint64_t *out_d;    // owner-emitted keys
+  uint64_t dcap;      // capacity of out_d (appends past it are counted, not written)
+};
 
 template <int D, int P, int MODE>
 __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc, int LB, int k,
                                                            const uint64_t *__restrict__ sig,
                                                            const uint32_t *__restrict__ list, uint64_t n,
                                                            const uint64_t *__restrict__ tpts, int NP,
-                                                           const uint32_t *__restrict__ tedge, int NE, PolyDev Q,
+                                                           const uint32_t *__restrict__ tedge,
+                                                           const uint8_t *__restrict__ tface, int NE, PolyDev Q,
                                                            VEnt *fvt, uint64_t fvt_mask, uint32_t *eval_list,
-                                                           const uint32_t *__restrict__ pslot, uint64_t *et_keys,
-                                                           uint64_t et_mask, uint64_t *out, uint32_t *defer,
-                                                           Counters *ctr) {
+                                                           const uint32_t *__restrict__ pslot, SubOut so,
+                                                           uint32_t *defer, Counters *ctr) {
+  constexpr int NV = 1 << (D + 1);        // vertex subsets of a coarse simplex
+  constexpr int NVW = (NV + 63) / 64;     // 64-bit words per face mask
   extern __shared__ __align__(16) unsigned char smem[];
   const int wib = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int ncode = (NP + 7) & ~7;
-  uint64_t *stage = (uint64_t *)smem + (size_t)wib * kSubStage;
-  uint64_t *lpts = (uint64_t *)smem + (kBlock / 64) * kSubStage;
+  uint64_t *stage_s = (uint64_t *)smem + (size_t)wib * kSubStage;
+  uint64_t *stage_d = (uint64_t *)smem + (size_t)(kWaves + wib) * kSubStage;
+  uint64_t *fm = (uint64_t *)smem + (size_t)2 * kWaves * kSubStage + (size_t)wib * 8;
+  uint64_t *lpts = (uint64_t *)smem + (size_t)2 * kWaves * kSubStage + (size_t)kWaves * 8;
   uint32_t *ledge = (uint32_t *)(lpts + NP);
-  uint8_t *code = (uint8_t *)(ledge + NE) + (size_t)wib * ncode;
+  uint8_t *lface = (uint8_t *)(ledge + NE);
+  uint8_t *code = lface + NE + (size_t)wib * ncode;
   for (int i = threadIdx.x; i < NP; i += kBlock) lpts[i] = tpts[i];
   if (MODE != 1)
-    for (int i = threadIdx.x; i < NE; i += kBlock) ledge[i] = tedge[i];
+    for (int i = threadIdx.x; i < NE; i += kBlock) {
+      ledge[i] = tedge[i];
+      lface[i] = tface[i];
+    }
   __syncthreads();
-  int sn = 0;
-  auto put = [&](unsigned long long pos, uint64_t key) { out[pos] = key; };
-  unsigned long long hits = 0, n64 = 0, npts = 0, nuns = 0;
+  int sn = 0, snd = 0;
+  auto put_s = [&](unsigned long long pos, uint64_t key) { so.out_s[pos] = key; };
+  auto put_d = [&](unsigned long long pos, uint64_t key) {
+    if (pos < so.dcap) so.out_d[pos] = key;
+  };
+  unsigned long long hits = 0, shits = 0, n64 = 0, npts = 0, nuns = 0;
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const uint64_t n_waves = ((uint64_t)gridDim.x * kBlock) >> 6;
   for (uint64_t it = wave; it < n; it += n_waves) {
@@ -1097,41 +1130,114 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
       wave_lds_sync();
       continue;
     }
+    // traced coarse edges among the simplex's vertices: vertex i is
+    // v + 1_{w_0 .. w_{i-1}}, edge (i, j) for i < j has direction
+    // R = {w_i .. w_{j-1}} from its smaller end i; row i holds bit j when
+    // that edge is in the coarse trace
+    uint32_t row = 0;
+    if (lane <= D) {
+      int32_t cv[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) cv[q] = v[q];
+      for (int t = 0; t < lane; ++t) cv[w[t]] += 1;
+      if (vin_range<D>(Lc, cv)) {
+        const int64_t h = vt_find(so.cvt, so.cvt_mask, vpack<D>(Lc, cv));
+        if (h >= 0) {
+          const uint64_t m0 = so.cvt[h].m[0], m1 = so.cvt[h].m[1];
+          uint32_t R = 0;
+          for (int j = lane + 1; j <= D; ++j) {
+            R |= 1u << w[j - 1];
+            const uint64_t word = R < 64 ? m0 : m1;
+            if ((word >> (R & 63u)) & 1ull) row |= 1u << j;
+          }
+        }
+      }
+    }
+    uint32_t rows[D + 1];
+#pragma unroll
+    for (int i = 0; i <= D; ++i) rows[i] = (uint32_t)__shfl((int)row, i, 64);
+    // face masks over the vertex subsets V: traced (V holds a traced coarse
+    // edge) and canonical (this simplex is the canonical n-coface of V)
+#pragma unroll
+    for (int t = 0; t < NVW; ++t) {
+      const uint32_t V = (uint32_t)(lane + 64 * t);
+      bool trv = false, cnv = false;
+      if (V < (uint32_t)NV && V != 0u) {
+#pragma unroll
+        for (int i = 0; i <= D; ++i)
+          if (((V >> i) & 1u) && (rows[i] & V)) trv = true;
+        // blocks of V's partition: the roots after each vertex of V up to
+        // the next one, cyclically (root of step p: w_p for p < D, D for p = D)
+        const int start = __ffs((int)V) - 1;
+        int prev = -1;
+        cnv = true;
+        for (int q = 0; q <= D; ++q) {
+          int pidx = start + q;
+          if (pidx > D) pidx -= D + 1;
+          if ((V >> pidx) & 1u) prev = -1;
+          const int r = pidx < D ? w[pidx] : D;
+          if (r < prev) cnv = false;
+          prev = r;
+        }
+      }
+      const uint64_t bt = __ballot(trv), bc = __ballot(cnv);
+      if (lane == 0) {
+        fm[t] = bt;
+        fm[4 + t] = bc;
+      }
+    }
     wave_lds_sync();
     for (int e0 = 0; e0 < NE; e0 += 64) {
       const int e = e0 + lane;
-      bool is_new = false;
+      bool is_new = false, is_dir = false;
       uint64_t key = 0;
       if (e < NE) {
         const uint32_t te = ledge[e];
         const uint32_t ca = code[te & 0xfffu], cb = code[(te >> 12) & 0xfffu];
         if ((ca ^ cb) == 1u && (ca | cb) == 1u) {
           ++hits;
-          int32_t y[D];
-          template_point<D>(v, w, k, lpts[te & 0xfffu], y);
-          const uint32_t Rl = te >> 24;
-          uint32_t Rg = 0;
+          const uint32_t V = lface[e];
+          const bool tr = (fm[V >> 6] >> (V & 63u)) & 1ull;
+          const bool owner = (fm[4 + (V >> 6)] >> (V & 63u)) & 1ull;
+          if (!tr || owner) {
+            int32_t y[D];
+            template_point<D>(v, w, k, lpts[te & 0xfffu], y);
+            const uint32_t Rl = te >> 24;
+            uint32_t Rg = 0;
 #pragma unroll
-          for (int i = 0; i < D; ++i) Rg |= ((Rl >> i) & 1u) << w[i];
-          key = ekey<D>(Lf, y, Rg);
-          uint64_t slot;
-          const int ins = ht_insert(et_keys, et_mask, key, &slot);
-          if (ins == 1)
-            is_new = true;
-          else if (ins < 0)
-            atomicOr(&ctr->et_fail, 1u);
+            for (int i = 0; i < D; ++i) Rg |= ((Rl >> i) & 1u) << w[i];
+            key = ekey<D>(Lf, y, Rg);
+            if (tr) {
+              is_dir = true;
+            } else {
+              ++shits;
+              uint64_t slot;
+              const int ins = ht_insert(so.et_keys, so.et_mask, key, &slot);
+              if (ins == 1)
+                is_new = true;
+              else if (ins < 0)
+                atomicOr(&ctr->et_fail, 1u);
+            }
+          }
         }
       }
-      stage_put<kSubStage>(stage, sn, is_new, key, put, &ctr->n_out);
+      stage_put<kSubStage>(stage_s, sn, is_new, key, put_s, &ctr->n_out);
+      stage_put<kSubStage>(stage_d, snd, is_dir, key, put_d, &ctr->n_direct);
     }
     wave_lds_sync();
   }
-  if (MODE != 1) stage_flush(stage, sn, put, &ctr->n_out);
+  if (MODE != 1) {
+    stage_flush(stage_s, sn, put_s, &ctr->n_out);
+    stage_flush(stage_d, snd, put_d, &ctr->n_direct);
+  }
   if (hits) atomicAdd(&ctr->n_cof, hits);
+  if (shits) atomicAdd(&ctr->n_shared, shits);
   if (n64) atomicAdd(&ctr->n_cert64, n64);
   if (npts) atomicAdd(&ctr->n_pts, npts);
   if (nuns) atomicAdd(&ctr->n_unsettled, nuns);
 }
+
+__global__ void set_counter_kernel(unsigned long long *p, unsigned long long v) { *p = v; }
 
 // Ends of the listed edges as raw vertices: vraw[2r] = a, vraw[2r + 1] = b.
 template <int D>
@@ -1190,10 +1296,14 @@ __global__ void sub_redo_kernel(LatDev L, const uint64_t *keys, const uint64_t *
 // Local subdivision template (Sec. V-B, Eq. 2 read with >=): points u with
 // k >= u_0 >= ... >= u_{d-1} >= 0 and edges (u, R) whose other end u + 1_R
 // is inside too.  Points packed 8 bits per coordinate; edges packed as
-// (index a | index b << 12 | R << 24).
+// (index a | index b << 12 | R << 24).  face[e]: the vertices of the coarse
+// simplex whose barycentric weight is positive at either end of edge e
+// (Eq. 1: vertex 0 weighs k - u_0, vertex i in 1..d-1 weighs u_{i-1} - u_i,
+// vertex d weighs u_{d-1}), i.e. the smallest face holding the edge.
 struct Template {
   std::vector<uint64_t> pts;
   std::vector<uint32_t> edges;
+  std::vector<uint8_t> face;
 };
 
 Template make_template(int d, int k) {
@@ -1205,6 +1315,14 @@ Template make_template(int d, int k) {
     for (int i = 0; i + 1 < d; ++i)
       if (x[i] < x[i + 1]) return false;
     return x[d - 1] >= 0;
+  };
+  auto support = [&](const std::vector<int> &x) {
+    uint32_t m = 0;
+    if (x[0] < k) m |= 1u;
+    for (int i = 1; i < d; ++i)
+      if (x[i - 1] > x[i]) m |= 1u << i;
+    if (x[d - 1] > 0) m |= 1u << d;
+    return m;
   };
   for (;;) {
     if (inside(u)) P.push_back(u);
@@ -1230,6 +1348,7 @@ Template make_template(int d, int k) {
       if (!inside(y)) continue;
       int b = index_of(y);
       T.edges.push_back((uint32_t)a | ((uint32_t)b << 12) | (R << 24));
+      T.face.push_back((uint8_t)(support(P[a]) | support(y)));
     }
   return T;
 }
@@ -1239,45 +1358,6 @@ int lehmer_bits(int d) {
   while ((1 << b) < f) ++b;
   return b < 1 ? 1 : b;
 }
-
-// Batch-mode output: the global set of fine edge keys (ET, open addressing)
-// and the list of keys in insertion order; the list's capacity equals the
-// set's, since every key in the set was appended exactly once.
-struct BatchOut {
-  ip_ctx *ctx = nullptr;
-  uint64_t *et = nullptr;
-  uint64_t et_cap = 0;
-  uint64_t *keys = nullptr;
-  ~BatchOut() {
-    if (et) ip_dfree(ctx, et);
-    if (keys) ip_dfree(ctx, keys);
-  }
-  uint64_t *take_keys() {
-    uint64_t *k = keys;
-    keys = nullptr;
-    return k;
-  }
-  // Grow both to cap (power of two), keeping the first n keys.
-  int reserve(ip_ctx *ctx, uint64_t cap, uint64_t n) {
-    void *ne = nullptr, *nk = nullptr;
-    IP_TRY(alloc(ctx, &ne, cap * 8));
-    IP_TRY(alloc(ctx, &nk, cap * 8));
-    IP_TRY(fill(ctx, ne, cap, IP_EMPTY_KEY));
-    if (n) {
-      IP_TRY_HIP(ctx, hipMemcpyAsync(nk, keys, n * 8, hipMemcpyDeviceToDevice, ctx->stream));
-      hipLaunchKernelGGL(et_rebuild_keys_kernel, dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, (const uint64_t *)nk,
-                         n, (uint64_t *)ne, cap - 1, ctx->ctr_dev);
-      IP_TRY_HIP(ctx, hipGetLastError());
-    }
-    IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (et) ip_dfree(ctx, et);
-    if (keys) ip_dfree(ctx, keys);
-    et = (uint64_t *)ne;
-    keys = (uint64_t *)nk;
-    et_cap = cap;
-    return IP_OK;
-  }
-};
 
 // Grows the SoA point buffer (columns of length ld) to hold hi rows, keeping
 // the first lo rows.
@@ -1299,46 +1379,142 @@ int grow_points(ip_ctx *ctx, uint64_t lo, uint64_t hi, double *&pts, uint64_t &l
   return IP_OK;
 }
 
-// Runs `launch` (which inserts into the global edge set) until no insert
-// found the set full.  Before the first launch the set is grown to keep its
-// load at most 1/2; after an overflow it is grown from the output keys (which
-// include the partial appends of the failed launch) and the launch replayed,
-// which skips the edges already present.
+// Batch-mode output.  Owner-emitted keys (dkeys, capacity dcap) and the
+// global edge set for edges without an owner (et, open addressing, load
+// kept <= 1/2) with its keys in insertion order (skeys, capacity et_cap:
+// every key in the set was appended once).  FP64 mode keeps the points of
+// both lists too (dpts, spts, SoA with column strides dld, sld).
+struct BatchSink {
+  ip_ctx *ctx = nullptr;
+  uint64_t *et = nullptr, *skeys = nullptr, *dkeys = nullptr;
+  uint64_t et_cap = 0, dcap = 0;
+  double *dpts = nullptr, *spts = nullptr;
+  uint64_t dld = 0, sld = 0;
+  explicit BatchSink(ip_ctx *c) : ctx(c) {}
+  ~BatchSink() {
+    for (void *p : {(void *)et, (void *)skeys, (void *)dkeys, (void *)dpts, (void *)spts})
+      if (p) ip_dfree(ctx, p);
+  }
+  // Grow the set to cap (power of two), rebuilt from its first n keys.
+  int reserve_set(uint64_t cap, uint64_t n) {
+    void *ne = nullptr, *nk = nullptr;
+    IP_TRY(alloc(ctx, &ne, cap * 8));
+    IP_TRY(alloc(ctx, &nk, cap * 8));
+    IP_TRY(fill(ctx, ne, cap, IP_EMPTY_KEY));
+    if (n) {
+      IP_TRY_HIP(ctx, hipMemcpyAsync(nk, skeys, n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+      hipLaunchKernelGGL(et_rebuild_keys_kernel, dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, (const uint64_t *)nk,
+                         n, (uint64_t *)ne, cap - 1, ctx->ctr_dev);
+      IP_TRY_HIP(ctx, hipGetLastError());
+    }
+    IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (et) ip_dfree(ctx, et);
+    if (skeys) ip_dfree(ctx, skeys);
+    et = (uint64_t *)ne;
+    skeys = (uint64_t *)nk;
+    et_cap = cap;
+    return IP_OK;
+  }
+  // Grow the owner-emitted list to cap entries, keeping the first n.
+  int reserve_direct(uint64_t cap, uint64_t n) {
+    void *nk = nullptr;
+    IP_TRY(alloc(ctx, &nk, cap * 8));
+    if (n) IP_TRY_HIP(ctx, hipMemcpyAsync(nk, dkeys, n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (dkeys) ip_dfree(ctx, dkeys);
+    dkeys = (uint64_t *)nk;
+    dcap = cap;
+    return IP_OK;
+  }
+  SubOut sub_out(const VEnt *cvt, uint64_t cvt_mask) const {
+    return SubOut{cvt, cvt_mask, et, et_cap - 1, skeys, dkeys, dcap};
+  }
+  // Final output: the set keys (and FP64 points) appended after the owner
+  // keys; hands the key list over.
+  template <int D>
+  int assemble(uint64_t n_dir, uint64_t n_set, bool with_pts) {
+    const uint64_t n = n_dir + n_set;
+    if (n > dcap || !dkeys) IP_TRY(reserve_direct(std::max<uint64_t>(n, 1), n_dir));
+    if (n_set) IP_TRY_HIP(ctx, hipMemcpyAsync(dkeys + n_dir, skeys, n_set * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    if (with_pts) {
+      IP_TRY(grow_points<D>(ctx, n_dir, std::max<uint64_t>(n, 1), dpts, dld));
+      if (n_set)
+        for (int j = 0; j < D; ++j)
+          IP_TRY_HIP(ctx, hipMemcpyAsync(dpts + (uint64_t)j * dld + n_dir, spts + (uint64_t)j * sld, n_set * 8,
+                                         hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return IP_OK;
+  }
+};
+
+int set_counter(ip_ctx *ctx, unsigned long long *field, unsigned long long v) {
+  hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(1), 0, ctx->stream, field, v);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
+}
+
+// Runs `launch` (one subdivision launch) until it neither found the edge set
+// full nor overran the owner list.  Before the first launch the set is grown
+// to keep its load at most 1/2.  After a set overflow the set is grown from
+// its key list (which includes the partial appends of the failed launch) and
+// the launch replayed: set edges already present are skipped.  The owner
+// list is rewound to where the launch started and rewritten by the replay,
+// after growing it to the count the launch reported.
 template <typename F>
-int with_edge_growth(ip_ctx *ctx, BatchOut &g, int64_t &regrows, F launch) {
+int run_with_replay(ip_ctx *ctx, BatchSink &g, int64_t &regrows, F launch) {
   Counters *c = ctx->ctr_host;
   IP_TRY(read_ctr(ctx));
+  const uint64_t dir_lo = c->n_direct;
   uint64_t n_keys = c->n_out;
-  bool failed = false;
+  bool set_failed = false;
   for (int guard = 0;; ++guard) {
-    if (n_keys * 2 > g.et_cap || failed) {
-      if (guard > 40) return ip_fail(ctx, IP_ENOMEM, "edge table cannot grow");
+    if (guard > 40) return ip_fail(ctx, IP_ENOMEM, "edge tables cannot grow");
+    if (n_keys * 2 > g.et_cap || set_failed) {
       IP_TRY(zero_fail_flags(ctx));
-      IP_TRY(g.reserve(ctx, pow2_at_least(std::max<uint64_t>(n_keys * 4, g.et_cap * 2)), n_keys));
+      IP_TRY(g.reserve_set(pow2_at_least(std::max<uint64_t>(n_keys * 4, g.et_cap * 2)), n_keys));
       ++regrows;
     }
+    IP_TRY(set_counter(ctx, &ctx->ctr_dev->n_direct, dir_lo));
     IP_TRY(launch());
     IP_TRY(read_ctr(ctx));
-    if (!c->et_fail) return IP_OK;
-    failed = true;
+    const bool dir_over = c->n_direct > g.dcap;
+    if (!c->et_fail && !dir_over) return IP_OK;
+    set_failed = c->et_fail != 0;
     n_keys = c->n_out;
+    if (dir_over) {
+      IP_TRY(g.reserve_direct(c->n_direct + c->n_direct / 4 + 1024, dir_lo));
+      ++regrows;
+    }
   }
 }
 
 constexpr size_t kSubLdsMax = 64 * 1024;
 constexpr uint64_t kSubGrid = 4096;
 
+struct SubArgs {
+  int LB;
+  const uint64_t *tpts;
+  int NP;
+  const uint32_t *tedge;
+  const uint8_t *tface;
+  int NE;
+  const VEnt *cvt;
+  uint64_t cvt_mask;
+};
+
 template <int D, int MODE>
-int launch_sub(ip_ctx *ctx, const ip_problem *p, int LB, const uint64_t *sig, const uint32_t *list, uint64_t n,
-               const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, VEnt *fvt, uint64_t fvt_mask,
-               uint32_t *eval, BatchOut &g, uint32_t *defer, const uint32_t *pslot = nullptr) {
+int launch_sub(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig, const uint32_t *list,
+               uint64_t n, VEnt *fvt, uint64_t fvt_mask, uint32_t *eval, const BatchSink &g, uint32_t *defer,
+               const uint32_t *pslot = nullptr) {
   if (n == 0) return IP_OK;
-  const size_t lds = sub_lds_bytes(NP, NE);
-  const uint64_t blocks = std::min<uint64_t>((n + kBlock / 64 - 1) / (kBlock / 64), kSubGrid);
-#define IP_SUB(PP)                                                                                              \
-  hipLaunchKernelGGL((subdivide_kernel<D, PP, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, ctx->stream, \
-                     p->fine, p->coarse, LB, p->k, sig, list, n, tpts, NP, tedge, NE, p->poly, fvt, fvt_mask, eval, \
-                     pslot, g.et, g.et_cap - 1, g.keys, defer, ctx->ctr_dev)
+  const size_t lds = sub_lds_bytes(a.NP, a.NE);
+  const uint64_t blocks = std::min<uint64_t>((n + kWaves - 1) / kWaves, kSubGrid);
+  const SubOut so = g.sub_out(a.cvt, a.cvt_mask);
+#define IP_SUB(PP)                                                                                                  \
+  hipLaunchKernelGGL((subdivide_kernel<D, PP, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, ctx->stream,     \
+                     p->fine, p->coarse, a.LB, p->k, sig, list, n, a.tpts, a.NP, a.tedge, a.tface, a.NE, p->poly, \
+                     fvt, fvt_mask, eval, pslot, so, defer, ctx->ctr_dev)
   if (MODE == 3) {
     IP_SUB(1);
     IP_TRY_HIP(ctx, hipGetLastError());
@@ -1364,6 +1540,8 @@ struct DevTmp {
   ~DevTmp() {
     if (p) ip_dfree(ctx, p);
   }
+  DevTmp(const DevTmp &) = delete;
+  DevTmp &operator=(const DevTmp &) = delete;
   int get(size_t bytes) { return alloc(ctx, &p, bytes); }
   template <typename T>
   T *as() const {
@@ -1404,46 +1582,52 @@ int sub_points(ip_ctx *ctx, const ip_problem *p, const uint64_t *keys, uint64_t 
   return IP_OK;
 }
 
-// Subdivision of the coarse simplices sig[0 .. nsig) in the FP32-certified
-// mode (subdivide_kernel): no vertex table, so the per-batch workspace is one
-// 4-byte deferred-list entry per coarse simplex, plus the fallback vertex
-// table for the points no certified tier settles (sized from their count).
-// The point buffer is handed back through pts / pts_ld also on failure.
+// Initial sizes of the batch outputs from the coarse edge count: fine edges
+// are about coarse edges x k^(d-1) (the owner list gets 1.6 times that, the
+// set for edges without an owner a quarter); both grow on demand.
 template <int D>
-int subdivide_fused_run(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_all, uint64_t nsig, uint64_t nc,
-                        int LB, const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, uint64_t budget,
-                        ip_stats &st, ip_cells *res, double *&pts, uint64_t &pts_ld) {
-  const int k = p->k;
+int init_sink(BatchSink &g, uint64_t nc, int k) {
+  double est = (double)nc;
+  for (int q = 0; q < D - 1; ++q) est *= k;
+  IP_TRY(g.reserve_direct((uint64_t)std::min(est * 1.6, 4.0e9) + 1024, 0));
+  IP_TRY(g.reserve_set(pow2_at_least((uint64_t)std::min(est * 0.5, 4.0e9)), 0));
+  return IP_OK;
+}
+
+// Subdivision of the coarse simplices sig[0 .. nsig) in the FP32-certified
+// mode (subdivide_kernel MODE 0-2): no vertex table, so the per-batch
+// workspace is one 4-byte deferred-list entry per coarse simplex, plus the
+// fallback vertex table for the points no certified tier settles (sized
+// from their count).
+template <int D>
+int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig_all, uint64_t nsig,
+                    uint64_t nc, uint64_t budget, ip_stats &st, ip_cells *res) {
+  const int NP = a.NP, NE = a.NE;
   if (budget == 0) budget = 4ull << 30;
   uint64_t B = std::min<uint64_t>(budget / 4, 0xffffffffull);
   if (B == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
   if (B > nsig) B = nsig ? nsig : 1;
   IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * 4));
   uint32_t *defer = (uint32_t *)ctx->vt_aux.p;
-  BatchOut g;
-  g.ctx = ctx;
-  {
-    double est = (double)nc;
-    for (int q = 0; q < D - 1; ++q) est *= k;
-    IP_TRY(g.reserve(ctx, pow2_at_least((uint64_t)std::min(est * 2.5, 4.0e9)), 0));
-  }
+  BatchSink g(ctx);
+  IP_TRY(init_sink<D>(g, nc, p->k));
   Counters *c = ctx->ctr_host;
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
-  uint64_t n_out = 0;
   int64_t regrows = 0, n_fallback = 0, n_settled64 = 0, n_pts = 0, batches = 0;
   Timer tf, tx, tp, ts;
   for (uint64_t b0 = 0; b0 < nsig; b0 += B) {
     const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
     const uint64_t *sig = sig_all + b0;
     ++batches;
-    IP_TRY(with_edge_growth(ctx, g, regrows, [&]() -> int {
+    IP_TRY(run_with_replay(ctx, g, regrows, [&]() -> int {
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_unsettled));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_pts));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cert64));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_shared));
       IP_TRY(ts.start(ctx, &st.ms_subdivide));
-      IP_TRY((launch_sub<D, 0>(ctx, p, LB, sig, nullptr, nb, tpts, NP, tedge, NE, nullptr, 0, nullptr, g, defer)));
+      IP_TRY((launch_sub<D, 0>(ctx, p, a, sig, nullptr, nb, nullptr, 0, nullptr, g, defer)));
       ++st.subdivide_launches;
       return ts.stop(ctx);
     }));
@@ -1451,18 +1635,20 @@ int subdivide_fused_run(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_al
     n_pts += (int64_t)c->n_pts;
     n_settled64 += (int64_t)c->n_cert64;
     st.n_edge_hits += (int64_t)c->n_cof;
+    st.n_shared_probes += (int64_t)c->n_shared;
     if (n_def) {
       // canonical FP64 for the points no certified tier settled
       const uint64_t fcap = pow2_at_least(2 * n_uns + 1024);
-      IP_TRY(ip_ensure(ctx, ctx->vt_keys, fcap * sizeof(VEnt)));
-      IP_TRY(ip_ensure(ctx, ctx->eval_list, fcap * 4));
-      VEnt *fvt = (VEnt *)ctx->vt_keys.p;
-      uint32_t *eval = (uint32_t *)ctx->eval_list.p;
+      DevTmp fvt_hold(ctx), eval_hold(ctx);
+      IP_TRY(fvt_hold.get(fcap * sizeof(VEnt)));
+      IP_TRY(eval_hold.get(fcap * 4));
+      VEnt *fvt = fvt_hold.as<VEnt>();
+      uint32_t *eval = eval_hold.as<uint32_t>();
       IP_TRY(fill_vt(ctx, fvt, fcap));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
       IP_TRY(zero_fail_flags(ctx));
       IP_TRY(tx.start(ctx, &st.ms_expand));
-      IP_TRY((launch_sub<D, 1>(ctx, p, LB, sig, defer, n_def, tpts, NP, tedge, NE, fvt, fcap - 1, eval, g, nullptr)));
+      IP_TRY((launch_sub<D, 1>(ctx, p, a, sig, defer, n_def, fvt, fcap - 1, eval, g, nullptr)));
       IP_TRY(tx.stop(ctx));
       IP_TRY(read_ctr(ctx));
       if (c->vt_fail) return ip_fail(ctx, IP_ENOMEM, "fallback vertex table overflow");
@@ -1471,61 +1657,55 @@ int subdivide_fused_run(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_al
       IP_TRY(launch_feval64(ctx, p, p->fine, eval, n_ev, fvt));
       IP_TRY(tf.stop(ctx));
       n_fallback += (int64_t)n_ev;
-      IP_TRY(with_edge_growth(ctx, g, regrows, [&]() -> int {
+      IP_TRY(run_with_replay(ctx, g, regrows, [&]() -> int {
         IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
+        IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_shared));
         IP_TRY(ts.start(ctx, &st.ms_subdivide));
-        IP_TRY((launch_sub<D, 2>(ctx, p, LB, sig, defer, n_def, tpts, NP, tedge, NE, fvt, fcap - 1, nullptr, g,
-                                 nullptr)));
+        IP_TRY((launch_sub<D, 2>(ctx, p, a, sig, defer, n_def, fvt, fcap - 1, nullptr, g, nullptr)));
         ++st.subdivide_launches;
         return ts.stop(ctx);
       }));
       st.n_edge_hits += (int64_t)c->n_cof;
+      st.n_shared_probes += (int64_t)c->n_shared;
       if (c->vt_fail) return ip_fail(ctx, IP_EDEVICE, "fallback vertex missing from its table");
     }
     st.n_template_edges += (int64_t)(nb * (uint64_t)NE);
-    const uint64_t lo = n_out, hi = c->n_out;
     if (log_on())
-      fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu deferred, %llu cells so far\n", (long long)batches,
-              (unsigned long long)nb, (unsigned long long)n_def, (unsigned long long)hi);
-    IP_TRY(grow_points<D>(ctx, lo, hi, pts, pts_ld));
-    IP_TRY(sub_points<D>(ctx, p, g.keys, lo, hi, pts, pts_ld, tp, st, n_fallback));
-    n_out = hi;
+      fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu deferred, %llu + %llu cells so far\n",
+              (long long)batches, (unsigned long long)nb, (unsigned long long)n_def,
+              (unsigned long long)c->n_direct, (unsigned long long)c->n_out);
+  }
+  (void)NP;
+  const uint64_t n_dir = c->n_direct, n_set = c->n_out, n = n_dir + n_set;
+  IP_TRY(g.assemble<D>(n_dir, n_set, false));
+  double *pts = nullptr;
+  uint64_t ld = 0;
+  IP_TRY(grow_points<D>(ctx, 0, std::max<uint64_t>(n, 1), pts, ld));
+  const int rc = sub_points<D>(ctx, p, g.dkeys, 0, n, pts, ld, tp, st, n_fallback);
+  if (rc != IP_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx, pts);
+    return rc;
   }
   IP_TRY(tf.flush(ctx));
   IP_TRY(tx.flush(ctx));
   IP_TRY(tp.flush(ctx));
   IP_TRY(ts.flush(ctx));
-  if (!pts) IP_TRY(alloc(ctx, (void **)&pts, 8 * D));
   res->d = D;
   res->B = p->fine.B;
   for (int j = 0; j < 8; ++j) res->vmin[j] = p->fine.vmin[j];
-  res->n = (int64_t)n_out;
-  res->keys = g.take_keys();
+  res->n = (int64_t)n;
+  res->keys = g.dkeys;
+  g.dkeys = nullptr;
   res->pts = pts;
-  res->ld = (int64_t)(pts_ld ? pts_ld : 1);
-  pts = nullptr;
-  st.n_cells = (int64_t)n_out;
+  res->ld = (int64_t)ld;
+  st.n_cells = (int64_t)n;
   st.n_batches = batches;
   st.n_vertices += n_pts;
   st.regrows += regrows;
   st.n_fallback += n_fallback;
   st.n_settled64 += n_settled64;
   return IP_OK;
-}
-
-template <int D>
-int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_all, uint64_t nsig, uint64_t nc, int LB,
-                    const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, uint64_t budget, ip_stats &st,
-                    ip_cells *res) {
-  double *pts = nullptr;
-  uint64_t pts_ld = 0;
-  const int rc = subdivide_fused_run<D>(ctx, p, sig_all, nsig, nc, LB, tpts, NP, tedge, NE, budget, st, res, pts,
-                                        pts_ld);
-  if (pts) {
-    (void)hipStreamSynchronize(ctx->stream);
-    release(ctx, pts);
-  }
-  return rc;
 }
 
 // Subdivision of the coarse simplices sig[0 .. nsig) with canonical FP64
@@ -1537,15 +1717,14 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_all, u
 // entry) and NP 4-byte template slots per coarse simplex; the largest table
 // that fits the budget fixes the batch size.
 template <int D>
-int subdivide_table_run(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_all, uint64_t nsig, uint64_t nc,
-                        int LB, const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, uint64_t budget,
-                        ip_stats &st, ip_cells *res, double *&pts, uint64_t &pts_ld) {
-  const int k = p->k;
+int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig_all, uint64_t nsig,
+                    uint64_t nc, uint64_t budget, ip_stats &st, ip_cells *res) {
+  const int k = p->k, NP = a.NP, NE = a.NE;
   const uint64_t slot_bytes = sizeof(VEnt) + 4;
   if (budget == 0) budget = 4ull << 30;
   uint64_t vcap_b = 0;
-  for (uint64_t c = 1024; c <= (1ull << 32); c <<= 1)
-    if (c * slot_bytes + (c / 2) * 4 <= budget && c >= 2 * (uint64_t)NP) vcap_b = c;
+  for (uint64_t cc = 1024; cc <= (1ull << 32); cc <<= 1)
+    if (cc * slot_bytes + (cc / 2) * 4 <= budget && cc >= 2 * (uint64_t)NP) vcap_b = cc;
   if (vcap_b == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
   uint64_t B = vcap_b / (2 * (uint64_t)NP);
   if (B > nsig) B = nsig ? nsig : 1;
@@ -1561,19 +1740,13 @@ int subdivide_table_run(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_al
   f.eval = (uint32_t *)ctx->eval_list.p;
   f.vt_cap = vcap;
   uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
-  BatchOut g;
-  g.ctx = ctx;
-  {
-    // fine edges are about coarse edges x k^(d-1): start the set there
-    double est = (double)nc;
-    for (int q = 0; q < D - 1; ++q) est *= k;
-    IP_TRY(g.reserve(ctx, pow2_at_least((uint64_t)std::min(est * 2.5, 4.0e9)), 0));
-  }
-  uint64_t n_out = 0;
+  BatchSink g(ctx);
+  IP_TRY(init_sink<D>(g, nc, k));
   Counters *c = ctx->ctr_host;
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
   Timer tf, tx, tp, ts;
   int64_t batches = 0;
+  uint64_t dir_done = 0, set_done = 0;
   for (uint64_t b0 = 0; b0 < nsig; b0 += B) {
     const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
     const uint64_t *sig = sig_all + b0;
@@ -1582,7 +1755,7 @@ int subdivide_table_run(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_al
     IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
     IP_TRY(tx.start(ctx, &st.ms_expand));
     hipLaunchKernelGGL((batch_vertices_kernel<D>), dim3(grid_for(nb * NP)), dim3(kBlock), 0, ctx->stream, p->fine,
-                       p->coarse, LB, k, sig, nb, tpts, NP, f.vt, vcap - 1, f.eval, pslot, ctx->ctr_dev);
+                       p->coarse, a.LB, k, sig, nb, a.tpts, NP, f.vt, vcap - 1, f.eval, pslot, ctx->ctr_dev);
     IP_TRY_HIP(ctx, hipGetLastError());
     IP_TRY(tx.stop(ctx));
     IP_TRY(read_ctr(ctx));
@@ -1592,62 +1765,58 @@ int subdivide_table_run(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_al
     IP_TRY(eval_pending(f, n_ev));
     IP_TRY(tf.stop(ctx));
     st.n_vertices += (int64_t)n_ev;
-    IP_TRY(with_edge_growth(ctx, g, f.regrows, [&]() -> int {
+    IP_TRY(run_with_replay(ctx, g, f.regrows, [&]() -> int {
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
+      IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_shared));
       IP_TRY(ts.start(ctx, &st.ms_subdivide));
-      IP_TRY((launch_sub<D, 3>(ctx, p, LB, sig, nullptr, nb, tpts, NP, tedge, NE, f.vt, vcap - 1, nullptr, g, nullptr,
-                               pslot)));
+      IP_TRY((launch_sub<D, 3>(ctx, p, a, sig, nullptr, nb, f.vt, vcap - 1, nullptr, g, nullptr, pslot)));
       ++st.subdivide_launches;
       return ts.stop(ctx);
     }));
     st.n_edge_hits += (int64_t)c->n_cof;
+    st.n_shared_probes += (int64_t)c->n_shared;
     st.n_template_edges += (int64_t)(nb * (uint64_t)NE);
-    const uint64_t lo = n_out, hi = c->n_out;
+    const uint64_t dir_hi = c->n_direct, set_hi = c->n_out;
     if (log_on())
-      fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu new vertices, %llu cells so far\n",
-              (long long)batches, (unsigned long long)nb, (unsigned long long)n_ev, (unsigned long long)hi);
-    IP_TRY(grow_points<D>(ctx, lo, hi, pts, pts_ld));
-    if (hi > lo) {
-      IP_TRY(tp.start(ctx, &st.ms_points));
-      hipLaunchKernelGGL((batch_points_kernel<D>), dim3(grid_for(hi - lo)), dim3(kBlock), 0, ctx->stream, p->fine,
-                         (const uint64_t *)g.keys, lo, hi, (const VEnt *)f.vt, vcap - 1, pts, (int64_t)pts_ld, p->poly);
-      IP_TRY_HIP(ctx, hipGetLastError());
-      IP_TRY(tp.stop(ctx));
-    }
-    n_out = hi;
+      fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu new vertices, %llu + %llu cells so far\n",
+              (long long)batches, (unsigned long long)nb, (unsigned long long)n_ev, (unsigned long long)dir_hi,
+              (unsigned long long)set_hi);
+    // points of this batch's new edges, from the batch vertex table
+    IP_TRY(grow_points<D>(ctx, dir_done, dir_hi, g.dpts, g.dld));
+    IP_TRY(grow_points<D>(ctx, set_done, set_hi, g.spts, g.sld));
+    IP_TRY(tp.start(ctx, &st.ms_points));
+    if (dir_hi > dir_done)
+      hipLaunchKernelGGL((batch_points_kernel<D>), dim3(grid_for(dir_hi - dir_done)), dim3(kBlock), 0, ctx->stream,
+                         p->fine, (const uint64_t *)g.dkeys, dir_done, dir_hi, (const VEnt *)f.vt, vcap - 1, g.dpts,
+                         (int64_t)g.dld, p->poly);
+    if (set_hi > set_done)
+      hipLaunchKernelGGL((batch_points_kernel<D>), dim3(grid_for(set_hi - set_done)), dim3(kBlock), 0, ctx->stream,
+                         p->fine, (const uint64_t *)g.skeys, set_done, set_hi, (const VEnt *)f.vt, vcap - 1, g.spts,
+                         (int64_t)g.sld, p->poly);
+    IP_TRY_HIP(ctx, hipGetLastError());
+    IP_TRY(tp.stop(ctx));
+    dir_done = dir_hi;
+    set_done = set_hi;
   }
+  IP_TRY(g.assemble<D>(dir_done, set_done, true));
   IP_TRY(tf.flush(ctx));
   IP_TRY(tx.flush(ctx));
   IP_TRY(tp.flush(ctx));
   IP_TRY(ts.flush(ctx));
-  if (!pts) IP_TRY(alloc(ctx, (void **)&pts, 8 * D));
+  const uint64_t n = dir_done + set_done;
   res->d = D;
   res->B = p->fine.B;
   for (int j = 0; j < 8; ++j) res->vmin[j] = p->fine.vmin[j];
-  res->n = (int64_t)n_out;
-  res->keys = g.take_keys();
-  res->pts = pts;
-  res->ld = (int64_t)(pts_ld ? pts_ld : 1);
-  pts = nullptr;
-  st.n_cells = (int64_t)n_out;
+  res->n = (int64_t)n;
+  res->keys = g.dkeys;
+  g.dkeys = nullptr;
+  res->pts = g.dpts;
+  res->ld = (int64_t)g.dld;
+  g.dpts = nullptr;
+  st.n_cells = (int64_t)n;
   st.n_batches = batches;
   st.regrows += f.regrows;
   return IP_OK;
-}
-
-template <int D>
-int subdivide_table(ip_ctx *ctx, const ip_problem *p, const uint64_t *sig_all, uint64_t nsig, uint64_t nc, int LB,
-                    const uint64_t *tpts, int NP, const uint32_t *tedge, int NE, uint64_t budget, ip_stats &st,
-                    ip_cells *res) {
-  double *pts = nullptr;
-  uint64_t pts_ld = 0;
-  const int rc = subdivide_table_run<D>(ctx, p, sig_all, nsig, nc, LB, tpts, NP, tedge, NE, budget, st, res, pts,
-                                        pts_ld);
-  if (pts) {
-    (void)hipStreamSynchronize(ctx->stream);
-    release(ctx, pts);
-  }
-  return rc;
 }
 
 template <int D>
@@ -1676,6 +1845,12 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
       return rc;
     }
   }
+  // the coarse vertex table (visited-edge masks = the coarse trace) stays
+  // for the ownership test; the fine stage gets a table of its own
+  DevTmp cvt_hold(ctx);
+  cvt_hold.p = ctx->vt_keys.p;
+  ctx->vt_keys = DevBuf{};
+  const uint64_t cvt_cap = s.vt_cap;
   OutRec *coarse_edges = s.out;
   s.out = nullptr;
   s.out_cap = 0;
@@ -1716,7 +1891,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     release(ctx, sig_tab);
     sig_tab = nullptr;
   }
-  DevTmp sig_hold(ctx), tpts_hold(ctx), tedge_hold(ctx);
+  DevTmp sig_hold(ctx), tpts_hold(ctx), tedge_hold(ctx), tface_hold(ctx);
   sig_hold.p = sig_list;
   st.n_sigma = (int64_t)nsig;
   st.n_coarse_edges = (int64_t)nc;
@@ -1726,17 +1901,18 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   // ---- template on the device
   IP_TRY(tpts_hold.get(T.pts.size() * 8));
   IP_TRY(tedge_hold.get(T.edges.size() * 4));
-  void *tpts = tpts_hold.p, *tedge = tedge_hold.p;
-  IP_TRY_HIP(ctx, hipMemcpyAsync(tpts, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice, ctx->stream));
-  IP_TRY_HIP(ctx, hipMemcpyAsync(tedge, T.edges.data(), T.edges.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY(tface_hold.get(T.face.size()));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(tpts_hold.p, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY_HIP(ctx,
+             hipMemcpyAsync(tedge_hold.p, T.edges.data(), T.edges.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(tface_hold.p, T.face.data(), T.face.size(), hipMemcpyHostToDevice, ctx->stream));
+  const SubArgs a{LB, tpts_hold.as<uint64_t>(), NP, tedge_hold.as<uint32_t>(), tface_hold.as<uint8_t>(), NE,
+                  cvt_hold.as<VEnt>(), cvt_cap - 1};
   int rc;
-  if (cert) {
-    rc = subdivide_fused<D>(ctx, p, (const uint64_t *)sig_list, nsig, nc, LB, (const uint64_t *)tpts, NP,
-                            (const uint32_t *)tedge, NE, budget, st, res);
-  } else {
-    rc = subdivide_table<D>(ctx, p, (const uint64_t *)sig_list, nsig, nc, LB, (const uint64_t *)tpts, NP,
-                            (const uint32_t *)tedge, NE, budget, st, res);
-  }
+  if (cert)
+    rc = subdivide_fused<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, st, res);
+  else
+    rc = subdivide_table<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, st, res);
   (void)hipStreamSynchronize(ctx->stream);
   st.regrows += s.regrows;
   st.n_fallback += s.n_fallback;
