@@ -244,14 +244,24 @@ int build_poly(ip_ctx *ctx, ip_problem *p, const ip_fparams *f, const ip_space *
   for (int m = 0; m < M; ++m) cf[m] = (float)c[m];
   for (int m = 0; m < M; ++m)
     if (!std::isfinite(cf[m])) return IP_OK;  // out of FP32 range: FP64 only
-  // one buffer: M doubles, then M floats
-  IP_TRY_HIP(ctx, hipMalloc((void **)&p->poly_dev, 12 * (size_t)M));
+  // one buffer: M doubles, M floats, M monomial index words
+  // variable indices of each monomial, in the same depth-first order
+  std::vector<uint32_t> mono(M, 0u);
+  for (size_t mi = 0; mi < monos.size(); ++mi) {
+    uint32_t pk = (uint32_t)monos[mi].size();
+    for (size_t q = 0; q < monos[mi].size(); ++q) pk |= (uint32_t)monos[mi][q] << (4 + 4 * q);
+    mono[mi + 1] = pk;
+  }
+  IP_TRY_HIP(ctx, hipMalloc((void **)&p->poly_dev, 16 * (size_t)M));
   IP_TRY_HIP(ctx, hipMemcpyAsync(p->poly_dev, c.data(), 8 * (size_t)M, hipMemcpyHostToDevice, ctx->stream));
   IP_TRY_HIP(ctx, hipMemcpyAsync((char *)p->poly_dev + 8 * (size_t)M, cf.data(), 4 * (size_t)M,
+                                 hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY_HIP(ctx, hipMemcpyAsync((char *)p->poly_dev + 12 * (size_t)M, mono.data(), 4 * (size_t)M,
                                  hipMemcpyHostToDevice, ctx->stream));
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
   p->poly.cd = (const double *)p->poly_dev;
   p->poly.c = (const float *)((const char *)p->poly_dev + 8 * (size_t)M);
+  p->poly.mono = (const uint32_t *)((const char *)p->poly_dev + 12 * (size_t)M);
   p->poly.ok = 1;
   return IP_OK;
 }

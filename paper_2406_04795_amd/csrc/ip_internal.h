@@ -57,6 +57,7 @@ struct FDev {
 struct PolyDev {
   const float *c;
   const double *cd;
+  const uint32_t *mono;  // per coefficient: degree | variable index << (4 + 4 i)
   int32_t M;
   int32_t p;
   int32_t ok;   // 0: degree above 4, every vertex is evaluated in FP64
@@ -312,6 +313,20 @@ struct MonoWalk {
   }
 };
 
+// The same walk without the |c| |x^m| sum: sum c_m x^m into acc.
+template <typename T, int D, int K, int J>
+struct MonoVal {
+  static __device__ __forceinline__ void run(const T *x, T mono, const T *__restrict__ C, int &ci, T &acc) {
+    if constexpr (J < D) {
+      const T m = mono * x[J];
+      acc = fma(C[ci], m, acc);
+      ++ci;
+      if constexpr (K > 1) MonoVal<T, D, K - 1, J>::run(x, m, C, ci, acc);
+      MonoVal<T, D, K, J + 1>::run(x, mono, C, ci, acc);
+    }
+  }
+};
+
 // f in the monomial basis, FP64, with the rigorous bound on |f - F|.
 template <int D, int P>
 __device__ __forceinline__ double poly64(const PolyDev &Q, const double *x, double *bound) {
@@ -350,6 +365,42 @@ __device__ __forceinline__ int cert_eval(const PolyDev &Q, const double *x64, do
   if (fabs(*fv) > *bnd + Q.B64) return 1;
   *fv = poly64<D, P>(Q, x64, bnd);
   return fabs(*fv) > *bnd + Q.B64 ? 2 : 3;
+}
+
+// Upper bound, for every point x of a region with |x_j| <= X_j, of the FP32
+// sum S_abs that the FP32 tier forms beside f32 (sum of |c_m| |x^m| with the
+// FP32 roundings of coefficients, coordinates, products and the sum), from
+// the FP64 monomial coefficients: K32 * Smax + E0 then bounds |f32 - F| at
+// every such point.  The terms are spread over the wave (lane l takes
+// monomials l, l + 64, ...) and summed with shuffles; every lane gets the
+// result.  All lanes of the wave must call it together.
+template <int P>
+__device__ __forceinline__ double region_sabs_bound(const PolyDev &Q, const double *X, int lane) {
+  double t = 0.0;
+  for (int m = lane; m < Q.M; m += 64) {
+    const uint32_t pk = Q.mono[m];
+    double term = fabs(Q.cd[m]);
+    for (int q = 0; q < (int)(pk & 15u); ++q) term *= X[(pk >> (4 + 4 * q)) & 15u];
+    t += term;
+  }
+#pragma unroll
+  for (int off = 32; off; off >>= 1) t += __shfl_xor(t, off, 64);
+  const double u32 = 5.9604644775390625e-08;  // 2^-24
+  return t * (1.0 + (double)(2 * P + Q.M + 4) * u32) * (1.0 + 1e-12);
+}
+
+// Tier-1 evaluation against a bound B1 (= K32 * Smax + E0) valid for the
+// whole region of x64: 1 when |f32| settles the sign, else 3.
+template <int D, int P>
+__device__ __forceinline__ int cert_eval_region(const PolyDev &Q, const double *x64, double B1, double *fv) {
+  float x[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) x[j] = (float)x64[j];
+  float acc = Q.c[0];
+  int ci = 1;
+  MonoVal<float, D, P, 0>::run(x, 1.0f, Q.c, ci, acc);
+  *fv = (double)acc;
+  return fabs(*fv) > B1 + Q.B64 ? 1 : 3;
 }
 
 // Deposit the low bits of src into the set positions of mask (ascending).

@@ -1024,9 +1024,13 @@ __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo,
 constexpr int kSubStage = 128;
 constexpr int kWaves = kBlock / 64;
 
-__host__ __device__ inline size_t sub_lds_bytes(int NP, int NE) {
+constexpr int kEdgeStage = 128;
+
+// M: monomial coefficients staged in LDS (FP64 then FP32 copies).
+__host__ __device__ inline size_t sub_lds_bytes(int NP, int NE, int M) {
   const size_t codes = ((size_t)NP + 7) & ~(size_t)7;
-  return (size_t)kWaves * (2 * kSubStage + 8) * 8 + (size_t)NP * 8 + (size_t)NE * 5 + (size_t)kWaves * codes;
+  return (size_t)kWaves * (2 * kSubStage + 16) * 8 + (size_t)M * 8 + (size_t)NP * 8 + (size_t)M * 4 +
+         (size_t)kWaves * kEdgeStage * 4 + (size_t)NE * 5 + (size_t)kWaves * codes;
 }
 
 struct SubOut {
@@ -1058,11 +1062,25 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
   uint64_t *stage_s = (uint64_t *)smem + (size_t)wib * kSubStage;
   uint64_t *stage_d = (uint64_t *)smem + (size_t)(kWaves + wib) * kSubStage;
   uint64_t *fm = (uint64_t *)smem + (size_t)2 * kWaves * kSubStage + (size_t)wib * 8;
-  uint64_t *lpts = (uint64_t *)smem + (size_t)2 * kWaves * kSubStage + (size_t)kWaves * 8;
-  uint32_t *ledge = (uint32_t *)(lpts + NP);
+  const int M = MODE == 3 ? 0 : Q.M;
+  double *lx = (double *)smem + (size_t)2 * kWaves * kSubStage + (size_t)kWaves * 8 + (size_t)wib * 8;
+  double *lcd = (double *)smem + (size_t)2 * kWaves * kSubStage + (size_t)kWaves * 16;
+  uint64_t *lpts = (uint64_t *)(lcd + M);
+  float *lc = (float *)(lpts + NP);
+  uint32_t *est = (uint32_t *)(lc + M) + (size_t)wib * kEdgeStage;
+  uint32_t *ledge = (uint32_t *)(lc + M) + (size_t)kWaves * kEdgeStage;
   uint8_t *lface = (uint8_t *)(ledge + NE);
   uint8_t *code = lface + NE + (size_t)wib * ncode;
   for (int i = threadIdx.x; i < NP; i += kBlock) lpts[i] = tpts[i];
+  // the monomial coefficients, read by every lane at the same index, from
+  // LDS (kept out of the vector registers)
+  for (int i = threadIdx.x; i < M; i += kBlock) {
+    lcd[i] = Q.cd[i];
+    lc[i] = Q.c[i];
+  }
+  PolyDev Ql = Q;
+  Ql.c = lc;
+  Ql.cd = lcd;
   if (MODE != 1)
     for (int i = threadIdx.x; i < NE; i += kBlock) {
       ledge[i] = tedge[i];
@@ -1083,6 +1101,29 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
     int32_t v[D], w[D];
     sig_unpack<D>(Lc, sig[s], LB, v, w);
     bool unsettled = false;
+    // tier-1 bound for the whole coarse simplex: |x_j| is largest at a
+    // vertex (fine coordinates k (v + 1_{w_0 .. w_{i-1}})), so one bound on
+    // the FP32 sum S_abs covers every template point
+    double B1 = 0.0;
+    if (MODE != 3) {
+      const int vi = lane <= D ? lane : D;
+      int32_t yv[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) yv[q] = k * v[q];
+      for (int t = 0; t < vi; ++t) yv[w[t]] += k;
+      double xv[D];
+      lat_coords<D>(Lf, yv, xv);
+      double *X = lx;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double a = fabs(xv[j]);
+#pragma unroll
+        for (int off = 32; off; off >>= 1) a = fmax(a, __shfl_xor(a, off, 64));
+        if (lane == 0) X[j] = a * (1.0 + 1e-12) + 1e-300;
+      }
+      wave_lds_sync();
+      B1 = Ql.K32 * region_sabs_bound<P>(Ql, X, lane) + Ql.E0;
+    }
     for (int p0 = 0; p0 < NP; p0 += 64) {
       const int pt = p0 + lane;
       uint32_t c = 2;
@@ -1098,12 +1139,11 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
         double x[D];
         lat_coords<D>(Lf, y, x);
         if (lat_in_box<D>(Lf, x)) {
-          double fv, bnd;
-          const int tier = cert_eval<D, P>(Q, x, &fv, &bnd);
+          double fv;
+          const int tier = cert_eval_region<D, P>(Ql, x, B1, &fv);
           if (MODE == 0) ++npts;
           if (tier < 3) {
             c = fv < 0.0 ? 0u : 1u;
-            if (MODE == 0 && tier == 2) ++n64;
           } else if (MODE == 0) {
             c = 3;
             ++nuns;
@@ -1186,45 +1226,73 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
         fm[4 + t] = bc;
       }
     }
+    // edge pass: sign test from LDS; the edges to emit (owner) or to
+    // dedup (no owner) are staged by index, and their keys are formed and
+    // written 64 at a time, so the sparse hits do not serialize the wave
+    int sne = 0;
+    auto flush_edges = [&]() {
+      wave_lds_sync();
+      for (int b = 0; b < sne; b += 64) {
+        const int idx = b + lane;
+        bool dir = false, nw = false;
+        uint64_t key = 0;
+        if (idx < sne) {
+          const uint32_t item = est[idx];
+          const uint32_t te = ledge[item & 0x7fffffffu];
+          int32_t y[D];
+          template_point<D>(v, w, k, lpts[te & 0xfffu], y);
+          const uint32_t Rl = te >> 24;
+          uint32_t Rg = 0;
+#pragma unroll
+          for (int i = 0; i < D; ++i) Rg |= ((Rl >> i) & 1u) << w[i];
+          key = ekey<D>(Lf, y, Rg);
+          if (item >> 31) {
+            uint64_t slot;
+            const int ins = ht_insert(so.et_keys, so.et_mask, key, &slot);
+            if (ins == 1)
+              nw = true;
+            else if (ins < 0)
+              atomicOr(&ctr->et_fail, 1u);
+          } else {
+            dir = true;
+          }
+        }
+        stage_put<kSubStage>(stage_s, sn, nw, key, put_s, &ctr->n_out);
+        stage_put<kSubStage>(stage_d, snd, dir, key, put_d, &ctr->n_direct);
+      }
+      wave_lds_sync();
+      sne = 0;
+    };
     wave_lds_sync();
     for (int e0 = 0; e0 < NE; e0 += 64) {
       const int e = e0 + lane;
-      bool is_new = false, is_dir = false;
-      uint64_t key = 0;
+      bool take = false;
+      uint32_t item = 0;
       if (e < NE) {
         const uint32_t te = ledge[e];
         const uint32_t ca = code[te & 0xfffu], cb = code[(te >> 12) & 0xfffu];
         if ((ca ^ cb) == 1u && (ca | cb) == 1u) {
           ++hits;
           const uint32_t V = lface[e];
-          const bool tr = (fm[V >> 6] >> (V & 63u)) & 1ull;
-          const bool owner = (fm[4 + (V >> 6)] >> (V & 63u)) & 1ull;
-          if (!tr || owner) {
-            int32_t y[D];
-            template_point<D>(v, w, k, lpts[te & 0xfffu], y);
-            const uint32_t Rl = te >> 24;
-            uint32_t Rg = 0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) Rg |= ((Rl >> i) & 1u) << w[i];
-            key = ekey<D>(Lf, y, Rg);
-            if (tr) {
-              is_dir = true;
-            } else {
-              ++shits;
-              uint64_t slot;
-              const int ins = ht_insert(so.et_keys, so.et_mask, key, &slot);
-              if (ins == 1)
-                is_new = true;
-              else if (ins < 0)
-                atomicOr(&ctr->et_fail, 1u);
-            }
+          if (!((fm[V >> 6] >> (V & 63u)) & 1ull)) {
+            take = true;
+            item = (uint32_t)e | 0x80000000u;
+            ++shits;
+          } else if ((fm[4 + (V >> 6)] >> (V & 63u)) & 1ull) {
+            take = true;
+            item = (uint32_t)e;
           }
         }
       }
-      stage_put<kSubStage>(stage_s, sn, is_new, key, put_s, &ctr->n_out);
-      stage_put<kSubStage>(stage_d, snd, is_dir, key, put_d, &ctr->n_direct);
+      const uint64_t bal = __ballot(take);
+      if (bal) {
+        const int nb = __popcll(bal);
+        if (sne + nb > kEdgeStage) flush_edges();
+        if (take) est[sne + __popcll(bal & ((1ull << lane) - 1ull))] = item;
+        sne += nb;
+      }
     }
-    wave_lds_sync();
+    flush_edges();
   }
   if (MODE != 1) {
     stage_flush(stage_s, sn, put_s, &ctr->n_out);
@@ -1508,7 +1576,7 @@ int launch_sub(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_
                uint64_t n, VEnt *fvt, uint64_t fvt_mask, uint32_t *eval, const BatchSink &g, uint32_t *defer,
                const uint32_t *pslot = nullptr) {
   if (n == 0) return IP_OK;
-  const size_t lds = sub_lds_bytes(a.NP, a.NE);
+  const size_t lds = sub_lds_bytes(a.NP, a.NE, MODE == 3 ? 0 : p->poly.M);
   const uint64_t blocks = std::min<uint64_t>((n + kWaves - 1) / kWaves, kSubGrid);
   const SubOut so = g.sub_out(a.cvt, a.cvt_mask);
 #define IP_SUB(PP)                                                                                                  \
@@ -1828,7 +1896,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     return ip_fail(ctx, IP_ERANGE, "coarse simplex keys do not fit 63 bits for this domain and k");
   Template T = make_template(D, k);
   const int NP = (int)T.pts.size(), NE = (int)T.edges.size();
-  if (sub_lds_bytes(NP, NE) > kSubLdsMax)
+  if (sub_lds_bytes(NP, NE, p->poly.M) > kSubLdsMax)
     return ip_fail(ctx, IP_EINVAL, "subdivision template does not fit one workgroup's LDS (reduce k)");
   // ---- coarse trace (Sec. V-B: trace at scale k * lambda)
   Run s;
