@@ -236,6 +236,13 @@ int build_poly(ip_ctx *ctx, ip_problem *p, const ip_fparams *f, const ip_space *
   }
   p->poly.B64 = u64 * (double)((P - 1) + P * (d + 2) + S + 3) * sg * 1.01 + 2.0 * u64 * std::fabs(f->bias);
   p->poly.K32 = u32 * (double)(2 * P + M + 4) * (1.0 + (double)(M + 4) * u32) * 1.001;
+  // nested form: every term c_m x^m of f is perturbed by at most
+  // P (d + 1) roundings of the nested sums, P of the FP32 coordinates, one
+  // of its FP32 coefficient and one of the final addition
+  {
+    const double N = (double)(P * (d + 2) + 2);
+    p->poly.K32n = N * u32 / (1.0 - N * u32) * 1.001;
+  }
   p->poly.K64 = u64 * (double)(2 * P + M + 4) * (1.0 + (double)(M + 4) * u64) * 1.001;
   p->poly.E0 = E0 * (1.0 + 1e-9);
   p->poly.M = M;

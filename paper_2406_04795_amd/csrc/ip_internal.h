@@ -63,6 +63,7 @@ struct PolyDev {
   int32_t ok;   // 0: degree above 4, every vertex is evaluated in FP64
   int32_t pad;
   double K32, K64, E0, B64;
+  double K32n;  // nested FP32 evaluation: |f32 - F| <= K32n * sum |c_m| |x^m| + E0
 };
 
 struct Counters {
@@ -327,6 +328,25 @@ struct MonoVal {
   }
 };
 
+// Nested (multivariate Horner) form of the same polynomial, in the same
+// coefficient order: the sum over j = J .. D-1 of x_j * (c_{m x_j} + the
+// extensions of m x_j).  Each coefficient passes through at most D + 1
+// roundings per level and P levels, against the M - 1 of a flat sum.
+template <typename T, int D, int K, int J>
+struct MonoNest {
+  static __device__ __forceinline__ T run(const T *x, const T *__restrict__ C, int &ci) {
+    if constexpr (J < D) {
+      T sub = C[ci];
+      ++ci;
+      if constexpr (K > 1) sub = sub + MonoNest<T, D, K - 1, J>::run(x, C, ci);
+      const T rest = MonoNest<T, D, K, J + 1>::run(x, C, ci);
+      return fma(x[J], sub, rest);
+    } else {
+      return T(0);
+    }
+  }
+};
+
 // f in the monomial basis, FP64, with the rigorous bound on |f - F|.
 template <int D, int P>
 __device__ __forceinline__ double poly64(const PolyDev &Q, const double *x, double *bound) {
@@ -374,7 +394,6 @@ __device__ __forceinline__ int cert_eval(const PolyDev &Q, const double *x64, do
 // every such point.  The terms are spread over the wave (lane l takes
 // monomials l, l + 64, ...) and summed with shuffles; every lane gets the
 // result.  All lanes of the wave must call it together.
-template <int P>
 __device__ __forceinline__ double region_sabs_bound(const PolyDev &Q, const double *X, int lane) {
   double t = 0.0;
   for (int m = lane; m < Q.M; m += 64) {
@@ -385,21 +404,20 @@ __device__ __forceinline__ double region_sabs_bound(const PolyDev &Q, const doub
   }
 #pragma unroll
   for (int off = 32; off; off >>= 1) t += __shfl_xor(t, off, 64);
-  const double u32 = 5.9604644775390625e-08;  // 2^-24
-  return t * (1.0 + (double)(2 * P + Q.M + 4) * u32) * (1.0 + 1e-12);
+  return t * (1.0 + 1e-12);
 }
 
-// Tier-1 evaluation against a bound B1 (= K32 * Smax + E0) valid for the
-// whole region of x64: 1 when |f32| settles the sign, else 3.
+// Tier-1 evaluation, nested FP32 form, against a bound B1 (= K32n * Smax +
+// E0, Smax = region_sabs_bound) valid for the whole region of x64: 1 when
+// |f32| settles the sign, else 3.
 template <int D, int P>
 __device__ __forceinline__ int cert_eval_region(const PolyDev &Q, const double *x64, double B1, double *fv) {
   float x[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) x[j] = (float)x64[j];
-  float acc = Q.c[0];
   int ci = 1;
-  MonoVal<float, D, P, 0>::run(x, 1.0f, Q.c, ci, acc);
-  *fv = (double)acc;
+  const float v = Q.c[0] + MonoNest<float, D, P, 0>::run(x, Q.c, ci);
+  *fv = (double)v;
   return fabs(*fv) > B1 + Q.B64 ? 1 : 3;
 }
 

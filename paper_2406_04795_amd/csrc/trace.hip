@@ -1101,6 +1101,23 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
     int32_t v[D], w[D];
     sig_unpack<D>(Lc, sig[s], LB, v, w);
     bool unsettled = false;
+    // coarse vertex `lane` (lanes 0..D) of the simplex, v + 1_{w_0 .. w_{lane-1}},
+    // and the coarse-table entry at its home slot: loaded here, used after
+    // the point phase, so the load latency hides behind it
+    uint64_t ckey = IP_EMPTY_KEY, hkey = IP_EMPTY_KEY, hm0 = 0, hm1 = 0;
+    if (MODE != 1 && lane <= D) {
+      int32_t cv[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) cv[q] = v[q];
+      for (int t = 0; t < lane; ++t) cv[w[t]] += 1;
+      if (vin_range<D>(Lc, cv)) {
+        ckey = vpack<D>(Lc, cv);
+        const VEnt *e0 = so.cvt + (mix64(ckey) & so.cvt_mask);
+        hkey = e0->key;
+        hm0 = e0->m[0];
+        hm1 = e0->m[1];
+      }
+    }
     // tier-1 bound for the whole coarse simplex: |x_j| is largest at a
     // vertex (fine coordinates k (v + 1_{w_0 .. w_{i-1}})), so one bound on
     // the FP32 sum S_abs covers every template point
@@ -1122,7 +1139,7 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
         if (lane == 0) X[j] = a * (1.0 + 1e-12) + 1e-300;
       }
       wave_lds_sync();
-      B1 = Ql.K32 * region_sabs_bound<P>(Ql, X, lane) + Ql.E0;
+      B1 = Ql.K32n * region_sabs_bound(Ql, X, lane) + Ql.E0;
     }
     for (int p0 = 0; p0 < NP; p0 += 64) {
       const int pt = p0 + lane;
@@ -1175,27 +1192,36 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
     // R = {w_i .. w_{j-1}} from its smaller end i; row i holds bit j when
     // that edge is in the coarse trace
     uint32_t row = 0;
-    if (lane <= D) {
-      int32_t cv[D];
-#pragma unroll
-      for (int q = 0; q < D; ++q) cv[q] = v[q];
-      for (int t = 0; t < lane; ++t) cv[w[t]] += 1;
-      if (vin_range<D>(Lc, cv)) {
-        const int64_t h = vt_find(so.cvt, so.cvt_mask, vpack<D>(Lc, cv));
+    if (lane <= D && ckey != IP_EMPTY_KEY) {
+      bool found = hkey == ckey;
+      uint64_t m0 = hm0, m1 = hm1;
+      if (!found && hkey != IP_EMPTY_KEY) {
+        const int64_t h = vt_find(so.cvt, so.cvt_mask, ckey);
         if (h >= 0) {
-          const uint64_t m0 = so.cvt[h].m[0], m1 = so.cvt[h].m[1];
-          uint32_t R = 0;
-          for (int j = lane + 1; j <= D; ++j) {
-            R |= 1u << w[j - 1];
-            const uint64_t word = R < 64 ? m0 : m1;
-            if ((word >> (R & 63u)) & 1ull) row |= 1u << j;
-          }
+          found = true;
+          m0 = so.cvt[h].m[0];
+          m1 = so.cvt[h].m[1];
+        }
+      }
+      if (found) {
+        uint32_t R = 0;
+        for (int j = lane + 1; j <= D; ++j) {
+          R |= 1u << w[j - 1];
+          const uint64_t word = R < 64 ? m0 : m1;
+          if ((word >> (R & 63u)) & 1ull) row |= 1u << j;
         }
       }
     }
-    uint32_t rows[D + 1];
-#pragma unroll
-    for (int i = 0; i <= D; ++i) rows[i] = (uint32_t)__shfl((int)row, i, 64);
+    // rows and the cyclic root sequence (w_0 .. w_{D-1}, D) go to the
+    // wave's LDS scratch (the region-bound area, free again) for the
+    // lane-indexed reads below
+    uint32_t *lrow = (uint32_t *)lx;
+    int32_t *lseq = (int32_t *)lx + 8;
+    if (lane <= D) {
+      lrow[lane] = row;
+      lseq[lane] = lane < D ? w[lane < D ? lane : 0] : D;
+    }
+    wave_lds_sync();
     // face masks over the vertex subsets V: traced (V holds a traced coarse
     // edge) and canonical (this simplex is the canonical n-coface of V)
 #pragma unroll
@@ -1203,9 +1229,8 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
       const uint32_t V = (uint32_t)(lane + 64 * t);
       bool trv = false, cnv = false;
       if (V < (uint32_t)NV && V != 0u) {
-#pragma unroll
         for (int i = 0; i <= D; ++i)
-          if (((V >> i) & 1u) && (rows[i] & V)) trv = true;
+          if (((V >> i) & 1u) && (lrow[i] & V)) trv = true;
         // blocks of V's partition: the roots after each vertex of V up to
         // the next one, cyclically (root of step p: w_p for p < D, D for p = D)
         const int start = __ffs((int)V) - 1;
@@ -1215,7 +1240,7 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
           int pidx = start + q;
           if (pidx > D) pidx -= D + 1;
           if ((V >> pidx) & 1u) prev = -1;
-          const int r = pidx < D ? w[pidx] : D;
+          const int r = lseq[pidx];
           if (r < prev) cnv = false;
           prev = r;
         }
