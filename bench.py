@@ -218,14 +218,37 @@ def main():
     ap.add_argument("--serve", type=int, default=256, help="serving requests (0: skip)")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload-cache", default="",
+                    help="pickle of the generated workload: loaded if present, else written (profiling runs)")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only run one plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the traced path has no multi-GPU mode in this build",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration > 0:
+        import torch
+        n = int(args.copy_calibration * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+        return
 
     # inputs first, on the CPU: the pool forks before anything touches the GPU
-    wl = workload(args.config)
+    if args.workload_cache and os.path.exists(args.workload_cache):
+        import pickle
+        with open(args.workload_cache, "rb") as fh:
+            wl = pickle.load(fh)
+    else:
+        wl = workload(args.config)
+        if args.workload_cache:
+            import pickle
+            with open(args.workload_cache, "wb") as fh:
+                pickle.dump(wl, fh)
     reqs = []
     if args.serve:
         from concurrent.futures import ProcessPoolExecutor
