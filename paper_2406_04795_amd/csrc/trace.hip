@@ -917,6 +917,27 @@ __device__ __forceinline__ void template_point(const int32_t *v, const int32_t *
   for (int i = 0; i < D; ++i) y[w[i]] = k * v[w[i]] + (int32_t)((up >> (8 * i)) & 0xffu);
 }
 
+// The same point from the inverse order: coordinate c carries template
+// coordinate winv[c] (w[winv[c]] = c); no register array is indexed at run
+// time.
+template <int D>
+__device__ __forceinline__ void template_point_inv(const int32_t *v, const int32_t *winv, int k, uint64_t up,
+                                                   int32_t *y) {
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[c] = k * v[c] + (int32_t)((up >> (8 * winv[c])) & 0xffu);
+}
+
+template <int D>
+__device__ __forceinline__ void perm_inverse(const int32_t *w, int32_t *winv) {
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    int32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) r = w[i] == c ? i : r;
+    winv[c] = r;
+  }
+}
+
 // Fine vertices of a batch of coarse simplices: insert into the batch vertex
 // table, remember the slot of every (simplex, template point).
 template <int D>
@@ -991,21 +1012,6 @@ __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo,
 // ---------------------------------------------------------------------------
 // Subdivision kernel (Sec. V-B, Fig. 6): one wave per coarse simplex.
 //
-// Sign codes.  The wave takes the sign of f at every template point, keeps
-// the signs in LDS as byte codes, then tests every template edge against
-// them.  Codes: 0 (f < 0), 1 (f >= 0), 2 (outside the box), 3 (neither
-// certified tier settles the sign).
-//   MODE 0: FP32-certified signs of sig[0 .. n) (no vertex table: a point
-//           shared by several coarse simplices is evaluated by each of them,
-//           which costs fewer cycles than a probe into a table of 10^8
-//           vertices); a simplex with a code-3 point goes to `defer`.
-//   MODE 1: the deferred simplices: their code-3 points are inserted into
-//           the fallback vertex table fvt (new slots to eval_list).
-//   MODE 2: the deferred simplices again, code-3 points taking the sign of
-//           the canonical FP64 value in fvt; then the edge pass.
-//   MODE 3: FP64 mode: the sign of template point p of simplex s is read
-//           from fvt[pslot[s * NP + p]].f (pslot ~0: outside the box).
-//
 // Ownership.  A fine edge lies in the relative interior of exactly one face
 // tau of the coarse simplex (vertices: the union of the supports of its
 // ends' barycentric coordinates, precomputed per template edge), and every
@@ -1017,20 +1023,95 @@ __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo,
 // other intersecting edges go through the global edge set (et_keys), whose
 // new keys are appended to out_s.
 //
-// Dynamic LDS per block: two append stages per wave, the per-wave face masks
-// (traced / canonical, one bit per vertex subset), template points, template
-// edges and their faces, and the per-wave sign codes.
+// Active faces.  Whether this simplex takes the edges of face tau depends
+// only on the coarse trace (tau traced or not, this simplex canonical for
+// tau or not), not on f.  So the wave first lists its active faces (not
+// traced, or traced with this simplex canonical), then takes the sign of f
+// only at the template points of their edges, and tests only their edges:
+// the template edges are grouped by face, and the active groups are laid
+// end to end in a virtual index space [0, T) that the lanes walk 64 at a
+// time (a bitmap of group starts maps a virtual index to its group).
+//
+// Sign codes.  The signs are kept in LDS as byte codes: 0 (f < 0), 1
+// (f >= 0), 2 (outside the box), 3 (neither certified tier settles the
+// sign).
+//   MODE 0: FP32-certified signs of sig[0 .. n) (no vertex table: a point
+//           shared by several coarse simplices is evaluated by each of them,
+//           which costs fewer cycles than a probe into a table of 10^8
+//           vertices); a simplex with a code-3 point goes to `defer`.
+//   MODE 1: the deferred simplices: their code-3 points are inserted into
+//           the fallback vertex table fvt (new slots to eval_list).
+//   MODE 2: the deferred simplices again, code-3 points taking the sign of
+//           the canonical FP64 value in fvt; then the edge pass.
+//   MODE 3: FP64 mode: the sign of template point p of simplex s is read
+//           from fvt[pslot[s * NP + p]].f (pslot ~0: outside the box).
 // ---------------------------------------------------------------------------
 constexpr int kSubStage = 128;
 constexpr int kWaves = kBlock / 64;
 
 constexpr int kEdgeStage = 128;
 
-// M: monomial coefficients staged in LDS (FP64 then FP32 copies).
-__host__ __device__ inline size_t sub_lds_bytes(int NP, int NE, int M) {
-  const size_t codes = ((size_t)NP + 7) & ~(size_t)7;
-  return (size_t)kWaves * (2 * kSubStage + 16) * 8 + (size_t)M * 8 + (size_t)NP * 8 + (size_t)M * 4 +
-         (size_t)kWaves * kEdgeStage * 4 + (size_t)NE * 5 + (size_t)kWaves * codes;
+// Dynamic LDS of one block, as byte offsets (each array 16-byte aligned).
+// Shared by the block: the fine frame (M row-major stride 8, then o, lo, hi),
+// the monomial coefficients (FP64 and FP32), the template points, their
+// face masks, edges and face groups.  Per wave: two append stages, an
+// 8-double scratch (the region bound's |x| maxima, then the coarse edge rows
+// and root sequence), the start bitmap and the list of the active groups,
+// the edge stage, the active point list and the sign codes.
+struct SubLayout {
+  uint32_t stage_s, stage_d, lx, lmat, lcd, lpts, lpf, sbm, lc, est, ledge, lgrp, agl, plist, code, total;
+};
+
+__host__ __device__ inline uint32_t sub_take(uint32_t &o, size_t bytes) {
+  const uint32_t r = o;
+  o += (uint32_t)((bytes + 15) & ~(size_t)15);
+  return r;
+}
+
+// NP template points, NE template edges, M monomials (0: no coefficients),
+// NV = 2^(d+1) vertex subsets.
+__host__ __device__ inline SubLayout sub_layout(int NP, int NE, int M, int NV) {
+  const int NVW = (NV + 63) / 64, SBW = (NE + 63) / 64;
+  SubLayout L;
+  uint32_t o = 0;
+  L.stage_s = sub_take(o, (size_t)kWaves * kSubStage * 8);
+  L.stage_d = sub_take(o, (size_t)kWaves * kSubStage * 8);
+  L.lx = sub_take(o, (size_t)kWaves * 8 * 8);
+  L.lmat = sub_take(o, 88 * 8);
+  L.lcd = sub_take(o, (size_t)M * 8);
+  L.lpts = sub_take(o, (size_t)NP * 8);
+  L.lpf = sub_take(o, (size_t)NP * NVW * 8);
+  L.sbm = sub_take(o, (size_t)kWaves * SBW * 8);
+  L.lc = sub_take(o, (size_t)M * 4);
+  L.est = sub_take(o, (size_t)kWaves * kEdgeStage * 4);
+  L.ledge = sub_take(o, (size_t)NE * 4);
+  L.lgrp = sub_take(o, (size_t)NV * 4);
+  L.agl = sub_take(o, (size_t)kWaves * NV * 4);
+  L.plist = sub_take(o, (size_t)kWaves * NP * 2);
+  L.code = sub_take(o, (size_t)kWaves * NP);
+  L.total = o;
+  return L;
+}
+
+// lat_coords / lat_in_box with the frame at M (row-major, stride 8), then
+// o, lo, hi at M + 64, 72, 80: the same operations in the same order.
+template <int D>
+__device__ __forceinline__ void lat_coords_m(const double *M, const int32_t *v, double *x) {
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double acc = M[64 + j];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc = fma(M[j * 8 + k], (double)v[k], acc);
+    x[j] = acc;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ bool in_box_m(const double *M, const double *x) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < D; ++j) ok = ok && (x[j] >= M[72 + j]) && (x[j] <= M[80 + j]);
+  return ok;
 }
 
 struct SubOut {
@@ -1043,35 +1124,58 @@ struct SubOut {
   uint64_t dcap;      // capacity of out_d (appends past it are counted, not written)
 };
 
+// Four waves per SIMD (the LDS allows four blocks per CU): the register cap
+// this sets costs a few spilled registers, fewer than a wave of occupancy.
 template <int D, int P, int MODE>
-__global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc, int LB, int k,
+__global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev Lc, int LB, int k,
                                                            const uint64_t *__restrict__ sig,
                                                            const uint32_t *__restrict__ list, uint64_t n,
                                                            const uint64_t *__restrict__ tpts, int NP,
-                                                           const uint32_t *__restrict__ tedge,
-                                                           const uint8_t *__restrict__ tface, int NE, PolyDev Q,
+                                                           const uint32_t *__restrict__ tedge, int NE,
+                                                           const uint32_t *__restrict__ tgrp,
+                                                           const uint64_t *__restrict__ tpf, PolyDev Q,
                                                            VEnt *fvt, uint64_t fvt_mask, uint32_t *eval_list,
                                                            const uint32_t *__restrict__ pslot, SubOut so,
                                                            uint32_t *defer, Counters *ctr) {
   constexpr int NV = 1 << (D + 1);        // vertex subsets of a coarse simplex
   constexpr int NVW = (NV + 63) / 64;     // 64-bit words per face mask
   extern __shared__ __align__(16) unsigned char smem[];
-  const int wib = threadIdx.x >> 6;
+  // the wave index is wave-uniform: say so, so that the simplex index, its
+  // key and (v, w) live in scalar registers
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int ncode = (NP + 7) & ~7;
-  uint64_t *stage_s = (uint64_t *)smem + (size_t)wib * kSubStage;
-  uint64_t *stage_d = (uint64_t *)smem + (size_t)(kWaves + wib) * kSubStage;
-  uint64_t *fm = (uint64_t *)smem + (size_t)2 * kWaves * kSubStage + (size_t)wib * 8;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
   const int M = MODE == 3 ? 0 : Q.M;
-  double *lx = (double *)smem + (size_t)2 * kWaves * kSubStage + (size_t)kWaves * 8 + (size_t)wib * 8;
-  double *lcd = (double *)smem + (size_t)2 * kWaves * kSubStage + (size_t)kWaves * 16;
-  uint64_t *lpts = (uint64_t *)(lcd + M);
-  float *lc = (float *)(lpts + NP);
-  uint32_t *est = (uint32_t *)(lc + M) + (size_t)wib * kEdgeStage;
-  uint32_t *ledge = (uint32_t *)(lc + M) + (size_t)kWaves * kEdgeStage;
-  uint8_t *lface = (uint8_t *)(ledge + NE);
-  uint8_t *code = lface + NE + (size_t)wib * ncode;
-  for (int i = threadIdx.x; i < NP; i += kBlock) lpts[i] = tpts[i];
+  const int SBW = (NE + 63) / 64;
+  const SubLayout Ly = sub_layout(NP, NE, M, NV);
+  uint64_t *stage_s = (uint64_t *)(smem + Ly.stage_s) + (size_t)wib * kSubStage;
+  uint64_t *stage_d = (uint64_t *)(smem + Ly.stage_d) + (size_t)wib * kSubStage;
+  double *lx = (double *)(smem + Ly.lx) + (size_t)wib * 8;
+  // fine frame in LDS: read at wave-uniform addresses, it stays out of the
+  // scalar registers
+  double *lmat = (double *)(smem + Ly.lmat);
+  double *lcd = (double *)(smem + Ly.lcd);
+  uint64_t *lpts = (uint64_t *)(smem + Ly.lpts);
+  uint64_t *lpf = (uint64_t *)(smem + Ly.lpf);
+  uint64_t *sbm = (uint64_t *)(smem + Ly.sbm) + (size_t)wib * SBW;
+  float *lc = (float *)(smem + Ly.lc);
+  uint32_t *est = (uint32_t *)(smem + Ly.est) + (size_t)wib * kEdgeStage;
+  uint32_t *ledge = (uint32_t *)(smem + Ly.ledge);
+  uint32_t *lgrp = (uint32_t *)(smem + Ly.lgrp);
+  uint32_t *agl = (uint32_t *)(smem + Ly.agl) + (size_t)wib * NV;
+  uint16_t *plist = (uint16_t *)(smem + Ly.plist) + (size_t)wib * NP;
+  uint8_t *code = (uint8_t *)(smem + Ly.code) + (size_t)wib * NP;
+  for (int i = threadIdx.x; i < NP; i += kBlock) {
+    lpts[i] = tpts[i];
+#pragma unroll
+    for (int t = 0; t < NVW; ++t) lpf[i * NVW + t] = tpf[i * NVW + t];
+  }
+  if (threadIdx.x < 64) lmat[threadIdx.x] = Lf.M[threadIdx.x];
+  if (threadIdx.x < 8) {
+    lmat[64 + threadIdx.x] = Lf.o[threadIdx.x];
+    lmat[72 + threadIdx.x] = Lf.lo[threadIdx.x];
+    lmat[80 + threadIdx.x] = Lf.hi[threadIdx.x];
+  }
   // the monomial coefficients, read by every lane at the same index, from
   // LDS (kept out of the vector registers)
   for (int i = threadIdx.x; i < M; i += kBlock) {
@@ -1081,11 +1185,8 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
   PolyDev Ql = Q;
   Ql.c = lc;
   Ql.cd = lcd;
-  if (MODE != 1)
-    for (int i = threadIdx.x; i < NE; i += kBlock) {
-      ledge[i] = tedge[i];
-      lface[i] = tface[i];
-    }
+  for (int i = threadIdx.x; i < NE; i += kBlock) ledge[i] = tedge[i];
+  for (int i = threadIdx.x; i < NV; i += kBlock) lgrp[i] = tgrp[i];
   __syncthreads();
   int sn = 0, snd = 0;
   auto put_s = [&](unsigned long long pos, uint64_t key) { so.out_s[pos] = key; };
@@ -1098,18 +1199,17 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
   for (uint64_t it = wave; it < n; it += n_waves) {
     // MODE 0 and 3 walk sig[0 .. n); MODE 1 and 2 walk the deferred list
     const uint64_t s = (MODE == 0 || MODE == 3) ? it : (uint64_t)list[it];
-    int32_t v[D], w[D];
+    int32_t v[D], w[D], winv[D];
     sig_unpack<D>(Lc, sig[s], LB, v, w);
-    bool unsettled = false;
+    perm_inverse<D>(w, winv);
     // coarse vertex `lane` (lanes 0..D) of the simplex, v + 1_{w_0 .. w_{lane-1}},
     // and the coarse-table entry at its home slot: loaded here, used after
-    // the point phase, so the load latency hides behind it
+    // the region bound, so the load latency hides behind it
     uint64_t ckey = IP_EMPTY_KEY, hkey = IP_EMPTY_KEY, hm0 = 0, hm1 = 0;
-    if (MODE != 1 && lane <= D) {
+    if (lane <= D) {
       int32_t cv[D];
 #pragma unroll
-      for (int q = 0; q < D; ++q) cv[q] = v[q];
-      for (int t = 0; t < lane; ++t) cv[w[t]] += 1;
+      for (int c = 0; c < D; ++c) cv[c] = v[c] + (winv[c] < lane ? 1 : 0);
       if (vin_range<D>(Lc, cv)) {
         ckey = vpack<D>(Lc, cv);
         const VEnt *e0 = so.cvt + (mix64(ckey) & so.cvt_mask);
@@ -1126,10 +1226,9 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
       const int vi = lane <= D ? lane : D;
       int32_t yv[D];
 #pragma unroll
-      for (int q = 0; q < D; ++q) yv[q] = k * v[q];
-      for (int t = 0; t < vi; ++t) yv[w[t]] += k;
+      for (int c = 0; c < D; ++c) yv[c] = k * v[c] + (winv[c] < vi ? k : 0);
       double xv[D];
-      lat_coords<D>(Lf, yv, xv);
+      lat_coords_m<D>(lmat, yv, xv);
       double *X = lx;
 #pragma unroll
       for (int j = 0; j < D; ++j) {
@@ -1140,52 +1239,6 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
       }
       wave_lds_sync();
       B1 = Ql.K32n * region_sabs_bound(Ql, X, lane) + Ql.E0;
-    }
-    for (int p0 = 0; p0 < NP; p0 += 64) {
-      const int pt = p0 + lane;
-      uint32_t c = 2;
-      if (MODE == 3) {
-        if (pt < NP) {
-          const uint32_t ps = pslot[s * (uint64_t)NP + pt];
-          if (ps != 0xffffffffu) c = fvt[ps].f < 0.0 ? 0u : 1u;
-          code[pt] = (uint8_t)c;
-        }
-      } else if (pt < NP) {
-        int32_t y[D];
-        template_point<D>(v, w, k, lpts[pt], y);
-        double x[D];
-        lat_coords<D>(Lf, y, x);
-        if (lat_in_box<D>(Lf, x)) {
-          double fv;
-          const int tier = cert_eval_region<D, P>(Ql, x, B1, &fv);
-          if (MODE == 0) ++npts;
-          if (tier < 3) {
-            c = fv < 0.0 ? 0u : 1u;
-          } else if (MODE == 0) {
-            c = 3;
-            ++nuns;
-          } else if (MODE == 1) {
-            uint64_t slot;
-            const int ins = vt_insert(fvt, fvt_mask, vpack<D>(Lf, y), &slot);
-            if (ins == 1)
-              eval_list[atomicAdd(&ctr->n_eval, 1ull)] = (uint32_t)slot;
-            else if (ins < 0)
-              atomicOr(&ctr->vt_fail, 1u);
-          } else {
-            const int64_t h = vt_find(fvt, fvt_mask, vpack<D>(Lf, y));
-            if (h < 0) atomicOr(&ctr->vt_fail, 1u);
-            c = (h >= 0 && !(fvt[h].f < 0.0)) ? 1u : 0u;
-          }
-        }
-        code[pt] = (uint8_t)c;
-      }
-      if (MODE == 0 && __ballot(c == 3)) unsettled = true;
-    }
-    if (MODE == 1) continue;
-    if (MODE == 0 && unsettled) {
-      if (lane == 0) defer[atomicAdd(&ctr->n_aux, 1ull)] = (uint32_t)s;
-      wave_lds_sync();
-      continue;
     }
     // traced coarse edges among the simplex's vertices: vertex i is
     // v + 1_{w_0 .. w_{i-1}}, edge (i, j) for i < j has direction
@@ -1204,31 +1257,45 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
         }
       }
       if (found) {
-        uint32_t R = 0;
-        for (int j = lane + 1; j <= D; ++j) {
-          R |= 1u << w[j - 1];
+        // edge (lane, j): R = the coordinates c with lane <= winv[c] < j
+#pragma unroll
+        for (int j = 1; j <= D; ++j) {
+          if (j <= lane) continue;
+          uint32_t R = 0;
+#pragma unroll
+          for (int c = 0; c < D; ++c) R |= (winv[c] >= lane && winv[c] < j) ? 1u << c : 0u;
           const uint64_t word = R < 64 ? m0 : m1;
           if ((word >> (R & 63u)) & 1ull) row |= 1u << j;
         }
       }
     }
     // rows and the cyclic root sequence (w_0 .. w_{D-1}, D) go to the
-    // wave's LDS scratch (the region-bound area, free again) for the
-    // lane-indexed reads below
+    // wave's LDS scratch (the region-bound area, read above in order) for
+    // the lane-indexed reads below; the start bitmap is cleared
     uint32_t *lrow = (uint32_t *)lx;
     int32_t *lseq = (int32_t *)lx + 8;
     if (lane <= D) {
       lrow[lane] = row;
-      lseq[lane] = lane < D ? w[lane < D ? lane : 0] : D;
+      int32_t wl = D;
+#pragma unroll
+      for (int c = 0; c < D; ++c) wl = winv[c] == lane ? c : wl;
+      lseq[lane] = wl;
     }
+    for (int i = lane; i < SBW; i += 64) sbm[i] = 0ull;
     wave_lds_sync();
-    // face masks over the vertex subsets V: traced (V holds a traced coarse
-    // edge) and canonical (this simplex is the canonical n-coface of V)
+    // active faces V: traced (V holds a traced coarse edge) and canonical
+    // (this simplex is the canonical n-coface of V) decide; an active face
+    // with edges gets a slot in agl (first edge | virtual start << 15 |
+    // set path << 31) and its virtual start a bit in sbm
+    uint64_t A[NVW];
+    int T = 0, G = 0;
 #pragma unroll
     for (int t = 0; t < NVW; ++t) {
       const uint32_t V = (uint32_t)(lane + 64 * t);
       bool trv = false, cnv = false;
+      uint32_t gd = 0;
       if (V < (uint32_t)NV && V != 0u) {
+        gd = lgrp[V];
         for (int i = 0; i <= D; ++i)
           if (((V >> i) & 1u) && (lrow[i] & V)) trv = true;
         // blocks of V's partition: the roots after each vertex of V up to
@@ -1245,15 +1312,97 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
           prev = r;
         }
       }
-      const uint64_t bt = __ballot(trv), bc = __ballot(cnv);
-      if (lane == 0) {
-        fm[t] = bt;
-        fm[4 + t] = bc;
+      const bool act = (gd >> 16) != 0u && (!trv || cnv);
+      const uint32_t cnt = act ? gd >> 16 : 0u;
+      // exclusive prefix sum of cnt over the lanes, one bit plane at a time
+      uint32_t excl = 0, tot = 0;
+      for (int b = 0; __ballot((cnt >> b) != 0u); ++b) {
+        const uint64_t bb = __ballot((cnt >> b) & 1u);
+        excl += (uint32_t)__popcll(bb & lt_mask) << b;
+        tot += (uint32_t)__popcll(bb) << b;
       }
+      const uint64_t ba = __ballot(act);
+      A[t] = ba;
+      if (act) {
+        const uint32_t vs = (uint32_t)T + excl;
+        agl[G + __popcll(ba & lt_mask)] = (gd & 0x7fffu) | (vs << 15) | (trv ? 0u : 0x80000000u);
+        atomicOr((uint32_t *)sbm + (vs >> 5), 1u << (vs & 31u));
+      }
+      T += (int)tot;
+      G += __popcll(ba);
     }
-    // edge pass: sign test from LDS; the edges to emit (owner) or to
-    // dedup (no owner) are staged by index, and their keys are formed and
-    // written 64 at a time, so the sparse hits do not serialize the wave
+    // active template points: an end of an edge of an active face
+    int NPA = 0;
+    for (int p0 = 0; p0 < NP; p0 += 64) {
+      const int pt = p0 + lane;
+      bool a = false;
+      if (pt < NP) {
+        uint64_t hit = 0;
+#pragma unroll
+        for (int t = 0; t < NVW; ++t) hit |= lpf[pt * NVW + t] & A[t];
+        a = hit != 0ull;
+      }
+      const uint64_t bal = __ballot(a);
+      if (a) plist[NPA + __popcll(bal & lt_mask)] = (uint16_t)pt;
+      NPA += __popcll(bal);
+    }
+    wave_lds_sync();
+    bool unsettled = false;
+    for (int i0 = 0; i0 < NPA; i0 += 64) {
+      const int i = i0 + lane;
+      uint32_t c = 2;
+      if (i < NPA) {
+        const int pt = plist[i];
+        if (MODE == 3) {
+          const uint32_t ps = pslot[s * (uint64_t)NP + pt];
+          if (ps != 0xffffffffu) c = fvt[ps].f < 0.0 ? 0u : 1u;
+        } else {
+          int32_t y[D];
+          template_point_inv<D>(v, winv, k, lpts[pt], y);
+          // an opaque zero offset keeps the frame reads in the loop (hoisted,
+          // the 36 matrix entries would pin 72 vector registers)
+          int z = 0;
+          asm volatile("" : "+s"(z));
+          const double *Mz = lmat + z;
+          double x[D];
+          lat_coords_m<D>(Mz, y, x);
+          if (in_box_m<D>(Mz, x)) {
+            double fv;
+            const int tier = cert_eval_region<D, P>(Ql, x, B1, &fv);
+            if (MODE == 0) ++npts;
+            if (tier < 3) {
+              c = fv < 0.0 ? 0u : 1u;
+            } else if (MODE == 0) {
+              c = 3;
+              ++nuns;
+            } else if (MODE == 1) {
+              uint64_t slot;
+              const int ins = vt_insert(fvt, fvt_mask, vpack<D>(Lf, y), &slot);
+              if (ins == 1)
+                eval_list[atomicAdd(&ctr->n_eval, 1ull)] = (uint32_t)slot;
+              else if (ins < 0)
+                atomicOr(&ctr->vt_fail, 1u);
+            } else {
+              const int64_t h = vt_find(fvt, fvt_mask, vpack<D>(Lf, y));
+              if (h < 0) atomicOr(&ctr->vt_fail, 1u);
+              c = (h >= 0 && !(fvt[h].f < 0.0)) ? 1u : 0u;
+            }
+          }
+        }
+        code[pt] = (uint8_t)c;
+      }
+      if (MODE == 0 && __ballot(c == 3)) unsettled = true;
+    }
+    if (MODE == 1) continue;
+    if (MODE == 0 && unsettled) {
+      if (lane == 0) defer[atomicAdd(&ctr->n_aux, 1ull)] = (uint32_t)s;
+      wave_lds_sync();
+      continue;
+    }
+    // edge pass over the active groups: sign test from LDS; the edges to
+    // emit (owner) or to dedup (no owner) are staged by index, and their keys
+    // are formed and written 64 at a time, so the sparse hits do not
+    // serialize the wave
     int sne = 0;
     auto flush_edges = [&]() {
       wave_lds_sync();
@@ -1265,11 +1414,11 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
           const uint32_t item = est[idx];
           const uint32_t te = ledge[item & 0x7fffffffu];
           int32_t y[D];
-          template_point<D>(v, w, k, lpts[te & 0xfffu], y);
+          template_point_inv<D>(v, winv, k, lpts[te & 0xfffu], y);
           const uint32_t Rl = te >> 24;
           uint32_t Rg = 0;
 #pragma unroll
-          for (int i = 0; i < D; ++i) Rg |= ((Rl >> i) & 1u) << w[i];
+          for (int c = 0; c < D; ++c) Rg |= ((Rl >> winv[c]) & 1u) << c;
           key = ekey<D>(Lf, y, Rg);
           if (item >> 31) {
             uint64_t slot;
@@ -1289,31 +1438,31 @@ __global__ __launch_bounds__(kBlock) void subdivide_kernel(LatDev Lf, LatDev Lc,
       sne = 0;
     };
     wave_lds_sync();
-    for (int e0 = 0; e0 < NE; e0 += 64) {
-      const int e = e0 + lane;
+    int carry = 0;  // group starts before t0
+    for (int t0 = 0; t0 < T; t0 += 64) {
+      const int t = t0 + lane;
+      const uint64_t wd = sbm[t0 >> 6];
+      const int gi = carry + __popcll(wd & ((2ull << lane) - 1ull)) - 1;
+      carry += __popcll(wd);
       bool take = false;
       uint32_t item = 0;
-      if (e < NE) {
+      if (t < T) {
+        const uint32_t ent = agl[gi];
+        const uint32_t e = (ent & 0x7fffu) + (uint32_t)t - ((ent >> 15) & 0x7fffu);
         const uint32_t te = ledge[e];
         const uint32_t ca = code[te & 0xfffu], cb = code[(te >> 12) & 0xfffu];
         if ((ca ^ cb) == 1u && (ca | cb) == 1u) {
           ++hits;
-          const uint32_t V = lface[e];
-          if (!((fm[V >> 6] >> (V & 63u)) & 1ull)) {
-            take = true;
-            item = (uint32_t)e | 0x80000000u;
-            ++shits;
-          } else if ((fm[4 + (V >> 6)] >> (V & 63u)) & 1ull) {
-            take = true;
-            item = (uint32_t)e;
-          }
+          take = true;
+          item = e | (ent & 0x80000000u);
+          if (ent >> 31) ++shits;
         }
       }
       const uint64_t bal = __ballot(take);
       if (bal) {
         const int nb = __popcll(bal);
         if (sne + nb > kEdgeStage) flush_edges();
-        if (take) est[sne + __popcll(bal & ((1ull << lane) - 1ull))] = item;
+        if (take) est[sne + __popcll(bal & lt_mask)] = item;
         sne += nb;
       }
     }
@@ -1389,14 +1538,17 @@ __global__ void sub_redo_kernel(LatDev L, const uint64_t *keys, const uint64_t *
 // Local subdivision template (Sec. V-B, Eq. 2 read with >=): points u with
 // k >= u_0 >= ... >= u_{d-1} >= 0 and edges (u, R) whose other end u + 1_R
 // is inside too.  Points packed 8 bits per coordinate; edges packed as
-// (index a | index b << 12 | R << 24).  face[e]: the vertices of the coarse
-// simplex whose barycentric weight is positive at either end of edge e
+// (index a | index b << 12 | R << 24).  The face of an edge is the set of
+// coarse-simplex vertices whose barycentric weight is positive at either end
 // (Eq. 1: vertex 0 weighs k - u_0, vertex i in 1..d-1 weighs u_{i-1} - u_i,
-// vertex d weighs u_{d-1}), i.e. the smallest face holding the edge.
+// vertex d weighs u_{d-1}), i.e. the smallest face holding the edge.  Edges
+// are grouped by face: grp[V] = first edge of face V | edge count << 16, and
+// pf[p * NVW + t] holds bit V - 64 t for every face V of an edge at point p.
 struct Template {
   std::vector<uint64_t> pts;
   std::vector<uint32_t> edges;
-  std::vector<uint8_t> face;
+  std::vector<uint32_t> grp;
+  std::vector<uint64_t> pf;
 };
 
 Template make_template(int d, int k) {
@@ -1434,15 +1586,25 @@ Template make_template(int d, int k) {
     for (int i = 0; i < d; ++i) pk |= (uint64_t)x[i] << (8 * i);
     T.pts.push_back(pk);
   }
+  const int NV = 1 << (d + 1), NVW = (NV + 63) / 64;
+  std::vector<std::vector<uint32_t>> by_face(NV);
   for (size_t a = 0; a < P.size(); ++a)
     for (uint32_t R = 1; R < (1u << d); ++R) {
       std::vector<int> y = P[a];
       for (int i = 0; i < d; ++i) y[i] += (int)((R >> i) & 1u);
       if (!inside(y)) continue;
-      int b = index_of(y);
-      T.edges.push_back((uint32_t)a | ((uint32_t)b << 12) | (R << 24));
-      T.face.push_back((uint8_t)(support(P[a]) | support(y)));
+      const int b = index_of(y);
+      by_face[support(P[a]) | support(y)].push_back((uint32_t)a | ((uint32_t)b << 12) | (R << 24));
     }
+  T.grp.assign(NV, 0u);
+  T.pf.assign(P.size() * NVW, 0ull);
+  for (int V = 0; V < NV; ++V) {
+    T.grp[V] = (uint32_t)T.edges.size() | ((uint32_t)by_face[V].size() << 16);
+    for (uint32_t te : by_face[V]) {
+      T.edges.push_back(te);
+      for (uint32_t q : {te & 0xfffu, (te >> 12) & 0xfffu}) T.pf[q * NVW + V / 64] |= 1ull << (V % 64);
+    }
+  }
   return T;
 }
 
@@ -1590,8 +1752,9 @@ struct SubArgs {
   const uint64_t *tpts;
   int NP;
   const uint32_t *tedge;
-  const uint8_t *tface;
   int NE;
+  const uint32_t *tgrp;
+  const uint64_t *tpf;
   const VEnt *cvt;
   uint64_t cvt_mask;
 };
@@ -1601,12 +1764,12 @@ int launch_sub(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_
                uint64_t n, VEnt *fvt, uint64_t fvt_mask, uint32_t *eval, const BatchSink &g, uint32_t *defer,
                const uint32_t *pslot = nullptr) {
   if (n == 0) return IP_OK;
-  const size_t lds = sub_lds_bytes(a.NP, a.NE, MODE == 3 ? 0 : p->poly.M);
+  const size_t lds = sub_layout(a.NP, a.NE, MODE == 3 ? 0 : p->poly.M, 1 << (D + 1)).total;
   const uint64_t blocks = std::min<uint64_t>((n + kWaves - 1) / kWaves, kSubGrid);
   const SubOut so = g.sub_out(a.cvt, a.cvt_mask);
 #define IP_SUB(PP)                                                                                                  \
   hipLaunchKernelGGL((subdivide_kernel<D, PP, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, ctx->stream,     \
-                     p->fine, p->coarse, a.LB, p->k, sig, list, n, a.tpts, a.NP, a.tedge, a.tface, a.NE, p->poly, \
+                     p->fine, p->coarse, a.LB, p->k, sig, list, n, a.tpts, a.NP, a.tedge, a.NE, a.tgrp, a.tpf, p->poly, \
                      fvt, fvt_mask, eval, pslot, so, defer, ctx->ctr_dev)
   if (MODE == 3) {
     IP_SUB(1);
@@ -1921,7 +2084,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     return ip_fail(ctx, IP_ERANGE, "coarse simplex keys do not fit 63 bits for this domain and k");
   Template T = make_template(D, k);
   const int NP = (int)T.pts.size(), NE = (int)T.edges.size();
-  if (sub_lds_bytes(NP, NE, p->poly.M) > kSubLdsMax)
+  if (sub_layout(NP, NE, p->poly.M, 1 << (D + 1)).total > kSubLdsMax || NE > 0x7fff)
     return ip_fail(ctx, IP_EINVAL, "subdivision template does not fit one workgroup's LDS (reduce k)");
   // ---- coarse trace (Sec. V-B: trace at scale k * lambda)
   Run s;
@@ -1984,7 +2147,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     release(ctx, sig_tab);
     sig_tab = nullptr;
   }
-  DevTmp sig_hold(ctx), tpts_hold(ctx), tedge_hold(ctx), tface_hold(ctx);
+  DevTmp sig_hold(ctx), tpts_hold(ctx), tedge_hold(ctx), tgrp_hold(ctx), tpf_hold(ctx);
   sig_hold.p = sig_list;
   st.n_sigma = (int64_t)nsig;
   st.n_coarse_edges = (int64_t)nc;
@@ -1994,12 +2157,15 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   // ---- template on the device
   IP_TRY(tpts_hold.get(T.pts.size() * 8));
   IP_TRY(tedge_hold.get(T.edges.size() * 4));
-  IP_TRY(tface_hold.get(T.face.size()));
+  IP_TRY(tgrp_hold.get(T.grp.size() * 4));
+  IP_TRY(tpf_hold.get(T.pf.size() * 8));
   IP_TRY_HIP(ctx, hipMemcpyAsync(tpts_hold.p, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   IP_TRY_HIP(ctx,
              hipMemcpyAsync(tedge_hold.p, T.edges.data(), T.edges.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-  IP_TRY_HIP(ctx, hipMemcpyAsync(tface_hold.p, T.face.data(), T.face.size(), hipMemcpyHostToDevice, ctx->stream));
-  const SubArgs a{LB, tpts_hold.as<uint64_t>(), NP, tedge_hold.as<uint32_t>(), tface_hold.as<uint8_t>(), NE,
+  IP_TRY_HIP(ctx, hipMemcpyAsync(tgrp_hold.p, T.grp.data(), T.grp.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(tpf_hold.p, T.pf.data(), T.pf.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  const SubArgs a{LB, tpts_hold.as<uint64_t>(), NP, tedge_hold.as<uint32_t>(), NE, tgrp_hold.as<uint32_t>(),
+                  tpf_hold.as<uint64_t>(),
                   cvt_hold.as<VEnt>(), cvt_cap - 1};
   int rc;
   if (cert)
