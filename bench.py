@@ -68,6 +68,30 @@ def template_size(d: int, k: int):
     return len(pts), ne
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "subdivide_d6_k4_traffic.json")
+
+
+def subdivide_traffic(wl):
+    """HBM bytes of one fused subdivision launch from the committed memory
+    counter runs (FETCH_SIZE, WRITE_SIZE, each scaled by what it reads for a
+    plain copy of known size), or None when they do not describe the kernel
+    as built now (its sources changed) or another workload."""
+    import hashlib
+
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for rel in rec["sources"]:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec["sources_sha256_16"] or not rec["workload"].startswith(wl.name):
+        return None
+    return round(rec["fetch_size_kib"] * 1024 * rec["fetch_factor"] + rec["write_size_kib"] * 1024 * rec["write_factor"])
+
+
 def subdivide_flops_per_simplex(wl) -> int:
     """Algorithmic floating-point operations of the fused subdivision kernel
     per coarse simplex: for each template point its FP64 lattice coordinates
@@ -303,9 +327,11 @@ def main():
         launches = stats[-1]["subdivide_launches"]
         flops = subdivide_flops_per_simplex(wl) * stats[-1]["n_sigma"]
         tfs = flops / (ms * 1e-3) / 1e12
+        # one fused launch over every coarse simplex, plus the deferred pass
+        # over the few (<1 %) with an unsettled point: the time is the sum
         roof = {"kernel": "subdivide_kernel (fused, FP32-certified)", "bound": "alu", "achieved": round(tfs, 2),
                 "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tfs / VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "ms_per_launch": round(ms / max(1, launches), 3), "launches_per_step": launches,
+                "traffic": subdivide_traffic(wl), "ms_per_step": round(ms, 3), "launches_per_step": launches,
                 "flops_per_coarse_simplex": subdivide_flops_per_simplex(wl)}
     else:
         x_ms = phase(stats, "ms_expand")
