@@ -1193,7 +1193,8 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
   auto put_d = [&](unsigned long long pos, uint64_t key) {
     if (pos < so.dcap) so.out_d[pos] = key;
   };
-  unsigned long long hits = 0, shits = 0, n64 = 0, npts = 0, nuns = 0;
+  // per-lane tallies (a lane sees far fewer than 2^32 events per launch)
+  uint32_t hits = 0, shits = 0, n64 = 0, npts = 0, nuns = 0;
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const uint64_t n_waves = ((uint64_t)gridDim.x * kBlock) >> 6;
   for (uint64_t it = wave; it < n; it += n_waves) {
@@ -1229,13 +1230,21 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
       for (int c = 0; c < D; ++c) yv[c] = k * v[c] + (winv[c] < vi ? k : 0);
       double xv[D];
       lat_coords_m<D>(lmat, yv, xv);
+      // max over the D + 1 vertices through LDS (the edge stage is free
+      // until the edge pass): vertex i's |x| at va[i * D + j]
+      static_assert(kEdgeStage * 4 >= (D + 1) * D * 8, "edge stage too small for the vertex coordinates");
+      double *va = (double *)est;
+      if (lane <= D) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) va[lane * D + j] = fabs(xv[j]);
+      }
+      wave_lds_sync();
       double *X = lx;
+      if (lane < D) {
+        double a = 0.0;
 #pragma unroll
-      for (int j = 0; j < D; ++j) {
-        double a = fabs(xv[j]);
-#pragma unroll
-        for (int off = 32; off; off >>= 1) a = fmax(a, __shfl_xor(a, off, 64));
-        if (lane == 0) X[j] = a * (1.0 + 1e-12) + 1e-300;
+        for (int i = 0; i <= D; ++i) a = fmax(a, va[i * D + lane]);
+        X[lane] = a * (1.0 + 1e-12) + 1e-300;
       }
       wave_lds_sync();
       B1 = Ql.K32n * region_sabs_bound(Ql, X, lane) + Ql.E0;
@@ -1472,11 +1481,11 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
     stage_flush(stage_s, sn, put_s, &ctr->n_out);
     stage_flush(stage_d, snd, put_d, &ctr->n_direct);
   }
-  if (hits) atomicAdd(&ctr->n_cof, hits);
-  if (shits) atomicAdd(&ctr->n_shared, shits);
-  if (n64) atomicAdd(&ctr->n_cert64, n64);
-  if (npts) atomicAdd(&ctr->n_pts, npts);
-  if (nuns) atomicAdd(&ctr->n_unsettled, nuns);
+  if (hits) atomicAdd(&ctr->n_cof, (unsigned long long)hits);
+  if (shits) atomicAdd(&ctr->n_shared, (unsigned long long)shits);
+  if (n64) atomicAdd(&ctr->n_cert64, (unsigned long long)n64);
+  if (npts) atomicAdd(&ctr->n_pts, (unsigned long long)npts);
+  if (nuns) atomicAdd(&ctr->n_unsettled, (unsigned long long)nuns);
 }
 
 __global__ void set_counter_kernel(unsigned long long *p, unsigned long long v) { *p = v; }
