@@ -1512,6 +1512,13 @@ __global__ void redo_ends_kernel(LatDev L, const uint64_t *keys, const uint64_t 
 template <int D>
 __global__ void sub_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo, uint64_t hi, double *pts, int64_t ld,
                                   PolyDev Q, uint64_t *redo, Counters *ctr) {
+  // the FP64 monomial coefficients, read by every lane at the same index,
+  // from LDS (from global memory each read would be a vector load)
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *lcd = (double *)smem;
+  for (int m = threadIdx.x; m < Q.M; m += blockDim.x) lcd[m] = Q.cd[m];
+  __syncthreads();
+  Q.cd = lcd;
   for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (uint64_t)gridDim.x * blockDim.x) {
     int32_t a[D], b[D];
     uint32_t R;
@@ -1825,7 +1832,8 @@ int sub_points(ip_ctx *ctx, const ip_problem *p, const uint64_t *keys, uint64_t 
   uint64_t *redo = (uint64_t *)ctx->scratch.p;
   IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
   IP_TRY(tp.start(ctx, &st.ms_points));
-  hipLaunchKernelGGL((sub_points_kernel<D>), dim3(grid_for(hi - lo)), dim3(kBlock), 0, ctx->stream, p->fine, keys, lo,
+  hipLaunchKernelGGL((sub_points_kernel<D>), dim3(grid_for(hi - lo)), dim3(kBlock), (size_t)p->poly.M * 8, ctx->stream,
+                     p->fine, keys, lo,
                      hi, pts, (int64_t)ld, p->poly, redo, ctx->ctr_dev);
   IP_TRY_HIP(ctx, hipGetLastError());
   IP_TRY(tp.stop(ctx));
