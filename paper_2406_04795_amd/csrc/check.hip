@@ -239,13 +239,13 @@ __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__
       const double Rb = lb[3] + S.eps;
       for (int b0 = 0; b0 < nobs; b0 += 64) {
         const int nb = nobs - b0 < 64 ? nobs - b0 : 64;
+        // spheres first, then boxes: two uniform loops, no per-obstacle branch
         uint64_t near = 0;
-        for (int b = 0; b < nb; ++b) {
-          const int o = b0 + b;
-          const bool nr = o < S.n_osph ? ball_near_sphere(cb, Rb, S.osph + 4 * o)
-                                       : ball_near_box(cb, Rb, S.obox + 16 * (o - S.n_osph));
-          near |= (uint64_t)nr << b;
-        }
+        const int nsb = S.n_osph - b0 < 0 ? 0 : (S.n_osph - b0 < nb ? S.n_osph - b0 : nb);
+        for (int b = 0; b < nsb; ++b)
+          near |= (uint64_t)ball_near_sphere(cb, Rb, S.osph + 4 * (b0 + b)) << b;
+        for (int b = nsb; b < nb; ++b)
+          near |= (uint64_t)ball_near_box(cb, Rb, S.obox + 16 * (b0 + b - S.n_osph)) << b;
         if (hit) near = 0;
         const uint64_t any = wave_or64(near);
         if (!any) continue;
