@@ -54,20 +54,6 @@ def workload(name: str):
     raise SystemExit(f"unknown config {name}")
 
 
-def template_size(d: int, k: int):
-    """Points and edges of the local subdivision template of one coarse
-    simplex (points k >= u_0 >= ... >= u_{d-1} >= 0; edges (u, u + 1_R))."""
-    import itertools
-    pts = [u for u in itertools.product(range(k + 1), repeat=d) if all(u[i] >= u[i + 1] for i in range(d - 1))]
-    ps = set(pts)
-    ne = 0
-    for u in pts:
-        for r in range(1, 1 << d):
-            if tuple(u[i] + ((r >> i) & 1) for i in range(d)) in ps:
-                ne += 1
-    return len(pts), ne
-
-
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "subdivide_d6_k4_traffic.json")
 
 
@@ -92,17 +78,56 @@ def subdivide_traffic(wl):
     return round(rec["fetch_size_kib"] * 1024 * rec["fetch_factor"] + rec["write_size_kib"] * 1024 * rec["write_factor"])
 
 
-def subdivide_flops_per_simplex(wl) -> int:
-    """Algorithmic floating-point operations of the fused subdivision kernel
-    per coarse simplex: for each template point its FP64 lattice coordinates
-    (d^2 fma) and the FP32 monomial-basis value with its bound sum (per
-    non-constant monomial: 1 mul for the monomial, 1 fma for the value, 1 fma
-    for the bound sum)."""
+def nest_flops(d: int, p: int) -> int:
+    """FP32 operations per point of the nested (multivariate Horner) form of
+    the degree-p polynomial over the monomial basis: one fma (2 flops) per
+    non-constant monomial, one add per monomial of degree below p (its
+    sub-sum), one final add of the constant term.  194 at d = 6, p = 3."""
+    from math import comb
+    n = [comb(d + k - 1, k) for k in range(1, p + 1)]
+    return 2 * sum(n) + sum(n[:-1]) + 1
+
+
+def subdivide_flops(st, wl) -> int:
+    """Floating-point operations of the fused subdivision launches, from the
+    counters of the code that runs: every template point it evaluated
+    (n_vertices; in the box, on an active face) costs its FP64 lattice
+    coordinates (d^2 fma) and the nested FP32 value; every coarse simplex
+    costs the coordinates of its d + 1 vertices and the region bound (per
+    non-constant monomial up to p multiplies and an add)."""
     from math import comb
     d, p = wl.f.d, wl.f.p
-    n_mono = comb(d + p, p)
-    npnt, _ = template_size(d, wl.k)
-    return npnt * (2 * d * d + 5 * (n_mono - 1))
+    m1 = comb(d + p, p) - 1
+    per_pt = 2 * d * d + nest_flops(d, p)
+    per_sigma = (d + 1) * 2 * d * d + (p + 1) * m1
+    return st["n_vertices"] * per_pt + st["n_sigma"] * per_sigma
+
+
+def check_flops_per_cell(wl) -> int:
+    """FP64 operations of the collision kernel per configuration: per link
+    the own sine/cosine (42), two 3x4 compositions (2 x 63), the link ball's
+    world centre (18) and the ball's culling test against every obstacle
+    (10 per sphere, 30 per box).  Early exits are ignored; the exact tests of
+    the few pairs that pass culling are not counted."""
+    sc = wl.scene
+    d = wl.f.d
+    return d * (42 + 126 + 18) + d * (10 * len(sc.osph_r) + 30 * len(sc.obox_l))
+
+
+def points_flops_per_cell(wl) -> int:
+    """FP64 operations of the intersection-point kernel per traced edge: both
+    ends' coordinates (2 x 2 d^2), both ends' FP64 monomial values with their
+    bound sums (2 x 5 per non-constant monomial), t and the point (3 d + 2)."""
+    from math import comb
+    d, p = wl.f.d, wl.f.p
+    return 2 * (2 * d * d + 5 * (comb(d + p, p) - 1) + 2) + 3 * d + 2
+
+
+def sigma_bytes(st) -> int:
+    """HBM bytes of the coarse n-simplex kernel: each coarse edge record read
+    (16 B), one 8 B key probe per n-coface, and per new coarse simplex its
+    8 B table write and 8 B list write."""
+    return st["n_coarse_edges"] * 16 + st["n_ncofaces"] * 8 + st["n_sigma"] * 16
 
 
 def expand_bytes(st, wl) -> float:
@@ -112,6 +137,21 @@ def expand_bytes(st, wl) -> float:
     new vertex one 8 B key CAS; per traced edge a 16 B append and 2 x 16 B
     frontier reads."""
     return st["n_cofaces"] * 32 + st["n_vertices"] * 8 + st["n_cells"] * 48
+
+
+def host_info():
+    """The host CPU the oracle ran on: model name and the CPUs this process
+    may use (the oracle itself is single-threaded)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
 
 
 def cpu_baseline(wl, budget_s: float = 20.0):
@@ -154,6 +194,7 @@ def cpu_baseline(wl, budget_s: float = 20.0):
         "value": n / total if total > 0 else None,
         "unit": "simplices/s",
         "cores": 1,
+        "host": host_info(),
         "kind": "oracle",
         "sample": f"same f/scale/k/scene traced in a sub-box of half-width {half:.3f} around the first "
                   f"seed: {n} cells, trace {t_trace:.2f}s + points {t_pts:.2f}s + check {t_check:.2f}s",
@@ -297,9 +338,7 @@ def main():
              "fp64": [ip.IP_FP64]}[args.precision]
     runs = {}
     for prec in precs:
-        first = prec == precs[0]
-        runs[prec] = timed_runs(ip, ctx, prob, wl, prec, args.steps if first else max(1, args.steps - 1),
-                                args.warmup if first else 0, budget)
+        runs[prec] = timed_runs(ip, ctx, prob, wl, prec, args.steps, args.warmup, budget)
     prob.close()
     ctx.close()
 
@@ -318,27 +357,48 @@ def main():
                               "points": phase(st, "ms_points"), "check": phase(st, "ms_check")},
                 "edge_hits": s["n_edge_hits"], "edge_set_probes": s["n_shared_probes"],
                 "vertices_evaluated": s["n_vertices"], "fp64_canonical_evals": s["n_fallback"],
-                "settled_by_fp64_monomial": s["n_settled64"]}
+                "settled_by_fp64_monomial": s["n_settled64"],
+                "hip_malloc_per_step": phase(st, "n_hip_malloc"),
+                "step_ms": [round(x["ms_total"] + x["ms_check"], 2) for x in st]}
 
     # roofline of the dominant kernel of the main run, from the library's HIP
     # events around its launches on the context's stream
+    kernels = {}
+    s_last = stats[-1]
+
+    def alu(name, flops, ms, **extra):
+        tfs = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        kernels[name] = {"bound": "alu", "achieved": round(tfs, 3), "peak": VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tfs / VECTOR_PEAK_TFLOPS, 4),
+                         "ms_per_step": round(ms, 3), "flops": int(flops), **extra}
+
+    if wl.scene is not None:
+        alu("check_kernel", check_flops_per_cell(wl) * n_cells, phase(stats, "ms_check"),
+            flops_per_cell=check_flops_per_cell(wl))
     if wl.k > 1 and main_prec == ip.IP_FP32_CERTIFY:
         ms = phase(stats, "ms_subdivide")
-        launches = stats[-1]["subdivide_launches"]
-        flops = subdivide_flops_per_simplex(wl) * stats[-1]["n_sigma"]
-        tfs = flops / (ms * 1e-3) / 1e12
         # one fused launch over every coarse simplex, plus the deferred pass
         # over the few (<1 %) with an unsettled point: the time is the sum
-        roof = {"kernel": "subdivide_kernel (fused, FP32-certified)", "bound": "alu", "achieved": round(tfs, 2),
-                "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tfs / VECTOR_PEAK_TFLOPS, 4),
-                "traffic": subdivide_traffic(wl), "ms_per_step": round(ms, 3), "launches_per_step": launches,
-                "flops_per_coarse_simplex": subdivide_flops_per_simplex(wl)}
+        alu("subdivide_kernel", subdivide_flops(s_last, wl), ms,
+            launches_per_step=s_last["subdivide_launches"], points_evaluated=s_last["n_vertices"],
+            coarse_simplices=s_last["n_sigma"],
+            flops_per_point=2 * wl.f.d ** 2 + nest_flops(wl.f.d, wl.f.p))
+        alu("sub_points_kernel", points_flops_per_cell(wl) * n_cells, phase(stats, "ms_points"),
+            flops_per_cell=points_flops_per_cell(wl))
+        sg_ms = phase(stats, "ms_sigma")
+        gbs = sigma_bytes(s_last) / (sg_ms * 1e-3) / 1e9 if sg_ms > 0 else 0.0
+        kernels["sigma_kernel"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                   "ms_per_step": round(sg_ms, 3), "bytes": sigma_bytes(s_last)}
+        roof = {"kernel": "subdivide_kernel (fused, FP32-certified)", **kernels["subdivide_kernel"],
+                "traffic": subdivide_traffic(wl)}
     else:
         x_ms = phase(stats, "ms_expand")
         gbs = expand_bytes(stats[-1], wl) / (x_ms * 1e-3) / 1e9
         roof = {"kernel": "expand_kernel (2 passes)", "bound": "hbm", "achieved": round(gbs, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                 "ms_per_step": round(x_ms, 3)}
+        kernels["expand_kernel"] = dict(roof)
     out = {
         "metric": METRIC,
         "value": value,
@@ -357,6 +417,7 @@ def main():
                    "cells": n_cells, "free_cells": int(nf), "coarse_simplices": stats[-1]["n_sigma"],
                    "batches": stats[-1]["n_batches"], "levels": stats[-1]["levels"]},
         "roofline": roof,
+        "kernels": kernels,
     }
     for prec in precs:
         out["fp32_certify" if prec == ip.IP_FP32_CERTIFY else "fp64"] = summary(prec)

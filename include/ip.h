@@ -140,6 +140,12 @@ typedef struct {
                               face with no traced coarse edge, which go through
                               the global edge set (all others are emitted once,
                               by the canonical coarse simplex of their face) */
+  double ms_sigma;       /* batch mode: time in the coarse n-simplex kernel */
+  int64_t n_ncofaces;    /* batch mode: n-simplex cofaces of the coarse edges
+                            (with repeats), the probes of that kernel */
+  int64_t n_hip_malloc;  /* device allocations of the call that missed the
+                            context's cache and reached hipMalloc */
+  int64_t hip_malloc_bytes; /* their bytes */
 } ip_stats;
 
 /* Create a context on HIP device `device`; work is issued on `hip_stream`

@@ -18,8 +18,10 @@
  *   orc_trace_batch              pinned (k = 1 equals the direct trace;
  *                                subset of brute force; Fig. 5 template)
  *   orc_points                   pinned (linear f: the point is a root)
- *   orc_sincos, orc_fk           pinned (long-double series, quarter turns)
- *   collision predicates         pinned (textbook clamp distance, hand cases)
+ *   orc_sincos, orc_fk           pinned (library sine/cosine, Rodrigues rotation
+ *                                about every axis, spatial-arm hand poses)
+ *   collision predicates         pinned (textbook clamp distance, hand cases
+ *                                of link spheres against spheres and boxes)
  */
 #include "oracle.h"
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -20,6 +21,12 @@ int ip_hip(ip_ctx *ctx, hipError_t e, const char *what) {
   snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
   (void)hipGetLastError();
   return ip_fail(ctx, e == hipErrorOutOfMemory ? IP_ENOMEM : IP_EDEVICE, buf);
+}
+
+// Allocator diagnostics on stderr when the environment sets IP_LOG.
+static bool alloc_log_on() {
+  static const bool on = getenv("IP_LOG") != nullptr;
+  return on;
 }
 
 int ip_dalloc(ip_ctx *ctx, void **p, size_t bytes) {
@@ -48,6 +55,11 @@ int ip_dalloc(ip_ctx *ctx, void **p, size_t bytes) {
   }
   std::lock_guard<std::mutex> lk(ctx->cache.mu);
   ctx->cache.size_of[*p] = want;
+  ++ctx->n_hip_malloc;
+  ctx->hip_malloc_bytes += (int64_t)want;
+  if (alloc_log_on())
+    fprintf(stderr, "[ip] hipMalloc %.3f GiB (idle cache %.3f GiB)\n", want / 1073741824.0,
+            ctx->cache.idle_bytes / 1073741824.0);
   return IP_OK;
 }
 
@@ -61,6 +73,7 @@ void ip_dfree(ip_ctx *ctx, void *p) {
     // keep the newest blocks: drop the largest idle ones first
     while (!ctx->cache.idle.empty() && ctx->cache.idle_bytes + sz > ctx->cache.limit) {
       auto last = std::prev(ctx->cache.idle.end());
+      if (alloc_log_on()) fprintf(stderr, "[ip] cache evicts %.3f GiB\n", last->first / 1073741824.0);
       (void)hipFree(last->second);
       ctx->cache.size_of.erase(last->second);
       ctx->cache.idle_bytes -= last->first;
@@ -78,7 +91,8 @@ void ip_dfree(ip_ctx *ctx, void *p) {
 
 void ip_cache_release(ip_ctx *ctx) {
   std::lock_guard<std::mutex> lk(ctx->cache.mu);
-  (void)hipDeviceSynchronize();
+  // idle blocks were last used on this context's stream
+  (void)hipStreamSynchronize(ctx->stream);
   for (auto &kv : ctx->cache.idle) {
     (void)hipFree(kv.second);
     ctx->cache.size_of.erase(kv.second);
@@ -313,8 +327,8 @@ void ip_destroy(ip_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  DevBuf *bufs[] = {&ctx->vt_keys, &ctx->vt_vals, &ctx->vt_aux, &ctx->et_keys, &ctx->eval_list,
-                    &ctx->fb_list, &ctx->scratch, &ctx->scene};
+  DevBuf *bufs[] = {&ctx->vtf.keys, &ctx->vtf.eval, &ctx->vtf.vals, &ctx->vtf.fb, &ctx->vtc.keys,
+                    &ctx->vtc.eval, &ctx->vtc.vals, &ctx->vtc.fb, &ctx->vt_aux, &ctx->scratch, &ctx->scene};
   for (DevBuf *b : bufs)
     if (b->p) ip_dfree(ctx, b->p);
   ip_cache_release(ctx);
@@ -415,7 +429,10 @@ int ip_trace(ip_ctx *ctx, const ip_problem *p, uint64_t batch_budget_bytes, int3
   if (!c) return ip_fail(ctx, IP_ENOMEM, "host allocation failed");
   c->ctx = ctx;
   IP_TRY_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+  const int64_t nm0 = ctx->n_hip_malloc, bm0 = ctx->hip_malloc_bytes;
   int rc = ip_trace_impl(ctx, p, batch_budget_bytes, precision, flags, c);
+  c->st.n_hip_malloc = ctx->n_hip_malloc - nm0;
+  c->st.hip_malloc_bytes = ctx->hip_malloc_bytes - bm0;
   if (rc == IP_OK) {
     hipError_t e = hipEventRecord(ctx->ev1, ctx->stream);
     if (e == hipSuccess) e = hipEventSynchronize(ctx->ev1);

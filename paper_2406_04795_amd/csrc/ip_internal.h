@@ -509,17 +509,28 @@ struct DevCache {
   size_t limit = 0;                     // bytes kept idle at most
 };
 
+// Buffers of one vertex table: its VEnt entries, the pending-evaluation
+// list, and in FP32 mode the per-slot bounds and the FP64 fallback list.
+struct VtBufs {
+  DevBuf keys, eval, vals, fb;
+};
+
 struct ip_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
   Counters *ctr_dev = nullptr;
   Counters *ctr_host = nullptr;  // pinned
-  // persistent workspace (grow-only)
-  DevBuf vt_keys;   // vertex table (VEnt entries)
-  DevBuf vt_vals, vt_aux, et_keys, eval_list, fb_list, scratch;
+  // persistent workspace (grow-only): the fine-lattice vertex table (direct
+  // trace, FP64 batch subdivision) and the coarse-lattice one (batch mode),
+  // kept apart so that neither is handed to the other and reallocated
+  VtBufs vtf, vtc;
+  DevBuf vt_aux, scratch;
   DevBuf scene;
   DevCache cache;
+  // device allocations that reached hipMalloc (cache misses), for the stats
+  int64_t n_hip_malloc = 0;
+  int64_t hip_malloc_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int64_t last_fallback = 0;  // FP64 re-evaluations of the last ip_feval
 };

@@ -472,6 +472,7 @@ struct Timer {
 struct Run {
   ip_ctx *ctx;
   const ip_problem *p;
+  VtBufs *tb = nullptr;   // the context buffers that hold this run's vertex table
   LatDev L;
   VEnt *vt = nullptr;
   uint64_t vt_cap = 0;
@@ -532,21 +533,22 @@ int alloc(ip_ctx *ctx, void **p, size_t bytes) { return ip_dalloc(ctx, p, bytes)
 
 void release(ip_ctx *ctx, void *p) { ip_dfree(ctx, p); }
 
-// Vertex table of capacity cap (power of two), reusing the context buffers.
+// Vertex table of capacity cap (power of two), reusing the buffers s.tb.
 int vt_init(Run &s, uint64_t cap) {
   ip_ctx *ctx = s.ctx;
-  IP_TRY(ip_ensure(ctx, ctx->vt_keys, cap * sizeof(VEnt)));
-  IP_TRY(ip_ensure(ctx, ctx->eval_list, cap * 4));
-  s.vt = (VEnt *)ctx->vt_keys.p;
-  s.eval = (uint32_t *)ctx->eval_list.p;
+  VtBufs &tb = *s.tb;
+  IP_TRY(ip_ensure(ctx, tb.keys, cap * sizeof(VEnt)));
+  IP_TRY(ip_ensure(ctx, tb.eval, cap * 4));
+  s.vt = (VEnt *)tb.keys.p;
+  s.eval = (uint32_t *)tb.eval.p;
   s.vt_cap = cap;
   IP_TRY(fill_vt(ctx, s.vt, cap));
   if (s.cert) {
-    IP_TRY(ip_ensure(ctx, ctx->vt_vals, cap * 4));
-    IP_TRY(ip_ensure(ctx, ctx->fb_list, cap * 4));
-    s.vb = (float *)ctx->vt_vals.p;
-    s.fb = (uint32_t *)ctx->fb_list.p;
-    s.fb_cap = ctx->fb_list.bytes / 4;
+    IP_TRY(ip_ensure(ctx, tb.vals, cap * 4));
+    IP_TRY(ip_ensure(ctx, tb.fb, cap * 4));
+    s.vb = (float *)tb.vals.p;
+    s.fb = (uint32_t *)tb.fb.p;
+    s.fb_cap = tb.fb.bytes / 4;
   }
   return IP_OK;
 }
@@ -580,20 +582,21 @@ int vt_grow(Run &s, uint64_t new_cap, uint64_t n_out) {
                      (const VEnt *)nt, new_cap, (uint32_t *)nl, ctx->ctr_dev);
   IP_TRY_HIP(ctx, hipGetLastError());
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  release(ctx, ctx->vt_keys.p);
-  release(ctx, ctx->eval_list.p);
-  ctx->vt_keys = {nt, new_cap * sizeof(VEnt)};
-  ctx->eval_list = {nl, new_cap * 4};
+  VtBufs &tb = *s.tb;
+  release(ctx, tb.keys.p);
+  release(ctx, tb.eval.p);
+  tb.keys = {nt, new_cap * sizeof(VEnt)};
+  tb.eval = {nl, new_cap * 4};
   s.vt = (VEnt *)nt;
   s.eval = (uint32_t *)nl;
   s.vt_cap = new_cap;
   if (s.cert) {
-    release(ctx, ctx->vt_vals.p);
-    ctx->vt_vals = {nvb, new_cap * 4};
+    release(ctx, tb.vals.p);
+    tb.vals = {nvb, new_cap * 4};
     s.vb = (float *)nvb;
-    IP_TRY(ip_ensure(ctx, ctx->fb_list, new_cap * 4));
-    s.fb = (uint32_t *)ctx->fb_list.p;
-    s.fb_cap = ctx->fb_list.bytes / 4;
+    IP_TRY(ip_ensure(ctx, tb.fb, new_cap * 4));
+    s.fb = (uint32_t *)tb.fb.p;
+    s.fb_cap = tb.fb.bytes / 4;
   }
   IP_TRY(remap_out<D>(s, n_out));
   ++s.regrows;
@@ -1323,9 +1326,11 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
       }
       const bool act = (gd >> 16) != 0u && (!trv || cnv);
       const uint32_t cnt = act ? gd >> 16 : 0u;
-      // exclusive prefix sum of cnt over the lanes, one bit plane at a time
+      // exclusive prefix sum of cnt over the lanes, one bit plane at a time;
+      // cnt is the upper half of a 32-bit group word, below 2^16, and the
+      // explicit bound keeps the loop finite whatever the word holds
       uint32_t excl = 0, tot = 0;
-      for (int b = 0; __ballot((cnt >> b) != 0u); ++b) {
+      for (int b = 0; b < 16 && __ballot((cnt >> b) != 0u); ++b) {
         const uint64_t bb = __ballot((cnt >> b) & 1u);
         excl += (uint32_t)__popcll(bb & lt_mask) << b;
         tot += (uint32_t)__popcll(bb) << b;
@@ -2004,13 +2009,14 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   Run f;
   f.ctx = ctx;
   f.p = p;
+  f.tb = &ctx->vtf;
   f.L = p->fine;
   const uint64_t vcap = std::min<uint64_t>(vcap_b, pow2_at_least(B * (uint64_t)NP * 2));
-  IP_TRY(ip_ensure(ctx, ctx->vt_keys, vcap * sizeof(VEnt)));
-  IP_TRY(ip_ensure(ctx, ctx->eval_list, vcap * 4));
+  IP_TRY(ip_ensure(ctx, ctx->vtf.keys, vcap * sizeof(VEnt)));
+  IP_TRY(ip_ensure(ctx, ctx->vtf.eval, vcap * 4));
   IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * (uint64_t)NP * 4));
-  f.vt = (VEnt *)ctx->vt_keys.p;
-  f.eval = (uint32_t *)ctx->eval_list.p;
+  f.vt = (VEnt *)ctx->vtf.keys.p;
+  f.eval = (uint32_t *)ctx->vtf.eval.p;
   f.vt_cap = vcap;
   uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
   BatchSink g(ctx);
@@ -2107,6 +2113,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   Run s;
   s.ctx = ctx;
   s.p = p;
+  s.tb = &ctx->vtc;
   s.L = p->coarse;
   s.cert = cert;
   IP_TRY(vt_init(s, 1ull << 16));
@@ -2118,11 +2125,9 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
       return rc;
     }
   }
-  // the coarse vertex table (visited-edge masks = the coarse trace) stays
-  // for the ownership test; the fine stage gets a table of its own
-  DevTmp cvt_hold(ctx);
-  cvt_hold.p = ctx->vt_keys.p;
-  ctx->vt_keys = DevBuf{};
+  // the coarse vertex table (visited-edge masks = the coarse trace) stays in
+  // ctx->vtc for the ownership test; the fine stage uses ctx->vtf
+  const VEnt *cvt = s.vt;
   const uint64_t cvt_cap = s.vt_cap;
   OutRec *coarse_edges = s.out;
   s.out = nullptr;
@@ -2143,6 +2148,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     }
     IP_TRY(read_ctr(ctx));
     const uint64_t bound = ctx->ctr_host->n_aux;
+    st.n_ncofaces = (int64_t)bound;
     const uint64_t cap = pow2_at_least(bound * 2 + 2);
     int rc = alloc(ctx, &sig_tab, cap * 8);
     if (rc == IP_OK) rc = alloc(ctx, &sig_list, (bound + 1) * 8);
@@ -2153,12 +2159,16 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     }
     IP_TRY(fill(ctx, sig_tab, cap, IP_EMPTY_KEY));
     IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
+    Timer tsg;
     if (nc) {
+      IP_TRY(tsg.start(ctx, &st.ms_sigma));
       hipLaunchKernelGGL((sigma_kernel<D>), dim3(grid_for(nc * 4, 8192)), dim3(kBlock), 0, ctx->stream, p->coarse, LB,
                          coarse_edges, nc, (uint64_t *)sig_tab, cap - 1, (uint64_t *)sig_list, ctx->ctr_dev);
       IP_TRY_HIP(ctx, hipGetLastError());
+      IP_TRY(tsg.stop(ctx));
     }
     IP_TRY(read_ctr(ctx));
+    IP_TRY(tsg.flush(ctx));
     nsig = ctx->ctr_host->n_aux;
     free_coarse();
     release(ctx, sig_tab);
@@ -2183,7 +2193,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   IP_TRY_HIP(ctx, hipMemcpyAsync(tpf_hold.p, T.pf.data(), T.pf.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   const SubArgs a{LB, tpts_hold.as<uint64_t>(), NP, tedge_hold.as<uint32_t>(), NE, tgrp_hold.as<uint32_t>(),
                   tpf_hold.as<uint64_t>(),
-                  cvt_hold.as<VEnt>(), cvt_cap - 1};
+                  cvt, cvt_cap - 1};
   int rc;
   if (cert)
     rc = subdivide_fused<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, st, res);
@@ -2204,8 +2214,8 @@ int direct_points(Run &s, uint64_t n, uint64_t *keys, double *pts, ip_stats &st)
   uint64_t *redo = nullptr;
   if (s.cert) {
     IP_TRY(ip_ensure(ctx, ctx->scratch, n * 8));
-    IP_TRY(ip_ensure(ctx, ctx->fb_list, (2 * n + 64) * 4));
-    s.fb = (uint32_t *)ctx->fb_list.p;
+    IP_TRY(ip_ensure(ctx, s.tb->fb, (2 * n + 64) * 4));
+    s.fb = (uint32_t *)s.tb->fb.p;
     redo = (uint64_t *)ctx->scratch.p;
     IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
     IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_fb));
@@ -2240,11 +2250,12 @@ int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_
   Run s;
   s.ctx = ctx;
   s.p = p;
+  s.tb = &ctx->vtf;
   s.L = p->fine;
   s.cert = cert;
   // start from the largest table the context already holds
   uint64_t vt0 = 1ull << 20;
-  while (vt0 * 2 * sizeof(VEnt) <= ctx->vt_keys.bytes) vt0 *= 2;
+  while (vt0 * 2 * sizeof(VEnt) <= ctx->vtf.keys.bytes) vt0 *= 2;
   IP_TRY(vt_init(s, vt0));
   ip_stats &st = res->st;
   uint64_t n = 0;

@@ -115,9 +115,15 @@ def box(d: int, half: float = PI) -> Domain:
 # --------------------------------------------------------------------------
 # Manifold parameters (numpy evaluation used only to size inputs and seeds)
 # --------------------------------------------------------------------------
-def _f0(fm: Manifold, X: np.ndarray) -> np.ndarray:
-    t = fm.gamma * (X @ fm.sv.T) + fm.coef0
-    return (t ** fm.p) @ fm.alpha
+def _f0(fm: Manifold, X: np.ndarray, chunk: int = 8192) -> np.ndarray:
+    out = np.empty(X.shape[0])
+    for a in range(0, X.shape[0], chunk):
+        t = fm.gamma * (X[a:a + chunk] @ fm.sv.T) + fm.coef0
+        tp = t.copy()
+        for _ in range(fm.p - 1):
+            tp *= t
+        out[a:a + chunk] = tp @ fm.alpha
+    return out
 
 
 def feval_np(fm: Manifold, X: np.ndarray) -> np.ndarray:
@@ -251,8 +257,12 @@ _SPATIAL_AXES = [2, 1, 1, 2, 1, 2, 1]
 
 def spatial_arm_scene(rng, n_links, link=0.3, capsule_r=None, spheres_per_link=0,
                       sphere_r=0.05, n_osph=8, osph_r=(0.1, 0.3), n_obox=0,
-                      obox_l=(0.1, 0.4)) -> Scene:
-    """Spatial nR arm: axes z,y,y,z,y,z,...; links of length `link` along z."""
+                      obox_l=(0.1, 0.4), obst_ball=None) -> Scene:
+    """Spatial nR arm: axes z,y,y,z,y,z,...; links of length `link` along z.
+
+    Obstacle centres are drawn in the reach ball (radii between 0.58 and 1
+    times the reach), or, with obst_ball = (centre, radius), uniformly in that
+    ball (a cluttered workspace around the arm)."""
     joint_T = np.stack([_T() if i == 0 else _T(t=(0, 0, link)) for i in range(n_links)])
     reach = link * n_links
     sc = Scene(joint_T=joint_T, joint_axis=np.array(_SPATIAL_AXES[:n_links], np.int32))
@@ -271,6 +281,8 @@ def spatial_arm_scene(rng, n_links, link=0.3, capsule_r=None, spheres_per_link=0
     def in_ball(n):
         v = rng.standard_normal((n, 3))
         v /= np.linalg.norm(v, axis=1, keepdims=True)
+        if obst_ball is not None:
+            return np.asarray(obst_ball[0], float) + v * (obst_ball[1] * rng.uniform(0.0, 1.0, size=(n, 1)) ** (1 / 3))
         return v * (reach * rng.uniform(0.2, 1.0, size=(n, 1)) ** (1 / 3))
 
     sc.osph_c = in_ball(n_osph)
@@ -334,11 +346,20 @@ def config_c2(seed=0, eps=0.02) -> Workload:
     return w
 
 
+# Scene stream of the d=6 workload: obstacles in a ball of radius 0.9 around
+# the shoulder (0, 0, 0.3), where the arm sits folded at the workload's cells.
+# The stream number was picked so that the cells' verdicts are mixed (about
+# 60 % in collision, estimated with the oracle on cells around each seed by
+# tests/golden/make_c3_scene.py, recorded in tests/golden/c3_scene.json).
+C3_SCENE_STREAM = 204
+C3_OBST_BALL = ((0.0, 0.0, 0.3), 0.9)
+
+
 def config_c3(seed=0, eps=0.002, k=4) -> Workload:
     """d=6, 2000 SVs, degree 3, scale 0.06, batch k; 6R arm, 8 boxes + 8 spheres."""
-    rng = np.random.default_rng(seed + 200)
+    rng = np.random.default_rng(seed + C3_SCENE_STREAM)
     sc = spatial_arm_scene(rng, 6, spheres_per_link=3, sphere_r=0.05,
-                           n_osph=8, n_obox=8)
+                           n_osph=8, n_obox=8, obst_ball=C3_OBST_BALL)
     w = cubic_case(6, 2000, 0.06, eps, seed=seed, k=k, scene=sc)
     w.name = f"d6_S2000_p3_lam0.06_k{k}"
     return w

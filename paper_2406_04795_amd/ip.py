@@ -58,7 +58,8 @@ class ip_stats(C.Structure):
                 ("ms_total", C.c_double), ("ms_feval", C.c_double), ("ms_expand", C.c_double),
                 ("ms_points", C.c_double), ("ms_check", C.c_double), ("ms_subdivide", C.c_double),
                 ("subdivide_launches", C.c_int64), ("n_edge_hits", C.c_int64),
-                ("n_coarse_edges", C.c_int64), ("n_shared_probes", C.c_int64)]
+                ("n_coarse_edges", C.c_int64), ("n_shared_probes", C.c_int64),
+                ("ms_sigma", C.c_double), ("n_ncofaces", C.c_int64), ("n_hip_malloc", C.c_int64), ("hip_malloc_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
