@@ -187,8 +187,15 @@ int ip_cells_points(const ip_cells *c, const double **pts_dev, int64_t *ld);
 /* Order-independent digest of the traced set: digest[0] = sum and
  * digest[1] = xor, over the cells, of the SplitMix64 finalizer of the packed
  * edge key (the set is unique, its order is not).  Device-side; two 8-byte
- * host outputs. */
+ * host outputs.  The packed key of cell (v, mask) is
+ *   sum_j (v_j - vmin_j) << (j * bits)  |  mask << (d * bits)
+ * with bits and vmin from ip_cells_key_layout; the finalizer is
+ * z ^= z >> 30; z *= 0xbf58476d1ce4e5b9; z ^= z >> 27; z *= 0x94d049bb133111eb;
+ * z ^= z >> 31 (mod 2^64). */
 int ip_cells_digest(ip_ctx *ctx, const ip_cells *c, uint64_t digest[2]);
+/* Key layout of the cells (host outputs): bits per coordinate and vmin (d
+ * int32), fixed by the domain box and the lattice frame. */
+int ip_cells_key_layout(const ip_cells *c, int32_t *bits, int32_t *vmin);
 /* Copy rows idx[0 .. n) (host array, each in [0, count)) of the cells to the
  * host: vertex v (n x d), mask, point (n x d, row-major) and, once
  * ip_check_cells has run, the verdict.  Any output may be NULL.  An index out
@@ -217,6 +224,37 @@ int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict,
  * bound used (0 for FP64 results). */
 int ip_feval(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n,
              int32_t precision, double *f_dev, double *bound_dev);
+
+/* The first certified tier of batch subdivision (Sec. V-B, Eq. 1-2 with the
+ * FP32 certification), on given coarse simplices, for inspection: the fused
+ * subdivision evaluates each template point of a coarse simplex (v, w) in
+ * FP32 (nested monomial form) and settles its sign when |f32| exceeds one
+ * bound per simplex, B1 + B64, formed from the largest |x_j| over the
+ * simplex's vertices.  simplex_dev: device, n x 2d int32 rows (coarse vertex
+ * v, then the coordinate order w, a permutation of 0..d-1).  Outputs
+ * (device): y_dev n x NP x d int32 (fine vertex of template point t of
+ * simplex s: y_{w_i} = k v_{w_i} + u_i), f_dev n x NP (the FP32 value, NaN
+ * outside the box), bound_dev n (B1 + B64).  *n_points receives NP =
+ * C(d + k, d); with y_dev NULL only NP is returned.  k is the problem's
+ * coarse_k.  IP_EINVAL when the degree has no FP32 form (above 4). */
+int ip_region_eval(ip_ctx *ctx, const ip_problem *p, const int32_t *simplex_dev, int64_t n,
+                   int32_t *y_dev, double *f_dev, double *bound_dev, int32_t *n_points);
+
+/* The same evaluation for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It calls no hipMalloc, hipFree or allocating library routine
+ * and never waits for the device: the FP64 fallback list and its counters
+ * live in a fixed device scratch array of 256 + 4 * IP_NOALLOC_MAX_VERTICES
+ * bytes (4 MiB), one per device, held until the process ends.  n above
+ * IP_NOALLOC_MAX_VERTICES is IP_EINVAL.  Arguments and results are those of
+ * ip_feval (bound_dev may be NULL); the work is queued on the context's
+ * stream.  Every call on one device shares that device's scratch, which
+ * keeps the last call's contents (the call clears its counters itself):
+ * calls that overlap on one device (two streams, or two host threads) race,
+ * so serialise them. */
+#define IP_NOALLOC_MAX_VERTICES 1048576
+int ip_feval_noalloc(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n,
+                     int32_t precision, double *f_dev, double *bound_dev);
 
 /* ------------------------------------------------------------------------
  * Serving loop (the proof requests of the planning loop, Sec. IV-A / Fig. 1:

@@ -87,6 +87,8 @@ def lib():
         L.orc_template.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int64), _ip,
                                    C.POINTER(C.c_int64), _ip, _up]
         L.orc_points.argtypes = [C.POINTER(_F), C.POINTER(_Space), C.c_int64, _ip, _up, _dp, _dp]
+        L.orc_points_refined.argtypes = [C.POINTER(_F), C.POINTER(_Space), C.c_int64, _ip, _up, C.c_int32,
+                                         _dp]
         L.orc_sincos.argtypes = [C.c_double, _dp, _dp]
         L.orc_sphere_sphere.argtypes = [_dp, C.c_double, _dp, C.c_double]
         L.orc_capsule_sphere.argtypes = [_dp, _dp, C.c_double, _dp, C.c_double]
@@ -270,6 +272,18 @@ def points(wl, v, mask):
     lib().orc_points(C.byref(c.f), C.byref(c.sp), n, pv, mask.ctypes.data_as(_up),
                      pts.ctypes.data_as(_dp), t.ctypes.data_as(_dp))
     return pts, t
+
+
+def points_refined(wl, v, mask, iters):
+    """Intersection points after `iters` false-position (Illinois) steps."""
+    c = _Ctx(wl.f, wl.lat, wl.dom)
+    v, pv = _i(v)
+    mask = np.ascontiguousarray(mask, np.uint32)
+    n = v.shape[0]
+    pts = np.zeros((n, wl.f.d), np.float64)
+    _check(lib().orc_points_refined(C.byref(c.f), C.byref(c.sp), n, pv, mask.ctypes.data_as(_up), iters,
+                                    pts.ctypes.data_as(_dp)), "points_refined")
+    return pts
 
 
 def sincos(q):

@@ -18,6 +18,10 @@
  *   orc_trace_batch              pinned (k = 1 equals the direct trace;
  *                                subset of brute force; Fig. 5 template)
  *   orc_points                   pinned (linear f: the point is a root)
+ *   orc_points_refined           pinned (zero iterations equal orc_points;
+ *                                linear f exact; sphere radius error shrinks
+ *                                to rounding; converged points equal a
+ *                                library root finder's)
  *   orc_sincos, orc_fk           pinned (library sine/cosine, Rodrigues rotation
  *                                about every axis, spatial-arm hand poses)
  *   collision predicates         pinned (textbook clamp distance, hand cases
@@ -691,6 +695,41 @@ int orc_points(const orc_fparams *f, const orc_space *sp, int64_t n,
     double tt = fa / (fa - fb);
     if (t) t[i] = tt;
     for (int j = 0; j < d; ++j) pts[i * d + j] = fma(tt, xb[j] - xa[j], xa[j]);
+  }
+  return 0;
+}
+
+int orc_points_refined(const orc_fparams *f, const orc_space *sp, int64_t n,
+                       const int32_t *v, const uint32_t *mask, int32_t iters,
+                       double *pts) {
+  if (iters < 0) return -2;
+  const int d = sp->d;
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t bv[ORC_MAXD];
+    double a[ORC_MAXD], b[ORC_MAXD], m[ORC_MAXD];
+    for (int j = 0; j < d; ++j) bv[j] = v[i * d + j] + (int32_t)((mask[i] >> j) & 1u);
+    orc_coords(sp, v + i * d, a);
+    orc_coords(sp, bv, b);
+    double fa = orc_f(f, a), fb = orc_f(f, b);
+    int last = 0; /* -1: a moved last, +1: b moved last */
+    for (int it = 0; it < iters; ++it) {
+      double t = fa / (fa - fb);
+      for (int j = 0; j < d; ++j) m[j] = fma(t, b[j] - a[j], a[j]);
+      double fm = orc_f(f, m);
+      if (sign_bit(fm) == sign_bit(fa)) {
+        memcpy(a, m, sizeof(double) * (size_t)d);
+        fa = fm;
+        if (last == -1) fb = 0.5 * fb;
+        last = -1;
+      } else {
+        memcpy(b, m, sizeof(double) * (size_t)d);
+        fb = fm;
+        if (last == 1) fa = 0.5 * fa;
+        last = 1;
+      }
+    }
+    double t = fa / (fa - fb);
+    for (int j = 0; j < d; ++j) pts[i * d + j] = fma(t, b[j] - a[j], a[j]);
   }
   return 0;
 }

@@ -120,6 +120,19 @@ int orc_template(int32_t d, int32_t k, int64_t *n_pts, int32_t *pts,
 int orc_points(const orc_fparams *f, const orc_space *sp, int64_t n,
                const int32_t *v, const uint32_t *mask, double *pts, double *t);
 
+/* Intersection points computed iteratively (Sec. V-B; Sec. VI: the point
+ * is refined until a desired accuracy).  The edge (a, b), a the smaller
+ * endpoint, brackets the crossing: s(a) != s(b).  Each iteration is a false
+ * position step with the Illinois modification (Dowell & Jarratt 1971):
+ * t = f_a / (f_a - f_b), m_j = fma(t, x_b,j - x_a,j, x_a,j), f_m = f(m) in the
+ * canonical order; the end whose sign bit equals s(m) = !(f_m < 0) moves to
+ * m, and when the same end moves twice in a row the value kept at the other
+ * end is halved.  After `iters` iterations the point is the false position
+ * point of the final bracket; iters = 0 gives orc_points. */
+int orc_points_refined(const orc_fparams *f, const orc_space *sp, int64_t n,
+                       const int32_t *v, const uint32_t *mask, int32_t iters,
+                       double *pts);
+
 /* Collision scene (Sec. V-C and Appendix A).  Robot: d revolute joints,
  * T_i = T_{i-1} * J_i * Rot(axis_i, q_i), T_{-1} = I.  Geometry in link
  * frames; obstacles in the world frame.  3x4 transforms are row-major

@@ -311,6 +311,14 @@ int ip_create(ip_ctx **out, int device, void *stream) {
     return IP_EDEVICE;
   }
   memset(ctx->ctr_host, 0, sizeof(Counters));
+  if (ip_noalloc_setup(ctx) != IP_OK) {
+    (void)hipFree(ctx->ctr_dev);
+    (void)hipHostFree(ctx->ctr_host);
+    (void)hipEventDestroy(ctx->ev0);
+    (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+    return IP_EDEVICE;
+  }
   {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
@@ -650,6 +658,38 @@ int ip_feval(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, 
   IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
   if (n == 0) return IP_OK;
   return ip_feval_impl(ctx, p, v_dev, n, precision, f_dev, bound_dev);
+}
+
+int ip_region_eval(ip_ctx *ctx, const ip_problem *p, const int32_t *simplex_dev, int64_t n, int32_t *y_dev,
+                   double *f_dev, double *bound_dev, int32_t *n_points) {
+  if (!ctx) return IP_EINVAL;
+  if (!p || !n_points || n < 0 || (n > 0 && y_dev && (!simplex_dev || !f_dev || !bound_dev)))
+    return ip_fail(ctx, IP_EINVAL, "ip_region_eval: bad arguments");
+  if (p->ctx != ctx) return ip_fail(ctx, IP_EINVAL, "problem belongs to another context");
+  if (!p->poly.ok) return ip_fail(ctx, IP_EINVAL, "ip_region_eval: no FP32 form for this degree");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  return ip_region_eval_impl(ctx, p, simplex_dev, n, y_dev, f_dev, bound_dev, n_points);
+}
+
+int ip_cells_key_layout(const ip_cells *c, int32_t *bits, int32_t *vmin) {
+  if (!c || !bits || !vmin) return IP_EINVAL;
+  *bits = c->B;
+  for (int j = 0; j < c->d; ++j) vmin[j] = c->vmin[j];
+  return IP_OK;
+}
+
+int ip_feval_noalloc(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, int32_t precision,
+                     double *f_dev, double *bound_dev) {
+  if (!ctx) return IP_EINVAL;
+  if (!p || (n > 0 && (!v_dev || !f_dev)) || n < 0) return ip_fail(ctx, IP_EINVAL, "ip_feval_noalloc: bad arguments");
+  if (p->ctx != ctx) return ip_fail(ctx, IP_EINVAL, "problem belongs to another context");
+  if (precision != IP_FP64 && precision != IP_FP32_CERTIFY) return ip_fail(ctx, IP_EINVAL, "unknown precision");
+  if (n > IP_NOALLOC_MAX_VERTICES)
+    return ip_fail(ctx, IP_EINVAL, "ip_feval_noalloc: at most " + std::to_string(IP_NOALLOC_MAX_VERTICES) +
+                                       " vertices per call (the size of its device scratch)");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  if (n == 0) return IP_OK;
+  return ip_feval_noalloc_impl(ctx, p, v_dev, n, precision, f_dev, bound_dev);
 }
 
 }  // extern "C"

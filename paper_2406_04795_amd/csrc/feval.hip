@@ -17,7 +17,18 @@
 // |f32| > B32 + B64 has sign(f32) = sign(F) = sign(f64); every other vertex
 // is re-evaluated by the canonical FP64 kernel, so the sign bits, and the
 // traced set, equal the FP64 ones.
+#include <algorithm>
+#include <mutex>
+
 #include "ip_internal.h"
+
+// Device scratch of ip_feval_noalloc, one copy per device at its own
+// address: a 256-byte header holding two counters (the fallback-list length
+// and the FP64-monomial settlements), then the fallback list, one 4-byte
+// vertex index per vertex of the largest call.  Host code never passes this
+// name to a kernel: it passes the address hipGetSymbolAddress returned for
+// the current device (noalloc_scratch of the context).
+static __device__ __align__(256) unsigned char scratch[256 + 4 * (size_t)IP_NOALLOC_MAX_VERTICES];
 
 namespace {
 
@@ -25,12 +36,16 @@ namespace {
 //         to out[slot * 4]);
 // MODE 1: raw int32 vertices, result to out[i];
 // MODE 2: raw int32 vertices at the indices in list, result to out[index].
+// n_dev (may be NULL): the item count is *n_dev, written by an earlier
+// kernel on the stream, at most n (the grid is sized for n).
 template <int D, int P, int R, int MODE>
 __global__ __launch_bounds__(256) void feval64_kernel(FDev F, LatDev L, const uint32_t *__restrict__ list,
-                                                      uint64_t n, const uint64_t *__restrict__ keys,
+                                                      uint64_t n, const unsigned long long *n_dev,
+                                                      const uint64_t *__restrict__ keys,
                                                       const int32_t *__restrict__ vraw,
                                                       double *__restrict__ out) {
   constexpr uint64_t S4 = MODE == 0 ? 4 : 1;
+  if (n_dev) n = (uint64_t)*n_dev < n ? (uint64_t)*n_dev : n;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * R;
   for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * R; base < n; base += stride) {
     double x[R][D];
@@ -85,40 +100,41 @@ __global__ __launch_bounds__(256) void feval64_kernel(FDev F, LatDev L, const ui
 
 template <int D, int P, int MODE>
 void launch64(hipStream_t st, const FDev &F, const LatDev &L, const uint32_t *list, uint64_t n,
-              const uint64_t *keys, const int32_t *vraw, double *out) {
+              const unsigned long long *n_dev, const uint64_t *keys, const int32_t *vraw, double *out) {
   constexpr int R = D <= 4 ? 4 : 2;
   const uint64_t threads = (n + R - 1) / R;
   uint64_t blocks = (threads + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) return;
-  hipLaunchKernelGGL((feval64_kernel<D, P, R, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, F, L, list, n, keys,
-                     vraw, out);
+  hipLaunchKernelGGL((feval64_kernel<D, P, R, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, F, L, list, n, n_dev,
+                     keys, vraw, out);
 }
 
 template <int D, int MODE>
 void launch64_p(hipStream_t st, const FDev &F, const LatDev &L, const uint32_t *list, uint64_t n,
-                const uint64_t *keys, const int32_t *vraw, double *out) {
+                const unsigned long long *n_dev, const uint64_t *keys, const int32_t *vraw, double *out) {
   switch (F.p) {
-    case 1: launch64<D, 1, MODE>(st, F, L, list, n, keys, vraw, out); break;
-    case 2: launch64<D, 2, MODE>(st, F, L, list, n, keys, vraw, out); break;
-    case 3: launch64<D, 3, MODE>(st, F, L, list, n, keys, vraw, out); break;
-    case 4: launch64<D, 4, MODE>(st, F, L, list, n, keys, vraw, out); break;
-    default: launch64<D, 0, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 1: launch64<D, 1, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
+    case 2: launch64<D, 2, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
+    case 3: launch64<D, 3, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
+    case 4: launch64<D, 4, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
+    default: launch64<D, 0, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
   }
 }
 
 template <int MODE>
 int dispatch64(ip_ctx *ctx, const FDev &F, const LatDev &L, const uint32_t *list, uint64_t n,
-               const uint64_t *keys, const int32_t *vraw, double *out) {
+               const uint64_t *keys, const int32_t *vraw, double *out,
+               const unsigned long long *n_dev = nullptr) {
   if (n == 0) return IP_OK;
   hipStream_t st = ctx->stream;
   switch (L.d) {
-    case 2: launch64_p<2, MODE>(st, F, L, list, n, keys, vraw, out); break;
-    case 3: launch64_p<3, MODE>(st, F, L, list, n, keys, vraw, out); break;
-    case 4: launch64_p<4, MODE>(st, F, L, list, n, keys, vraw, out); break;
-    case 5: launch64_p<5, MODE>(st, F, L, list, n, keys, vraw, out); break;
-    case 6: launch64_p<6, MODE>(st, F, L, list, n, keys, vraw, out); break;
-    case 7: launch64_p<7, MODE>(st, F, L, list, n, keys, vraw, out); break;
+    case 2: launch64_p<2, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
+    case 3: launch64_p<3, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
+    case 4: launch64_p<4, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
+    case 5: launch64_p<5, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
+    case 6: launch64_p<6, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
+    case 7: launch64_p<7, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
     default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
   }
   IP_TRY_HIP(ctx, hipGetLastError());
@@ -176,7 +192,7 @@ __global__ __launch_bounds__(256) void feval32_kernel(PolyDev Q, LatDev L, const
         vb[id] = unsure ? -1.0f : (float)(bnd * (1.0 + 1e-6));
       } else {
         out[i] = fv;
-        bout[i] = unsure ? 0.0 : bnd + Q.B64;
+        if (bout) bout[i] = unsure ? 0.0 : bnd + Q.B64;
       }
     }
     stage_put<kStage>(st[wib], sn, unsure, id, put, fb_ctr);
@@ -212,8 +228,9 @@ void launch32_p(hipStream_t st, const PolyDev &Q, const LatDev &L, const uint32_
 
 template <int MODE>
 int dispatch32(ip_ctx *ctx, const PolyDev &Q, const LatDev &L, const uint32_t *list, uint64_t n, VEnt *vt, float *vb,
-               const int32_t *vraw, double *out, double *bout, uint32_t *fb, unsigned long long *fb_ctr) {
-  unsigned long long *c64 = &ctx->ctr_dev->n_cert64;
+               const int32_t *vraw, double *out, double *bout, uint32_t *fb, unsigned long long *fb_ctr,
+               unsigned long long *c64 = nullptr) {
+  if (!c64) c64 = &ctx->ctr_dev->n_cert64;
   if (n == 0) return IP_OK;
   hipStream_t st = ctx->stream;
   switch (L.d) {
@@ -229,7 +246,58 @@ int dispatch32(ip_ctx *ctx, const PolyDev &Q, const LatDev &L, const uint32_t *l
   return IP_OK;
 }
 
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+__global__ void fill_f64_kernel(double *p, uint64_t n, double v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {nullptr};
+
 }  // namespace
+
+int ip_noalloc_setup(ip_ctx *ctx) {
+  if (ctx->device < 0 || ctx->device >= 64) return ip_fail(ctx, IP_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    // the device is current (ip_create set it): its own copy of the array
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return ip_hip(ctx, e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[ctx->device] = ptr;
+  }
+  ctx->noalloc_scratch = g_scratch_ptr[ctx->device];
+  return IP_OK;
+}
+
+// Same kernels and launch shapes as ip_feval_impl, with the fallback list and
+// its counters in the device scratch and the FP64 pass sized on the device
+// (it reads the list length the FP32 pass left), so nothing is allocated and
+// nothing waits for the host.
+int ip_feval_noalloc_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, int32_t prec,
+                          double *f_dev, double *bound_dev) {
+  if (!ctx->noalloc_scratch) return ip_fail(ctx, IP_EDEVICE, "device scratch not set up");
+  hipStream_t st = ctx->stream;
+  if (prec == IP_FP64 || !p->poly.ok) {
+    if (bound_dev) {
+      const uint64_t blocks = std::min<uint64_t>(((uint64_t)n + 255) / 256, 4096);
+      hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, st, bound_dev, (uint64_t)n, 0.0);
+      IP_TRY_HIP(ctx, hipGetLastError());
+    }
+    return dispatch64<1>(ctx, p->f, p->fine, nullptr, (uint64_t)n, nullptr, v_dev, f_dev);
+  }
+  unsigned long long *hdr = (unsigned long long *)ctx->noalloc_scratch;
+  uint32_t *fbl = (uint32_t *)((unsigned char *)ctx->noalloc_scratch + 256);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, hdr, 2);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  IP_TRY(dispatch32<1>(ctx, p->poly, p->fine, nullptr, (uint64_t)n, nullptr, nullptr, v_dev, f_dev, bound_dev, fbl,
+                       hdr, hdr + 1));
+  return dispatch64<2>(ctx, p->f, p->fine, fbl, (uint64_t)n, nullptr, v_dev, f_dev, hdr);
+}
 
 int launch_feval64(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n_list,
                    VEnt *vt) {
@@ -262,14 +330,17 @@ int ip_feval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_
     return dispatch64<1>(ctx, p->f, p->fine, nullptr, (uint64_t)n, nullptr, v_dev, f_dev);
   }
   // FP32 pass, then canonical FP64 for the unsettled indices
+  if (n >= (1ll << 32)) return ip_fail(ctx, IP_EINVAL, "ip_feval: at most 2^32 - 1 vertices per call");
   double *bnd = bound_dev;
   void *tmp_b = nullptr, *fbl = nullptr;
   if (!bnd) {
     IP_TRY(ip_dalloc(ctx, &tmp_b, sizeof(double) * (size_t)n));
     bnd = (double *)tmp_b;
   }
-  if (n >= (1ll << 32)) return ip_fail(ctx, IP_EINVAL, "ip_feval: at most 2^32 - 1 vertices per call");
-  IP_TRY(ip_dalloc(ctx, &fbl, sizeof(uint32_t) * (size_t)n));
+  if (ip_dalloc(ctx, &fbl, sizeof(uint32_t) * (size_t)n) != IP_OK) {
+    ip_dfree(ctx, tmp_b);
+    return IP_ENOMEM;
+  }
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
   int rc = dispatch32<1>(ctx, p->poly, p->fine, nullptr, (uint64_t)n, nullptr, nullptr, v_dev, f_dev, bnd,
                          (uint32_t *)fbl, &ctx->ctr_dev->n_fb);

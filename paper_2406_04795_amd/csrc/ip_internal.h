@@ -528,6 +528,8 @@ struct ip_ctx {
   DevBuf vt_aux, scratch;
   DevBuf scene;
   DevCache cache;
+  // this device's copy of the scratch array of ip_feval_noalloc
+  void *noalloc_scratch = nullptr;
   // device allocations that reached hipMalloc (cache misses), for the stats
   int64_t n_hip_malloc = 0;
   int64_t hip_malloc_bytes = 0;
@@ -590,6 +592,13 @@ int ip_trace_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t pre
                   ip_cells *out);
 int ip_feval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, int32_t prec,
                   double *f_dev, double *bound_dev);
+int ip_feval_noalloc_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, int32_t prec,
+                          double *f_dev, double *bound_dev);
+int ip_region_eval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, int64_t n, int32_t *y, double *f,
+                        double *bound, int32_t *np_out);
+// Looks up this device's address of the ip_feval_noalloc scratch (once per
+// device) and stores it in ctx; the device must be current.
+int ip_noalloc_setup(ip_ctx *ctx);
 int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n, int64_t ld,
                   uint8_t *verdict_dev);
 int ip_check_gather_impl(ip_ctx *ctx, const ip_scene *scene, ip_cells *c);

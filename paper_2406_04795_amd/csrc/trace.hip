@@ -2289,7 +2289,106 @@ int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_
   return IP_OK;
 }
 
+// The tier-1 evaluation of the fused subdivision on given coarse simplices
+// (Sec. V-B, Eq. 1-2: the template points of each), for inspection: one wave
+// per simplex forms the region bound B1 from the largest |x_j| over the
+// simplex's vertices exactly as the subdivision kernel does, then every
+// template point gets its fine vertex y, its nested FP32 value (NaN outside
+// the box) and the simplex its bound B1 + B64.
+template <int D, int P>
+__global__ __launch_bounds__(256) void region_eval_kernel(LatDev Lf, int k, const int32_t *__restrict__ simp,
+                                                          uint64_t n, const uint64_t *__restrict__ tpts, int NP,
+                                                          PolyDev Q, int32_t *yout, double *fout, double *bout) {
+  __shared__ double va[4][(D + 1) * D];
+  __shared__ double Xs[4][8];
+  const int wib = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t s = wave; s < n; s += n_waves) {
+    int32_t v[D], w[D], winv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      v[j] = simp[s * 2 * D + j];
+      w[j] = simp[s * 2 * D + D + j];
+    }
+    perm_inverse<D>(w, winv);
+    const int vi = lane <= D ? lane : D;
+    int32_t yv[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) yv[c] = k * v[c] + (winv[c] < vi ? k : 0);
+    double xv[D];
+    lat_coords<D>(Lf, yv, xv);
+    if (lane <= D) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) va[wib][lane * D + j] = fabs(xv[j]);
+    }
+    wave_lds_sync();
+    if (lane < D) {
+      double a = 0.0;
+#pragma unroll
+      for (int i = 0; i <= D; ++i) a = fmax(a, va[wib][i * D + lane]);
+      Xs[wib][lane] = a * (1.0 + 1e-12) + 1e-300;
+    }
+    wave_lds_sync();
+    const double B1 = Q.K32n * region_sabs_bound(Q, Xs[wib], lane) + Q.E0;
+    if (lane == 0) bout[s] = B1 + Q.B64;
+    for (int pt = lane; pt < NP; pt += 64) {
+      int32_t y[D];
+      template_point_inv<D>(v, winv, k, tpts[pt], y);
+      double x[D];
+      lat_coords<D>(Lf, y, x);
+      double fv = __longlong_as_double(0x7ff8000000000000ll);
+      if (lat_in_box<D>(Lf, x)) (void)cert_eval_region<D, P>(Q, x, B1, &fv);
+      const uint64_t o = s * (uint64_t)NP + (uint64_t)pt;
+      fout[o] = fv;
+#pragma unroll
+      for (int j = 0; j < D; ++j) yout[o * D + j] = y[j];
+    }
+    wave_lds_sync();
+  }
+}
+
+template <int D>
+int region_eval_T(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, int64_t n, int32_t *y, double *f,
+                  double *bound, int32_t *np_out) {
+  const int k = p->k;
+  Template T = make_template(D, k);
+  const int NP = (int)T.pts.size();
+  *np_out = NP;
+  if (!y || n == 0) return IP_OK;
+  DevTmp tp(ctx);
+  IP_TRY(tp.get(T.pts.size() * 8));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(tp.p, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  const unsigned blocks = (unsigned)std::min<uint64_t>(((uint64_t)n + 3) / 4, 4096);
+#define IP_RE(PP)                                                                                                 \
+  hipLaunchKernelGGL((region_eval_kernel<D, PP>), dim3(blocks), dim3(256), 0, ctx->stream, p->fine, k, simp,      \
+                     (uint64_t)n, tp.as<uint64_t>(), NP, p->poly, y, f, bound)
+  switch (p->poly.p) {
+    case 1: IP_RE(1); break;
+    case 2: IP_RE(2); break;
+    case 3: IP_RE(3); break;
+    default: IP_RE(4); break;
+  }
+#undef IP_RE
+  IP_TRY_HIP(ctx, hipGetLastError());
+  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return IP_OK;
+}
+
 }  // namespace
+
+int ip_region_eval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, int64_t n, int32_t *y, double *f,
+                        double *bound, int32_t *np_out) {
+  switch (p->d) {
+    case 2: return region_eval_T<2>(ctx, p, simp, n, y, f, bound, np_out);
+    case 3: return region_eval_T<3>(ctx, p, simp, n, y, f, bound, np_out);
+    case 4: return region_eval_T<4>(ctx, p, simp, n, y, f, bound, np_out);
+    case 5: return region_eval_T<5>(ctx, p, simp, n, y, f, bound, np_out);
+    case 6: return region_eval_T<6>(ctx, p, simp, n, y, f, bound, np_out);
+    case 7: return region_eval_T<7>(ctx, p, simp, n, y, f, bound, np_out);
+    default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
+  }
+}
 
 int ip_trace_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, uint32_t flags,
                   ip_cells *out) {

@@ -102,6 +102,9 @@ _sig = {
     "ip_check_cells": (C.c_int, [_vp, _vp, _P(ip_scene), _P(C.c_int64)]),
     "ip_cells_download_check": (C.c_int, [_vp, _vp, C.POINTER(C.c_uint8), _dp]),
     "ip_feval": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, _vp, _vp]),
+    "ip_feval_noalloc": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, _vp, _vp]),
+    "ip_region_eval": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp, _P(C.c_int32)]),
+    "ip_cells_key_layout": (C.c_int, [_vp, _P(C.c_int32), _P(C.c_int32)]),
     "ip_server_create": (C.c_int, [_P(_vp), C.c_int, C.c_uint64, C.c_int32]),
     "ip_server_submit": (C.c_int, [_vp, _P(ip_request), _P(C.c_uint64)]),
     "ip_server_poll": (C.c_int, [_vp, C.c_uint64, _P(_P(ip_result))]),
@@ -278,6 +281,29 @@ def ip_feval(ctx, prob, v_dev_ptr: int, n: int, precision, f_dev_ptr: int, bound
     _chk(ctx, _lib.ip_feval(ctx, prob, v_dev_ptr, n, precision, f_dev_ptr, bound_dev_ptr or None))
 
 
+def ip_region_eval(ctx, prob, simplex_dev_ptr: int, n: int, y_dev_ptr: int = 0, f_dev_ptr: int = 0,
+                   bound_dev_ptr: int = 0) -> int:
+    """Returns NP, the template points per coarse simplex."""
+    np_out = C.c_int32()
+    _chk(ctx, _lib.ip_region_eval(ctx, prob, simplex_dev_ptr or None, n, y_dev_ptr or None, f_dev_ptr or None,
+                                  bound_dev_ptr or None, C.byref(np_out)))
+    return np_out.value
+
+
+def ip_cells_key_layout(cells, d):
+    bits = C.c_int32()
+    vmin = np.zeros(8, np.int32)
+    _chk(None, _lib.ip_cells_key_layout(cells, C.byref(bits), vmin.ctypes.data_as(_ip)))
+    return bits.value, vmin[:d].copy()
+
+
+IP_NOALLOC_MAX_VERTICES = 1048576
+
+
+def ip_feval_noalloc(ctx, prob, v_dev_ptr: int, n: int, precision, f_dev_ptr: int, bound_dev_ptr: int = 0):
+    _chk(ctx, _lib.ip_feval_noalloc(ctx, prob, v_dev_ptr, n, precision, f_dev_ptr, bound_dev_ptr or None))
+
+
 # --------------------------------------------------------------------------
 # Small conveniences over the same calls (still marshalling only)
 # --------------------------------------------------------------------------
@@ -333,6 +359,9 @@ class Cells:
 
     def digest(self):
         return ip_cells_digest(self.ctx.h, self.h)
+
+    def key_layout(self):
+        return ip_cells_key_layout(self.h, self.d)
 
     def gather(self, idx, verdict=False):
         return ip_cells_gather(self.ctx.h, self.h, self.d, idx, verdict)

@@ -1,0 +1,125 @@
+"""ip_feval_noalloc (the entry point for callers that cannot allocate) against
+ip_feval on the same inputs: values and bounds bit for bit, on two calls in
+a row (the second smaller, so stale scratch contents would show), in both
+precisions, with vertices that the FP32 bound cannot settle (exact zeros of
+f and the cancellation stress), at the scratch's maximum size, and the size
+limit as an error."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2406_04795_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ip():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    from paper_2406_04795_amd import ip as _ip
+    return _ip
+
+
+@pytest.fixture(scope="module")
+def ctx(ip):
+    c = ip.Context(0)
+    yield c
+    c.close()
+
+
+def _eval(ip, ctx, prob, V, prec, noalloc, with_bound=True):
+    import torch
+    n = V.shape[0]
+    vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    fd = torch.full((max(n, 1),), np.nan, dtype=torch.float64, device="cuda")
+    bd = torch.full((max(n, 1),), np.nan, dtype=torch.float64, device="cuda")
+    fn = ip.ip_feval_noalloc if noalloc else ip.ip_feval
+    fn(ctx.h, prob.h, vd.data_ptr(), n, prec, fd.data_ptr(), bd.data_ptr() if with_bound else 0)
+    torch.cuda.synchronize()
+    return fd.cpu().numpy()[:n], bd.cpu().numpy()[:n]
+
+
+def _dyadic_vertices(rng, n, d=3):
+    """Random vertices of the lattice x = v / 8 plus the 6 on the unit
+    sphere's axes, where f = |x|^2 - 1 is exactly 0."""
+    V = rng.integers(-12, 13, size=(n, d)).astype(np.int32)
+    on = np.concatenate([8 * np.eye(d, dtype=np.int32), -8 * np.eye(d, dtype=np.int32)])
+    V[: len(on)] = on
+    return V[rng.permutation(n)]
+
+
+CASES = {
+    "dyadic_sphere_d3": lambda: I.dyadic_sphere_case(),
+    "stress_d5": lambda: I.config_c5(lam=0.35, eps=3e-3),
+}
+
+
+def _vertices(name, wl, rng, n):
+    if name == "dyadic_sphere_d3":
+        return _dyadic_vertices(rng, n)
+    d = wl.f.d
+    Y = rng.uniform(wl.dom.lo * 0.95, wl.dom.hi * 0.95, size=(n, d))
+    return np.floor((Y - wl.lat.o) @ wl.lat.Minv.T).astype(np.int32)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
+def test_noalloc_equals_feval_on_two_calls(ip, ctx, name, prec_name):
+    prec = ip.IP_FP32_CERTIFY if prec_name == "fp32" else ip.IP_FP64
+    print(f"no-alloc case {name} {prec_name}", flush=True)
+    wl = CASES[name]()
+    rng = np.random.default_rng(7)
+    prob = ip.Problem(ctx, wl)
+    try:
+        for n in (3 * 4096 + 17, 1000):
+            V = _vertices(name, wl, rng, n)
+            want_f, want_b = _eval(ip, ctx, prob, V, prec, noalloc=False)
+            got_f, got_b = _eval(ip, ctx, prob, V, prec, noalloc=True)
+            assert np.array_equal(got_f.view(np.uint64), want_f.view(np.uint64))
+            assert np.array_equal(got_b.view(np.uint64), want_b.view(np.uint64))
+            # the canonical FP64 values are the oracle's, bit for bit, where
+            # the bound is 0 (every value in FP64 mode)
+            exact = got_b == 0
+            ref = O.feval(wl.f, wl.lat, V[exact])
+            assert np.array_equal(got_f[exact].view(np.uint64), ref.view(np.uint64))
+            if prec_name == "fp32":
+                # most vertices are settled by a certified tier; on the dyadic
+                # sphere the exact zeros must take the canonical FP64 pass
+                assert exact.sum() < n
+                if name == "dyadic_sphere_d3":
+                    assert exact.sum() > 0
+            # without a bound output
+            f2, _ = _eval(ip, ctx, prob, V, prec, noalloc=True, with_bound=False)
+            assert np.array_equal(f2.view(np.uint64), want_f.view(np.uint64))
+    finally:
+        prob.close()
+
+
+def test_noalloc_at_the_size_limit(ip, ctx):
+    print("no-alloc at the size limit", flush=True)
+    wl = CASES["stress_d5"]()
+    rng = np.random.default_rng(9)
+    prob = ip.Problem(ctx, wl)
+    try:
+        n = ip.IP_NOALLOC_MAX_VERTICES
+        V = _vertices("stress_d5", wl, rng, n)
+        want_f, want_b = _eval(ip, ctx, prob, V, ip.IP_FP32_CERTIFY, noalloc=False)
+        got_f, got_b = _eval(ip, ctx, prob, V, ip.IP_FP32_CERTIFY, noalloc=True)
+        assert np.array_equal(got_f.view(np.uint64), want_f.view(np.uint64))
+        assert np.array_equal(got_b.view(np.uint64), want_b.view(np.uint64))
+        # one vertex more is refused before anything runs
+        import torch
+        vd = torch.zeros((n + 1, wl.f.d), dtype=torch.int32, device="cuda")
+        fd = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+        with pytest.raises(ip.IPError) as e:
+            ip.ip_feval_noalloc(ctx.h, prob.h, vd.data_ptr(), n + 1, ip.IP_FP32_CERTIFY, fd.data_ptr())
+        assert e.value.code == ip.IP_EINVAL
+        # and a smaller call after the largest one still matches
+        V = V[:777]
+        want_f, want_b = _eval(ip, ctx, prob, V, ip.IP_FP32_CERTIFY, noalloc=False)
+        got_f, got_b = _eval(ip, ctx, prob, V, ip.IP_FP32_CERTIFY, noalloc=True)
+        assert np.array_equal(got_f.view(np.uint64), want_f.view(np.uint64))
+        assert np.array_equal(got_b.view(np.uint64), want_b.view(np.uint64))
+    finally:
+        prob.close()
