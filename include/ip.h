@@ -47,21 +47,30 @@ typedef struct ip_ctx ip_ctx;
 typedef struct ip_problem ip_problem;
 typedef struct ip_cells ip_cells;
 
-/* Manifold function, the decision function of a polynomial-kernel SVM
- * (Sec. IV-A: the learned manifold):
- *   f(x) = sum_{i<n_sv} alpha_i * (gamma * <sv_i, x> + coef0)^degree + bias.
+/* Manifold function, the decision function of a kernel SVM (Sec. IV-A: the
+ * learned manifold; the experiments of Sec. VI train an RBF-kernel SVM):
+ *   IP_KERNEL_POLY: f(x) = sum_{i<n_sv} alpha_i (gamma <sv_i, x> + coef0)^degree + bias
+ *   IP_KERNEL_RBF:  f(x) = sum_{i<n_sv} alpha_i exp(-gamma |x - sv_i|^2) + bias
  * The FP64 value is defined by this evaluation order: x from the lattice
- * (see ip_space), then for i = 0..n_sv-1 in order: dot = fma chain over
- * j = 0..d-1 of sv_ij * x_j starting at 0; t = fma(gamma, dot, coef0);
- * t^degree by repeated multiplication; acc = fma(alpha_i, t^degree, acc);
+ * (see ip_space), then for i = 0..n_sv-1 in order:
+ *   POLY: dot = fma chain over j = 0..d-1 of sv_ij * x_j starting at 0;
+ *         t = fma(gamma, dot, coef0); t^degree by repeated multiplication;
+ *         acc = fma(alpha_i, t^degree, acc);
+ *   RBF:  d2 = fma chain over j of (x_j - sv_ij)^2 starting at 0;
+ *         acc = fma(alpha_i, E(-(gamma * d2)), acc), with E the library's
+ *         own exponential: 0 below -708, else k = floor(t / ln2 + 0.5),
+ *         r = t - k ln2 (two fma with ln2 split in two parts), the Taylor
+ *         polynomial of degree 13 in Horner form, times 2^k;
  * finally f = acc + bias.  Sign bit s = !(f < 0). */
+enum { IP_KERNEL_POLY = 0, IP_KERNEL_RBF = 1 };
 typedef struct {
   int32_t d;             /* ambient dimension, 2..IP_MAX_D */
-  int32_t degree;        /* >= 1 */
+  int32_t degree;        /* >= 1 (POLY; ignored for RBF) */
   int64_t n_sv;          /* >= 1 */
-  double gamma, coef0, bias;
+  double gamma, coef0, bias;   /* gamma > 0 for RBF; coef0 ignored for RBF */
   const double *sv;      /* host, n_sv x d */
   const double *alpha;   /* host, n_sv */
+  int32_t kernel;        /* IP_KERNEL_POLY or IP_KERNEL_RBF */
 } ip_fparams;
 
 /* Coxeter triangulation frame and domain (Sec. IV-B, V-A).  Lattice vertex
@@ -83,8 +92,16 @@ typedef struct {
  * Serial revolute robot: T_i = T_{i-1} * J_i * Rot(axis_i, q_i), T_{-1} = I,
  * with 3x4 row-major [R|t] transforms.  Robot geometry is given in link
  * frames (spheres, and capsules = segments with a radius); obstacles are
- * world-frame spheres and boxes (pose world-from-box, full extents).
- * Capsule-vs-box pairs are not defined (IP_EINVAL).  Touching collides. */
+ * world-frame spheres, boxes (pose world-from-box, full extents) and
+ * cylinders (pose world-from-cylinder with the axis on local z and the
+ * origin at its centre; radius and height).  Capsules are tested against
+ * obstacle spheres only: capsule-vs-box and capsule-vs-cylinder pairs are
+ * not defined (IP_EINVAL).  Touching collides.  Sphere vs cylinder follows
+ * Appendix A with its square roots squared away: in the cylinder frame,
+ * folded into the first octant, rho2 = p_x^2 + p_y^2 and g = p_z - h/2; no
+ * collision if g > r or rho2 > (r + rc)^2; in the ring region (g > 0 and
+ * rho2 > rc^2) no collision if L = (rho2 - rc^2) - (r^2 - g^2) > 0 and
+ * L^2 > 4 rc^2 (r^2 - g^2); else collision. */
 typedef struct {
   int32_t n_joints;            /* equals d of the configurations */
   const double *joint_T;       /* host, n_joints x 12 */
@@ -104,6 +121,9 @@ typedef struct {
   int32_t n_obox;
   const double *obox_T;        /* x12 */
   const double *obox_l;        /* x3 */
+  int32_t n_ocyl;
+  const double *ocyl_T;        /* x12 */
+  const double *ocyl_rh;       /* x2: radius, height */
 } ip_scene;
 
 typedef struct {
@@ -146,6 +166,9 @@ typedef struct {
   int64_t n_hip_malloc;  /* device allocations of the call that missed the
                             context's cache and reached hipMalloc */
   int64_t hip_malloc_bytes; /* their bytes */
+  double ms_refine;      /* time in the iterative intersection kernel */
+  int32_t refine_iters;  /* its iterations per edge (flags of ip_trace) */
+  int32_t pad0;
 } ip_stats;
 
 /* Create a context on HIP device `device`; work is issued on `hip_stream`
@@ -169,9 +192,18 @@ void ip_problem_free(ip_problem *p);
 /* Trace (Sec. V-A locate + breadth-first search; Sec. V-B batches).
  * batch_budget_bytes bounds the per-batch device workspace in batch mode
  * (0 = library default); the traced set does not depend on it.
- * precision: IP_FP64 or IP_FP32_CERTIFY.  flags: reserved, pass 0.
+ * precision: IP_FP64 or IP_FP32_CERTIFY.  flags: IP_REFINE(n) or 0.
  * The result holds the traced edges and their intersection points
- * p = x_a + t (x_b - x_a), t = f_a / (f_a - f_b), a the smaller endpoint. */
+ * p = x_a + t (x_b - x_a), t = f_a / (f_a - f_b), a the smaller endpoint.
+ * With IP_REFINE(n), n = 1..15, the points are computed iteratively instead
+ * (Sec. V-B; Sec. VI: refined until a desired accuracy): n false-position
+ * steps with the Illinois modification on the bracket [a, b]: m_j =
+ * fma(t, x_b,j - x_a,j, x_a,j) with t as above, f at m (canonical FP64 order
+ * in IP_FP64 mode, the FP64 monomial form in IP_FP32_CERTIFY mode), the end
+ * whose sign bit !(f < 0) equals that of f(m) moves to m, and the value kept
+ * at the other end is halved when the same end moved twice in a row; the
+ * point is the false-position point of the final bracket. */
+#define IP_REFINE(n) (((uint32_t)(n) & 15u) << 4)
 int ip_trace(ip_ctx *ctx, const ip_problem *p, uint64_t batch_budget_bytes,
              int32_t precision, uint32_t flags, ip_cells **out);
 
@@ -281,7 +313,7 @@ typedef struct {
   const ip_scene *scene;     /* host, copied; NULL = trace only */
   uint64_t batch_budget;     /* as for ip_trace */
   uint64_t mem_bytes;        /* projected device bytes (admission); 0 = pool / slots */
-  uint32_t flags;            /* IP_KEEP_CELLS */
+  uint32_t flags;            /* IP_KEEP_CELLS, and IP_REFINE(n) for ip_trace */
 } ip_request;
 
 typedef struct {

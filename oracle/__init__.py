@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
 class _F(C.Structure):
     _fields_ = [("d", C.c_int32), ("p", C.c_int32), ("S", C.c_int64),
                 ("gamma", C.c_double), ("coef0", C.c_double), ("bias", C.c_double),
-                ("sv", _dp), ("alpha", _dp)]
+                ("sv", _dp), ("alpha", _dp), ("kernel", C.c_int32)]
 
 
 class _Space(C.Structure):
@@ -53,7 +53,8 @@ class _Scene(C.Structure):
                 ("n_lcap", C.c_int32), ("lcap_link", _ip), ("lcap_p0", _dp), ("lcap_p1", _dp),
                 ("lcap_r", _dp),
                 ("n_osph", C.c_int32), ("osph_c", _dp), ("osph_r", _dp),
-                ("n_obox", C.c_int32), ("obox_T", _dp), ("obox_l", _dp)]
+                ("n_obox", C.c_int32), ("obox_T", _dp), ("obox_l", _dp),
+                ("n_ocyl", C.c_int32), ("ocyl_T", _dp), ("ocyl_rh", _dp)]
 
 
 _lib = None
@@ -65,6 +66,8 @@ def lib():
         if not os.path.exists(LIB):
             build(force=False)
         L = C.CDLL(LIB)
+        L.orc_exp.restype = C.c_double
+        L.orc_exp.argtypes = [C.c_double]
         L.orc_f.restype = C.c_double
         L.orc_f.argtypes = [C.POINTER(_F), _dp]
         L.orc_f_batch.argtypes = [C.POINTER(_F), C.POINTER(_Space), C.c_int64, _ip, _dp]
@@ -93,6 +96,7 @@ def lib():
         L.orc_sphere_sphere.argtypes = [_dp, C.c_double, _dp, C.c_double]
         L.orc_capsule_sphere.argtypes = [_dp, _dp, C.c_double, _dp, C.c_double]
         L.orc_sphere_box.argtypes = [_dp, C.c_double, _dp, _dp]
+        L.orc_sphere_cylinder.argtypes = [_dp, C.c_double, _dp, C.c_double, C.c_double]
         L.orc_fk.argtypes = [C.POINTER(_Scene), _dp, _dp]
         L.orc_check.argtypes = [C.POINTER(_Scene), C.c_int64, _dp, C.POINTER(C.c_uint8)]
         L.orc_free.argtypes = [C.c_void_p]
@@ -119,7 +123,8 @@ class _Ctx:
             sv, psv = _d(f.sv)
             al, pal = _d(f.alpha)
             self.keep += [sv, al]
-            self.f = _F(f.d, f.p, f.S, f.gamma, f.coef0, f.bias, psv, pal)
+            self.f = _F(f.d, f.p, f.S, f.gamma, f.coef0, f.bias, psv, pal,
+                        1 if getattr(f, "kernel", "poly") == "rbf" else 0)
         if lat is not None:
             M, pM = _d(lat.M)
             Mi, pMi = _d(lat.Minv)
@@ -160,6 +165,10 @@ def feval(wl_f, lat, v):
     out = np.empty(v.shape[0], np.float64)
     lib().orc_f_batch(C.byref(c.f), C.byref(c.sp), v.shape[0], pv, out.ctypes.data_as(_dp))
     return out
+
+
+def exp(t):
+    return lib().orc_exp(float(t))
 
 
 def f_at(wl_f, x):
@@ -313,6 +322,12 @@ def sphere_box(c, r, T, l):
     return lib().orc_sphere_box(pc, r, pT, pl)
 
 
+def sphere_cylinder(c, r, T, rc, h):
+    c, pc = _d(c)
+    T, pT = _d(T)
+    return lib().orc_sphere_cylinder(pc, r, pT, rc, h)
+
+
 class _SceneCtx:
     def __init__(self, sc):
         self.keep = []
@@ -333,7 +348,8 @@ class _SceneCtx:
                         len(sc.lcap_r), I(sc.lcap_link), D(sc.lcap_p0), D(sc.lcap_p1),
                         D(sc.lcap_r),
                         len(sc.osph_r), D(sc.osph_c), D(sc.osph_r),
-                        len(sc.obox_l), D(sc.obox_T), D(sc.obox_l))
+                        len(sc.obox_l), D(sc.obox_T), D(sc.obox_l),
+                        len(sc.ocyl_rh), D(sc.ocyl_T), D(sc.ocyl_rh))
 
 
 def fk(sc, q):

@@ -9,7 +9,10 @@
  * -ffp-contract=off so that only the fma() calls written here are fused.
  *
  * Parity status per function (the pins live in the test suite):
- *   orc_coords, orc_f            pinned (closed forms, sphere level set)
+ *   orc_coords, orc_f            pinned (closed forms, sphere level set;
+ *                                RBF: numpy value, one-SV sphere level set)
+ *   orc_exp                      pinned (library exp within 2 ulp, exact at 0,
+ *                                0 below the normal range)
  *   orc_locate                   pinned (barycentric containment)
  *   orc_cofaces2, orc_ncofaces   pinned (brute force over Kuhn simplices,
  *                                count formulas of Sec. V-A / V-B, Fig. 2)
@@ -25,7 +28,9 @@
  *   orc_sincos, orc_fk           pinned (library sine/cosine, Rodrigues rotation
  *                                about every axis, spatial-arm hand poses)
  *   collision predicates         pinned (textbook clamp distance, hand cases
- *                                of link spheres against spheres and boxes)
+ *                                of link spheres against spheres and boxes;
+ *                                cylinder: radial/axial clamp distance and
+ *                                exact touching cases)
  */
 #include "oracle.h"
 
@@ -164,11 +169,53 @@ void orc_coords(const orc_space *sp, const int32_t *v, double *x) {
   }
 }
 
-/* f(x) = sum_i alpha_i (gamma <s_i, x> + coef0)^p + bias, in index order,
- * the power as repeated multiplication. */
+/* ln 2 = LN2_HI + LN2_LO with LN2_HI a multiple of 2^-32, so that k * LN2_HI
+ * is exact for |k| < 2^20. */
+#define LN2_HI 0.6931471806019545
+#define LN2_LO -4.2009150726810846e-11
+#define INV_LN2 1.4426950408889634
+
+double orc_exp(double t) {
+  if (t < -708.0) return 0.0;
+  double k = floor(t * INV_LN2 + 0.5);
+  double r = fma(-k, LN2_HI, t);
+  r = fma(-k, LN2_LO, r);
+  /* Horner from 1/13! down to 1/1! and 1 */
+  double p = 1.6059043836821613e-10; /* 1/13! */
+  p = fma(r, p, 2.08767569878681e-09);   /* 1/12! */
+  p = fma(r, p, 2.505210838544172e-08);  /* 1/11! */
+  p = fma(r, p, 2.755731922398589e-07);  /* 1/10! */
+  p = fma(r, p, 2.7557319223985893e-06); /* 1/9!  */
+  p = fma(r, p, 2.48015873015873e-05);   /* 1/8!  */
+  p = fma(r, p, 0.0001984126984126984);  /* 1/7!  */
+  p = fma(r, p, 0.001388888888888889);   /* 1/6!  */
+  p = fma(r, p, 0.008333333333333333);   /* 1/5!  */
+  p = fma(r, p, 0.041666666666666664);   /* 1/4!  */
+  p = fma(r, p, 0.16666666666666666);    /* 1/3!  */
+  p = fma(r, p, 0.5);                    /* 1/2!  */
+  p = fma(r, p, 1.0);                    /* 1/1!  */
+  p = fma(r, p, 1.0);
+  return ldexp(p, (int)k);
+}
+
+/* f(x): ORC_POLY sums alpha_i (gamma <s_i, x> + coef0)^p in index order, the
+ * power as repeated multiplication; ORC_RBF sums alpha_i exp(-(gamma d2))
+ * with d2 the fma chain of (x_j - s_ij)^2 over j.  Then + bias. */
 double orc_f(const orc_fparams *f, const double *x) {
   const int d = f->d;
   double acc = 0.0;
+  if (f->kernel == ORC_RBF) {
+    for (int64_t i = 0; i < f->S; ++i) {
+      const double *s = f->sv + i * d;
+      double d2 = 0.0;
+      for (int j = 0; j < d; ++j) {
+        double df = x[j] - s[j];
+        d2 = fma(df, df, d2);
+      }
+      acc = fma(f->alpha[i], orc_exp(-(f->gamma * d2)), acc);
+    }
+    return acc + f->bias;
+  }
   for (int64_t i = 0; i < f->S; ++i) {
     const double *s = f->sv + i * d;
     double dot = 0.0;
@@ -844,6 +891,31 @@ int orc_sphere_box(const double *c, double r, const double *T, const double *l) 
   return 1;
 }
 
+/* Appendix A, sphere vs cylinder: centre into the cylinder frame (axis z,
+ * origin at its centre), folded into the first octant: p.  With rho the
+ * distance of p from the axis and g = p_z - h/2: no collision when g > r or
+ * rho > r + rc (the padded cylinder); otherwise, in the ring region (g > 0
+ * and rho > rc) no collision when (rho - rc)^2 + g^2 > r^2; anything else
+ * collides.  The ring test without square roots: with q = r^2 - g^2 >= 0
+ * there, (rho - rc)^2 > q with rho > rc holds exactly when
+ * L = rho^2 - rc^2 - q is positive and L^2 > 4 rc^2 q. */
+int orc_sphere_cylinder(const double *c, double r, const double *T, double rc, double h) {
+  double dx = c[0] - T[3], dy = c[1] - T[7], dz = c[2] - T[11];
+  double p[3];
+  for (int i = 0; i < 3; ++i) p[i] = fabs(fma(T[8 + i], dz, fma(T[4 + i], dy, T[i] * dx)));
+  double rho2 = fma(p[1], p[1], p[0] * p[0]);
+  double g = p[2] - 0.5 * h;
+  if (g > r) return 0;
+  double rr = r + rc;
+  if (rho2 > rr * rr) return 0;
+  if (g > 0.0 && rho2 > rc * rc) {
+    double q = r * r - g * g;
+    double L = (rho2 - rc * rc) - q;
+    if (L > 0.0 && L * L > 4.0 * (rc * rc) * q) return 0;
+  }
+  return 1;
+}
+
 static void compose(const double *A, const double *B, double *C) {
   for (int r = 0; r < 3; ++r) {
     for (int c = 0; c < 3; ++c)
@@ -894,7 +966,9 @@ void orc_fk(const orc_scene *sc, const double *q, double *T_out) {
 
 int orc_check(const orc_scene *sc, int64_t n, const double *q, uint8_t *verdict) {
   if (sc->n_joints < 1 || sc->n_joints > 7) return -2;
-  if (sc->n_lcap > 0 && sc->n_obox > 0) return -2; /* capsule-box not defined */
+  /* capsules are tested against spheres only (capsule-box, capsule-cylinder
+   * are not defined) */
+  if (sc->n_lcap > 0 && (sc->n_obox > 0 || sc->n_ocyl > 0)) return -2;
   double T[7 * 12];
   for (int64_t i = 0; i < n; ++i) {
     orc_fk(sc, q + i * sc->n_joints, T);
@@ -906,6 +980,9 @@ int orc_check(const orc_scene *sc, int64_t n, const double *q, uint8_t *verdict)
         hit = orc_sphere_sphere(cw, sc->lsph_r[a], sc->osph_c + 3 * b, sc->osph_r[b]);
       for (int b = 0; b < sc->n_obox && !hit; ++b)
         hit = orc_sphere_box(cw, sc->lsph_r[a], sc->obox_T + 12 * b, sc->obox_l + 3 * b);
+      for (int b = 0; b < sc->n_ocyl && !hit; ++b)
+        hit = orc_sphere_cylinder(cw, sc->lsph_r[a], sc->ocyl_T + 12 * b, sc->ocyl_rh[2 * b],
+                                  sc->ocyl_rh[2 * b + 1]);
     }
     for (int a = 0; a < sc->n_lcap && !hit; ++a) {
       double p0[3], p1[3];

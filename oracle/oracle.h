@@ -33,13 +33,20 @@ extern "C" {
 
 #define ORC_MAXD 8
 
+/* Decision function of a kernel SVM (Sec. IV-A; the experiments train an
+ * RBF-kernel SVM):
+ *   ORC_POLY: f(x) = sum_i alpha_i (gamma <s_i, x> + coef0)^p + bias,
+ *   ORC_RBF:  f(x) = sum_i alpha_i exp(-gamma |x - s_i|^2) + bias. */
+#define ORC_POLY 0
+#define ORC_RBF 1
 typedef struct {
   int32_t d;            /* ambient dimension, 2..7 */
-  int32_t p;            /* polynomial kernel degree >= 1 */
+  int32_t p;            /* polynomial kernel degree >= 1 (ORC_POLY) */
   int64_t S;            /* number of support vectors */
   double gamma, coef0, bias;
   const double *sv;     /* S x d, row-major */
   const double *alpha;  /* S */
+  int32_t kernel;       /* ORC_POLY or ORC_RBF */
 } orc_fparams;
 
 typedef struct {
@@ -58,6 +65,12 @@ typedef struct {
   int32_t *v;           /* n x d */
   uint32_t *mask;       /* n */
 } orc_edges;
+
+/* Own exponential for the RBF kernel: Cody-Waite reduction by ln 2 with a
+ * two-part constant (t = k ln2 + r, |r| <= ln2 / 2), the Taylor polynomial
+ * of exp(r) to degree 13 in Horner form (coefficients 1/n!), then the exact
+ * scaling by 2^k.  0 below t = -708 (under the normal range). */
+double orc_exp(double t);
 
 /* Canonical coordinates and f (Sec. III / IV-A: the learned manifold). */
 void   orc_coords(const orc_space *sp, const int32_t *v, double *x);
@@ -156,6 +169,9 @@ typedef struct {
   int32_t n_obox;            /* obstacle boxes */
   const double *obox_T;      /* x12, world-from-box pose */
   const double *obox_l;      /* x3 full extents */
+  int32_t n_ocyl;            /* obstacle cylinders */
+  const double *ocyl_T;      /* x12, world-from-cylinder pose (axis = z) */
+  const double *ocyl_rh;     /* x2: radius, height */
 } orc_scene;
 
 /* Own sine/cosine: Cody-Waite reduction by pi/2, Taylor polynomials. */
@@ -165,6 +181,9 @@ int  orc_sphere_sphere(const double *a, double ra, const double *b, double rb);
 int  orc_capsule_sphere(const double *p0, const double *p1, double rc,
                         const double *c, double rs);
 int  orc_sphere_box(const double *c, double r, const double *T, const double *l);
+/* Sphere vs solid cylinder of radius rc and height h (Appendix A, sphere vs
+ * cylinder), the square roots of its distance tests squared away. */
+int  orc_sphere_cylinder(const double *c, double r, const double *T, double rc, double h);
 /* Forward kinematics: world transform of every link (n_joints x 12). */
 void orc_fk(const orc_scene *sc, const double *q, double *T_out);
 /* Verdicts for n configurations q (n x n_joints). */

@@ -191,7 +191,7 @@ int build_poly(ip_ctx *ctx, ip_problem *p, const ip_fparams *f, const ip_space *
   p->poly = PolyDev{};
   const int d = f->d, P = f->degree;
   const int64_t S = f->n_sv;
-  if (P > 4) return IP_OK;
+  if (f->kernel != IP_KERNEL_POLY || P > 4) return IP_OK;
   std::vector<std::vector<int>> monos;
   std::vector<int> cur;
   mono_dfs(d, P, 0, cur, monos);
@@ -287,6 +287,55 @@ int build_poly(ip_ctx *ctx, ip_problem *p, const ip_fparams *f, const ip_space *
   return IP_OK;
 }
 
+// FP32 records of an RBF-kernel f and the bound of its canonical FP64 value.
+// Each canonical term alpha exp(-(gamma d2)) carries a relative error of at
+// most 62 u from the own exponential (reduction 2 u, Horner at most 28
+// roundings on terms whose absolute sum is at most twice the value, the
+// coefficients 2 u) and an absolute error of at most |alpha| u (d + 4) / e
+// from the rounding of d2 and of gamma d2 (the exponent moves by at most
+// gamma u (d + 4) d2, and gamma d2 exp(-gamma d2) <= 1/e); the sum over the
+// support vectors adds at most S u sum |alpha|, the bias and the final add
+// u (|bias| + sum |alpha|).
+int build_rbf(ip_ctx *ctx, ip_problem *p, const ip_fparams *f) {
+  p->rbf = RbfDev{};
+  if (f->kernel != IP_KERNEL_RBF) return IP_OK;
+  const int d = f->d;
+  const int64_t S = f->n_sv;
+  const double u64 = std::ldexp(1.0, -53);
+  double sum_a = 0.0, amax = 0.0, nmax = 0.0;
+  std::vector<float> rec((size_t)S * 8, 0.0f);
+  bool ok = std::isfinite((float)f->gamma) && std::isfinite((float)f->bias);
+  for (int64_t i = 0; i < S; ++i) {
+    double nrm = 0.0;
+    for (int j = 0; j < d; ++j) {
+      rec[i * 8 + j] = (float)f->sv[i * d + j];
+      nrm += f->sv[i * d + j] * f->sv[i * d + j];
+      ok = ok && std::isfinite(rec[i * 8 + j]);
+    }
+    rec[i * 8 + d] = (float)f->alpha[i];
+    ok = ok && std::isfinite(rec[i * 8 + d]);
+    nmax = std::max(nmax, nrm);
+    sum_a += std::fabs(f->alpha[i]);
+    amax = std::max(amax, std::fabs(f->alpha[i]));
+  }
+  const double B64 = 1.01 * u64 * (sum_a * (62.0 + (d + 4) / 2.718281828459045 + (double)S + 1.0) + 2.0 * std::fabs(f->bias));
+  p->rbf.B64 = B64;
+  p->rbf.amax = amax;
+  p->rbf.S = S;
+  p->rbf.gamma = (float)f->gamma;
+  p->rbf.bias = (float)f->bias;
+  p->rbf.nrm_max = std::nextafter((float)(nmax * (1.0 + 1e-6)), INFINITY);
+  // the points of FP32 mode check their placement against this bound too
+  p->poly.B64 = B64;
+  if (!ok) return IP_OK;  // out of FP32 range: FP64 only
+  IP_TRY_HIP(ctx, hipMalloc(&p->rbf_dev, rec.size() * 4));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(p->rbf_dev, rec.data(), rec.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  p->rbf.rec = (const float *)p->rbf_dev;
+  p->rbf.ok = 1;
+  return IP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -325,7 +374,9 @@ int ip_create(ip_ctx **out, int device, void *stream) {
       (void)hipGetLastError();
       tot = 64ull << 30;
     }
-    ctx->cache.limit = tot / 3;
+    // idle blocks kept for reuse: up to half the device (a serving slot
+    // gets its share of the server's pool instead)
+    ctx->cache.limit = tot / 2;
   }
   *out = ctx;
   return IP_OK;
@@ -358,7 +409,10 @@ int ip_problem_create(ip_ctx *ctx, const ip_fparams *f, const ip_space *sp, cons
   if (!f || !sp || (!seeds && n_seeds > 0)) return ip_fail(ctx, IP_EINVAL, "null argument");
   const int d = f->d;
   if (d < 2 || d > IP_MAX_D || sp->d != d) return ip_fail(ctx, IP_EINVAL, "dimension must be 2..7 and match");
-  if (f->degree < 1 || f->degree > 64) return ip_fail(ctx, IP_EINVAL, "degree must be 1..64");
+  if (f->kernel != IP_KERNEL_POLY && f->kernel != IP_KERNEL_RBF) return ip_fail(ctx, IP_EINVAL, "unknown kernel");
+  if (f->kernel == IP_KERNEL_POLY && (f->degree < 1 || f->degree > 64))
+    return ip_fail(ctx, IP_EINVAL, "degree must be 1..64");
+  if (f->kernel == IP_KERNEL_RBF && !(f->gamma > 0.0)) return ip_fail(ctx, IP_EINVAL, "RBF gamma must be positive");
   if (f->n_sv < 1 || !f->sv || !f->alpha) return ip_fail(ctx, IP_EINVAL, "need at least one support vector");
   if (coarse_k < 1 || coarse_k > 64) return ip_fail(ctx, IP_EINVAL, "coarse_k must be 1..64");
   if (n_seeds < 1) return ip_fail(ctx, IP_EINVAL, "need at least one seed");
@@ -403,11 +457,13 @@ int ip_problem_create(ip_ctx *ctx, const ip_fparams *f, const ip_space *sp, cons
   p->n_seeds = n_seeds;
   p->f.rec = p->rec_dev;
   p->f.S = S;
-  p->f.p = f->degree;
+  p->f.p = f->kernel == IP_KERNEL_POLY ? f->degree : 1;
+  p->f.kernel = f->kernel;
   p->f.gamma = f->gamma;
   p->f.coef0 = f->coef0;
   p->f.bias = f->bias;
   rc = build_poly(ctx, p, f, sp);
+  if (rc == IP_OK) rc = build_rbf(ctx, p, f);
   if (rc != IP_OK) {
     ip_problem_free(p);
     return rc;
@@ -422,6 +478,7 @@ void ip_problem_free(ip_problem *p) {
   if (p->rec_dev) (void)hipFree(p->rec_dev);
   if (p->seeds_dev) (void)hipFree(p->seeds_dev);
   if (p->poly_dev) (void)hipFree(p->poly_dev);
+  if (p->rbf_dev) (void)hipFree(p->rbf_dev);
   delete p;
 }
 

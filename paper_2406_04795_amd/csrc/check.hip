@@ -27,9 +27,10 @@ struct SceneDev {
   const double *lsph;         // [cx cy cz r] per sphere, grouped by link
   const int32_t *lcap_off;    // nj + 1
   const double *lcap;         // [p0 p1 r pad] (8 doubles) per capsule, by link
-  int32_t n_osph, n_obox;
+  int32_t n_osph, n_obox, n_ocyl, pad;
   const double *osph;         // [cx cy cz r]
   const double *obox;         // [T(12) l(3) pad] (16 doubles)
+  const double *ocyl;         // [T(12) rc h pad pad] (16 doubles)
   const double *lbound;       // per link [cx cy cz R]: a ball in the link frame
                               // holding all of the link's geometry (R < 0: none)
   double eps;                 // margin of the culling test
@@ -178,6 +179,30 @@ __device__ __forceinline__ bool sphere_box(const double *c, double r, const doub
   return true;
 }
 
+// Appendix A, sphere vs cylinder (axis z, origin at the centre): centre into
+// the cylinder frame, fold into the first octant, (1) padded cylinder test,
+// (2) ring region (rim) test with its square roots squared away: with
+// q = r^2 - g^2, (rho - rc)^2 > q for rho > rc exactly when
+// L = rho^2 - rc^2 - q > 0 and L^2 > 4 rc^2 q; anything else collides.
+__device__ __forceinline__ bool sphere_cyl(const double *c, double r, const double *C) {
+  const double dx = c[0] - C[3], dy = c[1] - C[7], dz = c[2] - C[11];
+  double p[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) p[i] = fabs(fma(C[8 + i], dz, fma(C[4 + i], dy, C[i] * dx)));
+  const double rc = C[12], h = C[13];
+  const double rho2 = fma(p[1], p[1], p[0] * p[0]);
+  const double g = p[2] - 0.5 * h;
+  if (g > r) return false;
+  const double rr = r + rc;
+  if (rho2 > rr * rr) return false;
+  if (g > 0.0 && rho2 > rc * rc) {
+    const double q = r * r - g * g;
+    const double L = (rho2 - rc * rc) - q;
+    if (L > 0.0 && L * L > 4.0 * (rc * rc) * q) return false;
+  }
+  return true;
+}
+
 // Culling: can a ball (centre c, radius R) reach obstacle b?  A false
 // answer proves that every sphere or capsule inside the ball misses the
 // obstacle by more than the margin eps, far beyond the rounding of the exact
@@ -195,6 +220,19 @@ __device__ __forceinline__ bool ball_near_box(const double *c, double R, const d
     const double g = fabs(fma(B[8 + i], dz, fma(B[4 + i], dy, B[i] * dx))) - 0.5 * B[12 + i];
     if (g > 0.0) s = fma(g, g, s);
   }
+  return !(s > R * R);
+}
+
+__device__ __forceinline__ bool ball_near_cyl(const double *c, double R, const double *C) {
+  const double dx = c[0] - C[3], dy = c[1] - C[7], dz = c[2] - C[11];
+  double p[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) p[i] = fabs(fma(C[8 + i], dz, fma(C[4 + i], dy, C[i] * dx)));
+  const double gr = sqrt(fma(p[1], p[1], p[0] * p[0])) - C[12];
+  const double gz = p[2] - 0.5 * C[13];
+  double s = 0.0;
+  if (gr > 0.0) s = gr * gr;
+  if (gz > 0.0) s = fma(gz, gz, s);
   return !(s > R * R);
 }
 
@@ -216,7 +254,8 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
 __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__restrict__ q, int64_t n, int64_t ld,
                                                     uint8_t *__restrict__ verdict) {
   const int d = S.nj;
-  const int nobs = S.n_osph + S.n_obox;
+  const int nobs = S.n_osph + S.n_obox + S.n_ocyl;
+  const int nsb_all = S.n_osph, nbx_all = S.n_osph + S.n_obox;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t rounds = (n + stride - 1) / stride;
@@ -239,13 +278,17 @@ __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__
       const double Rb = lb[3] + S.eps;
       for (int b0 = 0; b0 < nobs; b0 += 64) {
         const int nb = nobs - b0 < 64 ? nobs - b0 : 64;
-        // spheres first, then boxes: two uniform loops, no per-obstacle branch
+        // spheres, then boxes, then cylinders: uniform loops, no
+        // per-obstacle branch
         uint64_t near = 0;
-        const int nsb = S.n_osph - b0 < 0 ? 0 : (S.n_osph - b0 < nb ? S.n_osph - b0 : nb);
+        const int nsb = nsb_all - b0 < 0 ? 0 : (nsb_all - b0 < nb ? nsb_all - b0 : nb);
+        const int nbx = nbx_all - b0 < 0 ? 0 : (nbx_all - b0 < nb ? nbx_all - b0 : nb);
         for (int b = 0; b < nsb; ++b)
           near |= (uint64_t)ball_near_sphere(cb, Rb, S.osph + 4 * (b0 + b)) << b;
-        for (int b = nsb; b < nb; ++b)
-          near |= (uint64_t)ball_near_box(cb, Rb, S.obox + 16 * (b0 + b - S.n_osph)) << b;
+        for (int b = nsb; b < nbx; ++b)
+          near |= (uint64_t)ball_near_box(cb, Rb, S.obox + 16 * (b0 + b - nsb_all)) << b;
+        for (int b = nbx; b < nb; ++b)
+          near |= (uint64_t)ball_near_cyl(cb, Rb, S.ocyl + 16 * (b0 + b - nbx_all)) << b;
         if (hit) near = 0;
         const uint64_t any = wave_or64(near);
         if (!any) continue;
@@ -257,8 +300,9 @@ __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__
             const int b = __ffsll((long long)m) - 1;
             if (!((near >> b) & 1ull) || hit) continue;
             const int o = b0 + b;
-            hit = o < S.n_osph ? sphere_sphere(cw, sp[3], S.osph + 4 * o, S.osph[4 * o + 3])
-                               : sphere_box(cw, sp[3], S.obox + 16 * (o - S.n_osph));
+            hit = o < nsb_all   ? sphere_sphere(cw, sp[3], S.osph + 4 * o, S.osph[4 * o + 3])
+                  : o < nbx_all ? sphere_box(cw, sp[3], S.obox + 16 * (o - nsb_all))
+                                : sphere_cyl(cw, sp[3], S.ocyl + 16 * (o - nbx_all));
           }
         }
         for (int a = S.lcap_off[li]; a < S.lcap_off[li + 1]; ++a) {
@@ -278,6 +322,84 @@ __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__
     }
     if (valid) verdict[i] = hit ? 1 : 0;
   }
+}
+
+// Sphere-parallel layout (Sec. V-C: threads over the robot's spheres, then
+// over configurations), for batches too small to fill the device with one
+// lane per configuration: a group of NSP consecutive lanes (NSP a power of
+// two at least the robot's sphere count) takes one configuration, lane j of
+// the group its j-th link sphere (grouped by link).  Each lane runs the
+// forward kinematics up to its sphere's link, in the same operation order as
+// the per-configuration kernel, and tests its sphere against every obstacle;
+// the group's hits are ORed with a ballot and its first lane writes the
+// verdict.  Robots with capsules use the per-configuration kernel.
+template <int NSP>
+__global__ __launch_bounds__(256) void check_sphere_kernel(SceneDev S, int n_lsph, const double *__restrict__ q,
+                                                           int64_t n, int64_t ld, uint8_t *__restrict__ verdict) {
+  constexpr int GPW = 64 / NSP;  // configurations per wave
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int g = lane / NSP, a = lane % NSP;
+  for (int64_t w0 = wave * GPW; w0 < n; w0 += n_waves * GPW) {
+    const int64_t c = w0 + g;
+    bool hit = false;
+    if (c < n && a < n_lsph) {
+      int li = 0;
+      while (li + 1 < S.nj && S.lsph_off[li + 1] <= a) ++li;
+      double T[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+      for (int j = 0; j <= li; ++j) {
+        double sn_, cs_, A[12], Rm[12];
+        sincos_own(q[(int64_t)j * ld + c], &sn_, &cs_);
+        compose(T, S.joint_T + 12 * j, A);
+        rotation(S.joint_axis[j], sn_, cs_, Rm);
+        compose(A, Rm, T);
+      }
+      const double *sp = S.lsph + 4 * a;
+      double cw[3];
+      xform(T, sp, cw);
+      for (int b = 0; b < S.n_osph && !hit; ++b) hit = sphere_sphere(cw, sp[3], S.osph + 4 * b, S.osph[4 * b + 3]);
+      for (int b = 0; b < S.n_obox && !hit; ++b) hit = sphere_box(cw, sp[3], S.obox + 16 * b);
+      for (int b = 0; b < S.n_ocyl && !hit; ++b) hit = sphere_cyl(cw, sp[3], S.ocyl + 16 * b);
+    }
+    const uint64_t bal = __ballot(hit);
+    const uint64_t gmask = (NSP == 64 ? ~0ull : ((1ull << NSP) - 1ull)) << (g * NSP);
+    if (a == 0 && c < n) verdict[c] = (bal & gmask) ? 1 : 0;
+  }
+}
+
+// Launches the verdict kernel for n configurations: the sphere-parallel
+// layout when one lane per configuration would start fewer than 8192 waves
+// and the robot is made of at most 64 spheres, else the per-configuration
+// kernel.
+int launch_check(ip_ctx *ctx, const SceneDev &S, int n_lsph, int n_lcap, const double *q, int64_t n, int64_t ld,
+                 uint8_t *verdict) {
+  if (n == 0) return IP_OK;
+  if (n_lcap == 0 && n_lsph > 0 && n_lsph <= 64 && n < 8192 * 64) {
+    int nsp = 1;
+    while (nsp < n_lsph) nsp <<= 1;
+    const int64_t per_block = 4 * (64 / nsp);
+    const int64_t blocks = std::min<int64_t>((n + per_block - 1) / per_block, 65536);
+#define IP_CS(NN)                                                                                              \
+  hipLaunchKernelGGL((check_sphere_kernel<NN>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, n_lsph, q, \
+                     n, ld, verdict)
+    switch (nsp) {
+      case 1: IP_CS(1); break;
+      case 2: IP_CS(2); break;
+      case 4: IP_CS(4); break;
+      case 8: IP_CS(8); break;
+      case 16: IP_CS(16); break;
+      case 32: IP_CS(32); break;
+      default: IP_CS(64); break;
+    }
+#undef IP_CS
+  } else {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(check_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, q, n, ld, verdict);
+  }
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
 }
 
 // Stable compaction of the free (verdict 0) points, by tiles of kTile cells:
@@ -356,9 +478,10 @@ __global__ __launch_bounds__(256) void free_scatter_kernel(const uint8_t *__rest
 int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   const int nj = sc->n_joints;
   if (nj < 1 || nj > IP_MAX_D) return ip_fail(ctx, IP_EINVAL, "scene: joint count out of range");
-  if (sc->n_lcap > 0 && sc->n_obox > 0) return ip_fail(ctx, IP_EINVAL, "scene: capsule-vs-box pairs are not defined");
-  if (sc->n_lsph < 0 || sc->n_lcap < 0 || sc->n_osph < 0 || sc->n_obox < 0)
+  if (sc->n_lsph < 0 || sc->n_lcap < 0 || sc->n_osph < 0 || sc->n_obox < 0 || sc->n_ocyl < 0)
     return ip_fail(ctx, IP_EINVAL, "scene: negative counts");
+  if (sc->n_lcap > 0 && (sc->n_obox > 0 || sc->n_ocyl > 0))
+    return ip_fail(ctx, IP_EINVAL, "scene: capsules are tested against obstacle spheres only");
   for (int i = 0; i < nj; ++i)
     if (sc->joint_axis[i] < 0 || sc->joint_axis[i] > 2) return ip_fail(ctx, IP_EINVAL, "scene: axis must be 0..2");
   // group robot geometry by link (stable)
@@ -396,7 +519,13 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
       lcap[8 * pos + 7] = 0.0;
     }
   }
-  std::vector<double> osph(4 * (size_t)sc->n_osph), obox(16 * (size_t)sc->n_obox);
+  std::vector<double> osph(4 * (size_t)sc->n_osph), obox(16 * (size_t)sc->n_obox),
+      ocyl(16 * (size_t)sc->n_ocyl, 0.0);
+  for (int b = 0; b < sc->n_ocyl; ++b) {
+    for (int j = 0; j < 12; ++j) ocyl[16 * b + j] = sc->ocyl_T[12 * b + j];
+    ocyl[16 * b + 12] = sc->ocyl_rh[2 * b];
+    ocyl[16 * b + 13] = sc->ocyl_rh[2 * b + 1];
+  }
   for (int b = 0; b < sc->n_osph; ++b) {
     for (int j = 0; j < 3; ++j) osph[4 * b + j] = sc->osph_c[3 * b + j];
     osph[4 * b + 3] = sc->osph_r[b];
@@ -448,6 +577,8 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   for (double x : osph) scale = std::max(scale, std::fabs(x));
   for (int b = 0; b < sc->n_obox; ++b)
     for (int j = 0; j < 15; ++j) scale = std::max(scale, std::fabs(obox[16 * b + j]));
+  for (int b = 0; b < sc->n_ocyl; ++b)
+    for (int j = 0; j < 14; ++j) scale = std::max(scale, std::fabs(ocyl[16 * b + j]));
   // one contiguous blob: doubles first, then ints
   std::vector<double> blob;
   auto put = [&](const double *p, size_t n) {
@@ -460,6 +591,7 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   size_t o_lc = put(lcap.data(), lcap.size());
   size_t o_os = put(osph.data(), osph.size());
   size_t o_ob = put(obox.data(), obox.size());
+  size_t o_oc = put(ocyl.data(), ocyl.size());
   size_t o_lb = put(lbound.data(), lbound.size());
   size_t n_dbl = blob.size();
   std::vector<int32_t> ints;
@@ -486,6 +618,9 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   out->lcap = db + o_lc;
   out->n_osph = sc->n_osph;
   out->n_obox = sc->n_obox;
+  out->n_ocyl = sc->n_ocyl;
+  out->pad = 0;
+  out->ocyl = db + o_oc;
   out->osph = db + o_os;
   out->obox = db + o_ob;
   out->lbound = db + o_lb;
@@ -501,12 +636,7 @@ int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64
                   uint8_t *verdict_dev) {
   SceneDev S;
   IP_TRY(upload_scene(ctx, scene, &S));
-  if (n == 0) return IP_OK;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(check_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, q_dev, n, ld, verdict_dev);
-  IP_TRY_HIP(ctx, hipGetLastError());
-  return IP_OK;
+  return launch_check(ctx, S, scene->n_lsph, scene->n_lcap, q_dev, n, ld, verdict_dev);
 }
 
 // Verdicts of every cell, then the stable compaction of the free points.
@@ -527,10 +657,12 @@ int ip_check_gather_impl(ip_ctx *ctx, const ip_scene *scene, ip_cells *c) {
   uint32_t *cnt = (uint32_t *)(off + (ntiles ? ntiles : 1));
   IP_TRY_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
   if (n) {
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(check_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, S, (const double *)c->pts, n,
-                       c->ld, c->verdict);
+    const int rc = launch_check(ctx, S, scene->n_lsph, scene->n_lcap, (const double *)c->pts, n, c->ld, c->verdict);
+    if (rc != IP_OK) {
+      (void)hipStreamSynchronize(ctx->stream);
+      ip_dfree(ctx, tiles);
+      return rc;
+    }
     hipLaunchKernelGGL(free_count_kernel, dim3((unsigned)ntiles), dim3(256), 0, ctx->stream,
                        (const uint8_t *)c->verdict, n, cnt);
     hipLaunchKernelGGL(scan_tiles_kernel, dim3(1), dim3(1024), 0, ctx->stream, (const uint32_t *)cnt, ntiles, off,

@@ -98,6 +98,62 @@ __global__ __launch_bounds__(256) void feval64_kernel(FDev F, LatDev L, const ui
   }
 }
 
+// Canonical FP64 RBF evaluation (same MODEs as feval64_kernel): the support
+// vectors pass through LDS in tiles of kRbfTile records, which every lane of
+// the block then reads at the same address (a broadcast), in index order.
+// The loop over vertex groups is uniform across the block, so the barriers
+// around each tile are reached by every thread.
+constexpr int kRbfTile = 256;
+
+template <int D, int R, int MODE>
+__global__ __launch_bounds__(256) void rbf64_kernel(FDev F, LatDev L, const uint32_t *__restrict__ list, uint64_t n,
+                                                    const unsigned long long *n_dev,
+                                                    const uint64_t *__restrict__ keys,
+                                                    const int32_t *__restrict__ vraw, double *__restrict__ out) {
+  __shared__ double tile[kRbfTile * 8];
+  constexpr uint64_t S4 = MODE == 0 ? 4 : 1;
+  if (n_dev) n = (uint64_t)*n_dev < n ? (uint64_t)*n_dev : n;
+  const uint64_t per_block = (uint64_t)blockDim.x * R;
+  for (uint64_t blk = (uint64_t)blockIdx.x * per_block; blk < n; blk += (uint64_t)gridDim.x * per_block) {
+    const uint64_t base = blk + (uint64_t)threadIdx.x * R;
+    double x[R][D];
+    uint64_t dst[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t i = base + r < n ? base + r : n - 1;
+      int32_t v[D];
+      if (MODE == 0) {
+        const uint32_t s = list[i];
+        dst[r] = s;
+        vunpack<D>(L, keys[(uint64_t)s * 4], v);
+      } else {
+        const uint64_t src = MODE == 2 ? (uint64_t)list[i] : i;
+        dst[r] = src;
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = vraw[src * D + j];
+      }
+      lat_coords<D>(L, v, x[r]);
+    }
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int64_t t0 = 0; t0 < F.S; t0 += kRbfTile) {
+      const int nt = (int)(F.S - t0 < kRbfTile ? F.S - t0 : kRbfTile);
+      __syncthreads();
+      for (int q = threadIdx.x; q < nt * 8; q += blockDim.x) tile[q] = F.rec[t0 * 8 + q];
+      __syncthreads();
+      for (int s = 0; s < nt; ++s) {
+        const double *sv = tile + s * 8;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = rbf_term<D>(sv, sv[D], F.gamma, x[r], acc[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (base + r < n) out[dst[r] * S4] = acc[r] + F.bias;
+  }
+}
+
 template <int D, int P, int MODE>
 void launch64(hipStream_t st, const FDev &F, const LatDev &L, const uint32_t *list, uint64_t n,
               const unsigned long long *n_dev, const uint64_t *keys, const int32_t *vraw, double *out) {
@@ -113,6 +169,14 @@ void launch64(hipStream_t st, const FDev &F, const LatDev &L, const uint32_t *li
 template <int D, int MODE>
 void launch64_p(hipStream_t st, const FDev &F, const LatDev &L, const uint32_t *list, uint64_t n,
                 const unsigned long long *n_dev, const uint64_t *keys, const int32_t *vraw, double *out) {
+  if (F.kernel == IP_KERNEL_RBF) {
+    constexpr int R = 2;
+    const uint64_t blocks = std::min<uint64_t>((n + 256 * R - 1) / (256 * R), 65536);
+    if (blocks == 0) return;
+    hipLaunchKernelGGL((rbf64_kernel<D, R, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, F, L, list, n, n_dev,
+                       keys, vraw, out);
+    return;
+  }
   switch (F.p) {
     case 1: launch64<D, 1, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
     case 2: launch64<D, 2, MODE>(st, F, L, list, n, n_dev, keys, vraw, out); break;
@@ -201,6 +265,110 @@ __global__ __launch_bounds__(256) void feval32_kernel(PolyDev Q, LatDev L, const
   if (n64) atomicAdd(c64_ctr, n64);
 }
 
+// FP32 certified RBF evaluation (same MODEs and outputs as feval32_kernel).
+// With u = 2^-24, at the canonical FP64 coordinates x (rounded to FP32):
+// per support vector d2 = the FP32 fma chain of (x_j - s_j)^2, e = the own
+// FP32 exponential of -(gamma d2), term = alpha e; the terms are summed in
+// blocks of 32 and the block sums added, A = sum |term| and W = sum |term| d2
+// beside them.  The bound on |f32 - F| (F the exact value at x):
+//   43 u A'  (exponential 40 u, alpha and product 2 u, sum of A 1 u)
+// + gamma u ((d + 4) W' + 9 (|x|^2 + max |s|^2) A')  (the rounding of d2
+//   and of gamma d2 moves the exponent: |dt| <= gamma u ((d + 3) d2 +
+//   8.1 (|x|^2 + |s|^2)) per term, and |d exp| <= exp |dt| (1 + |dt|))
+// + (32 + S / 32 + 3) u A'  (two-level summation)
+// + u (|bias| + |f32|) + 2e-38 S max|alpha|  (final add; exponential underflow)
+// with A' = A (1 + (S + 60) u), W' likewise (the FP32 sums of positive terms
+// and the relative errors of their terms), all times 1.01 for the products
+// of the first-order terms.  Tier 1 settles the sign when |f32| exceeds the
+// bound plus B64; the rest go to the canonical FP64 kernel.
+constexpr int kRbf32Tile = 512;
+
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void rbf32_kernel(RbfDev Q, LatDev L,
+                                                    const uint32_t *__restrict__ list, uint64_t n, VEnt *vt,
+                                                    float *vb, const int32_t *__restrict__ vraw, double *out,
+                                                    double *bout, uint32_t *fb, unsigned long long *fb_ctr) {
+  __shared__ float tile[kRbf32Tile * 8];
+  constexpr int kStage = 128;
+  __shared__ uint32_t st[4][kStage];
+  const int wib = threadIdx.x >> 6;
+  int sn = 0;
+  auto put = [&](unsigned long long pos, uint32_t s) { fb[pos] = s; };
+  const double u = 5.9604644775390625e-08;
+  for (uint64_t blk = (uint64_t)blockIdx.x * blockDim.x; blk < n; blk += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = blk + threadIdx.x;
+    const bool valid = i < n;
+    const uint64_t ii = valid ? i : n - 1;
+    uint32_t id = 0;
+    int32_t v[D];
+    if (MODE == 0) {
+      id = list[ii];
+      vunpack<D>(L, vt[id].key, v);
+    } else {
+      id = (uint32_t)ii;
+#pragma unroll
+      for (int j = 0; j < D; ++j) v[j] = vraw[ii * D + j];
+    }
+    double x64[D];
+    lat_coords<D>(L, v, x64);
+    float x[D];
+    float X2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      x[j] = (float)x64[j];
+      X2 = fmaf(x[j], x[j], X2);
+    }
+    float acc = 0.0f, blk_acc = 0.0f, A = 0.0f, W = 0.0f;
+    int in_blk = 0;
+    for (int64_t t0 = 0; t0 < Q.S; t0 += kRbf32Tile) {
+      const int nt = (int)(Q.S - t0 < kRbf32Tile ? Q.S - t0 : kRbf32Tile);
+      __syncthreads();
+      for (int q = threadIdx.x; q < nt * 8; q += blockDim.x) tile[q] = Q.rec[t0 * 8 + q];
+      __syncthreads();
+      for (int s = 0; s < nt; ++s) {
+        const float *sv = tile + s * 8;
+        float d2 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const float df = x[j] - sv[j];
+          d2 = fmaf(df, df, d2);
+        }
+        const float term = sv[D] * exp32_own(-(Q.gamma * d2));
+        blk_acc += term;
+        A += fabsf(term);
+        W = fmaf(fabsf(term), d2, W);
+        if (++in_blk == 32) {
+          acc += blk_acc;
+          blk_acc = 0.0f;
+          in_blk = 0;
+        }
+      }
+    }
+    acc += blk_acc;
+    const float f32 = acc + Q.bias;
+    const double S = (double)Q.S;
+    const double grow = 1.0 + (S + 60.0) * u;
+    const double Ap = (double)A * grow, Wp = (double)W * grow;
+    const double X2p = (double)X2 * (1.0 + (D + 2) * u) + 1e-30;
+    const double bnd = 1.01 * (43.0 * u * Ap + (double)Q.gamma * u * ((D + 4) * Wp + 9.0 * (X2p + (double)Q.nrm_max) * Ap) +
+                               (35.0 + S / 32.0) * u * Ap + u * (fabs((double)Q.bias) + fabs((double)f32))) +
+                       2e-38 * S * Q.amax;
+    const double B64 = Q.B64;
+    const bool unsure = !(fabs((double)f32) > bnd + B64);
+    if (valid) {
+      if (MODE == 0) {
+        if (!unsure) vt[id].f = (double)f32;
+        vb[id] = unsure ? -1.0f : (float)(bnd * (1.0 + 1e-6));
+      } else {
+        out[i] = (double)f32;
+        if (bout) bout[i] = unsure ? 0.0 : bnd + B64;
+      }
+    }
+    stage_put<kStage>(st[wib], sn, valid && unsure, id, put, fb_ctr);
+  }
+  stage_flush(st[wib], sn, put, fb_ctr);
+}
+
 __global__ void set_vb_kernel(const uint32_t *list, uint64_t n, float *vb, float v) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     vb[list[i]] = v;
@@ -258,7 +426,45 @@ __global__ void fill_f64_kernel(double *p, uint64_t n, double v) {
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[64] = {nullptr};
 
+template <int MODE>
+int dispatch32_rbf(ip_ctx *ctx, const RbfDev &Q, const LatDev &L, const uint32_t *list, uint64_t n, VEnt *vt,
+                   float *vb, const int32_t *vraw, double *out, double *bout, uint32_t *fb,
+                   unsigned long long *fb_ctr) {
+  if (n == 0) return IP_OK;
+  const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 16384);
+  hipStream_t st = ctx->stream;
+#define IP_R32(DD)                                                                                              \
+  hipLaunchKernelGGL((rbf32_kernel<DD, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, Q, L, list, n, vt, vb, \
+                     vraw, out, bout, fb, fb_ctr)
+  switch (L.d) {
+    case 2: IP_R32(2); break;
+    case 3: IP_R32(3); break;
+    case 4: IP_R32(4); break;
+    case 5: IP_R32(5); break;
+    case 6: IP_R32(6); break;
+    case 7: IP_R32(7); break;
+    default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
+  }
+#undef IP_R32
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
+}
+
+// The certified FP32 tier of problem p (polynomial or RBF form).
+template <int MODE>
+int dispatch32_p(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n, VEnt *vt,
+                 float *vb, const int32_t *vraw, double *out, double *bout, uint32_t *fb,
+                 unsigned long long *fb_ctr, unsigned long long *c64 = nullptr) {
+  if (p->f.kernel == IP_KERNEL_RBF)
+    return dispatch32_rbf<MODE>(ctx, p->rbf, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr);
+  return dispatch32<MODE>(ctx, p->poly, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr, c64);
+}
+
 }  // namespace
+
+bool ip_has_fp32_form(const ip_problem *p) {
+  return p->f.kernel == IP_KERNEL_RBF ? p->rbf.ok != 0 : p->poly.ok != 0;
+}
 
 int ip_noalloc_setup(ip_ctx *ctx) {
   if (ctx->device < 0 || ctx->device >= 64) return ip_fail(ctx, IP_EINVAL, "device index out of range");
@@ -282,7 +488,7 @@ int ip_feval_noalloc_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev
                           double *f_dev, double *bound_dev) {
   if (!ctx->noalloc_scratch) return ip_fail(ctx, IP_EDEVICE, "device scratch not set up");
   hipStream_t st = ctx->stream;
-  if (prec == IP_FP64 || !p->poly.ok) {
+  if (prec == IP_FP64 || !ip_has_fp32_form(p)) {
     if (bound_dev) {
       const uint64_t blocks = std::min<uint64_t>(((uint64_t)n + 255) / 256, 4096);
       hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, st, bound_dev, (uint64_t)n, 0.0);
@@ -294,8 +500,8 @@ int ip_feval_noalloc_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev
   uint32_t *fbl = (uint32_t *)((unsigned char *)ctx->noalloc_scratch + 256);
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, hdr, 2);
   IP_TRY_HIP(ctx, hipGetLastError());
-  IP_TRY(dispatch32<1>(ctx, p->poly, p->fine, nullptr, (uint64_t)n, nullptr, nullptr, v_dev, f_dev, bound_dev, fbl,
-                       hdr, hdr + 1));
+  IP_TRY(dispatch32_p<1>(ctx, p, p->fine, nullptr, (uint64_t)n, nullptr, nullptr, v_dev, f_dev, bound_dev, fbl,
+                         hdr, hdr + 1));
   return dispatch64<2>(ctx, p->f, p->fine, fbl, (uint64_t)n, nullptr, v_dev, f_dev, hdr);
 }
 
@@ -311,7 +517,7 @@ int launch_feval64_raw(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const 
 
 int launch_feval32(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n_list,
                    VEnt *vt, float *vb, uint32_t *fb, unsigned long long *fb_ctr) {
-  return dispatch32<0>(ctx, p->poly, L, list, n_list, vt, vb, nullptr, nullptr, nullptr, fb, fb_ctr);
+  return dispatch32_p<0>(ctx, p, L, list, n_list, vt, vb, nullptr, nullptr, nullptr, fb, fb_ctr);
 }
 
 int launch_set_vb(ip_ctx *ctx, const uint32_t *list, uint64_t n, float *vb, float v) {
@@ -325,7 +531,7 @@ int launch_set_vb(ip_ctx *ctx, const uint32_t *list, uint64_t n, float *vb, floa
 
 int ip_feval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, int32_t prec,
                   double *f_dev, double *bound_dev) {
-  if (prec == IP_FP64 || !p->poly.ok) {
+  if (prec == IP_FP64 || !ip_has_fp32_form(p)) {
     if (bound_dev) IP_TRY_HIP(ctx, hipMemsetAsync(bound_dev, 0, sizeof(double) * (size_t)n, ctx->stream));
     return dispatch64<1>(ctx, p->f, p->fine, nullptr, (uint64_t)n, nullptr, v_dev, f_dev);
   }
@@ -342,8 +548,8 @@ int ip_feval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_
     return IP_ENOMEM;
   }
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
-  int rc = dispatch32<1>(ctx, p->poly, p->fine, nullptr, (uint64_t)n, nullptr, nullptr, v_dev, f_dev, bnd,
-                         (uint32_t *)fbl, &ctx->ctr_dev->n_fb);
+  int rc = dispatch32_p<1>(ctx, p, p->fine, nullptr, (uint64_t)n, nullptr, nullptr, v_dev, f_dev, bnd,
+                           (uint32_t *)fbl, &ctx->ctr_dev->n_fb);
   unsigned long long nfb = 0;
   if (rc == IP_OK) {
     hipError_t e = hipMemcpyAsync(ctx->ctr_host, ctx->ctr_dev, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream);

@@ -39,13 +39,99 @@ struct LatDev {
 
 // Manifold parameters on the device.  rec holds one 64-byte record per
 // support vector: s_0..s_{d-1}, alpha, zero padding (8 doubles).
+// kernel: IP_KERNEL_POLY (alpha_i (gamma <s_i, x> + coef0)^p) or
+// IP_KERNEL_RBF (alpha_i exp(-(gamma |x - s_i|^2))).
 struct FDev {
   const double *rec;
   int64_t S;
   int32_t p;
-  int32_t pad;
+  int32_t kernel;
   double gamma, coef0, bias;
 };
+
+// FP32 form of an RBF-kernel f: one 32-byte record per support vector
+// (s_0..s_{d-1} in FP32, alpha in FP32, |s|^2 rounded up, zero padding to 8
+// floats), with the constants of its error bound (see feval.hip).
+struct RbfDev {
+  const float *rec;
+  int64_t S;
+  int32_t ok;      // 0: no FP32 form, every vertex is evaluated in FP64
+  float gamma, bias;
+  float nrm_max;   // largest |s_i|^2 (rounded up)
+  double B64;      // |f64 - F| <= B64 for the canonical FP64 value
+  double amax;     // largest |alpha_i|
+};
+
+// ln 2 = LN2_HI + LN2_LO, LN2_HI a multiple of 2^-32 (k * LN2_HI exact for
+// |k| < 2^20); the FP32 split has 16 significant bits in its high part.
+#define IP_LN2_HI 0.6931471806019545
+#define IP_LN2_LO -4.2009150726810846e-11
+#define IP_INV_LN2 1.4426950408889634
+#define IP_LN2_HI32 0.693145751953125f
+#define IP_LN2_LO32 1.428606765330187e-06f
+#define IP_INV_LN2_32 1.4426950216293335f
+
+// Own exponential of the canonical RBF evaluation: Cody-Waite reduction by
+// ln 2 (t = k ln2 + r, |r| <= ln2 / 2), the Taylor polynomial of exp(r) to
+// degree 13 in Horner form (coefficients 1/n!), then the exact scaling by
+// 2^k; 0 below t = -708.  Written out in this order so that every device
+// and the host agree bit for bit.
+__host__ __device__ __forceinline__ double exp_own(double t) {
+  if (t < -708.0) return 0.0;
+  const double k = floor(t * IP_INV_LN2 + 0.5);
+  double r = fma(-k, IP_LN2_HI, t);
+  r = fma(-k, IP_LN2_LO, r);
+  double p = 1.6059043836821613e-10;
+  p = fma(r, p, 2.08767569878681e-09);
+  p = fma(r, p, 2.505210838544172e-08);
+  p = fma(r, p, 2.755731922398589e-07);
+  p = fma(r, p, 2.7557319223985893e-06);
+  p = fma(r, p, 2.48015873015873e-05);
+  p = fma(r, p, 0.0001984126984126984);
+  p = fma(r, p, 0.001388888888888889);
+  p = fma(r, p, 0.008333333333333333);
+  p = fma(r, p, 0.041666666666666664);
+  p = fma(r, p, 0.16666666666666666);
+  p = fma(r, p, 0.5);
+  p = fma(r, p, 1.0);
+  p = fma(r, p, 1.0);
+  return ldexp(p, (int)k);
+}
+
+// The FP32 exponential of the certified tier: the same reduction with the
+// FP32 split of ln 2 and the Taylor polynomial to degree 7; relative error
+// below 40 u32 on t in [-87, 0] (reduction below 1 u, truncation 0.1 u,
+// coefficient roundings 2 u, Horner at most 16 roundings on terms whose
+// absolute sum is at most twice the value), 0 below t = -87 (an absolute
+// error under 2e-38).
+__device__ __forceinline__ float exp32_own(float t) {
+  if (t < -87.0f) return 0.0f;
+  const float k = floorf(t * IP_INV_LN2_32 + 0.5f);
+  float r = fmaf(-k, IP_LN2_HI32, t);
+  r = fmaf(-k, IP_LN2_LO32, r);
+  float p = 1.984126984126984e-04f;
+  p = fmaf(r, p, 1.388888888888889e-03f);
+  p = fmaf(r, p, 8.333333333333333e-03f);
+  p = fmaf(r, p, 4.166666666666666e-02f);
+  p = fmaf(r, p, 1.666666666666667e-01f);
+  p = fmaf(r, p, 0.5f);
+  p = fmaf(r, p, 1.0f);
+  p = fmaf(r, p, 1.0f);
+  return ldexpf(p, (int)k);
+}
+
+// One canonical RBF term: alpha exp(-(gamma d2)) with d2 the fma chain of
+// (x_j - s_j)^2 over j, added to acc with an fma.
+template <int D>
+__device__ __forceinline__ double rbf_term(const double *sv, double al, double gamma, const double *x, double acc) {
+  double d2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const double df = x[j] - sv[j];
+    d2 = fma(df, df, d2);
+  }
+  return fma(al, exp_own(-(gamma * d2)), acc);
+}
 
 // FP32 monomial-basis form of f (see feval.hip).  c[0] is the constant term
 // (bias included), c[1..M-1] the monomial coefficients in depth-first order.
@@ -549,6 +635,8 @@ struct ip_problem {
   int64_t n_seeds = 0;
   PolyDev poly = {};
   void *poly_dev = nullptr;
+  RbfDev rbf = {};
+  void *rbf_dev = nullptr;
 };
 
 struct ip_cells {
@@ -596,6 +684,8 @@ int ip_feval_noalloc_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev
                           double *f_dev, double *bound_dev);
 int ip_region_eval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, int64_t n, int32_t *y, double *f,
                         double *bound, int32_t *np_out);
+// True when f has a certified FP32 form (polynomial of degree <= 4, or RBF).
+bool ip_has_fp32_form(const ip_problem *p);
 // Looks up this device's address of the ip_feval_noalloc scratch (once per
 // device) and stores it in ctx; the device must be current.
 int ip_noalloc_setup(ip_ctx *ctx);

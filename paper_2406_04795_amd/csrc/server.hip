@@ -26,7 +26,7 @@ struct OwnedRequest {
   ip_scene sc;
   bool has_scene = false;
   std::vector<double> sv, alpha, M, Minv, off, lo, hi, seeds;
-  std::vector<double> jT, lsc, lsr, lp0, lp1, lcr, osc, osr, obT, obl;
+  std::vector<double> jT, lsc, lsr, lp0, lp1, lcr, osc, osr, obT, obl, ocT, ocrh;
   std::vector<int32_t> jax, lsl, lcl;
   int64_t n_seeds = 0;
   int32_t k = 1, prec = IP_FP64;
@@ -74,9 +74,11 @@ void own(const ip_request *r, OwnedRequest &o) {
     o.osr = cp(s->osph_r, s->n_osph);
     o.obT = cp(s->obox_T, 12 * (int64_t)s->n_obox);
     o.obl = cp(s->obox_l, 3 * (int64_t)s->n_obox);
+    o.ocT = cp(s->ocyl_T, 12 * (int64_t)s->n_ocyl);
+    o.ocrh = cp(s->ocyl_rh, 2 * (int64_t)s->n_ocyl);
     o.sc = {s->n_joints, o.jT.data(), o.jax.data(), s->n_lsph, o.lsl.data(), o.lsc.data(), o.lsr.data(),
             s->n_lcap, o.lcl.data(), o.lp0.data(), o.lp1.data(), o.lcr.data(), s->n_osph, o.osc.data(),
-            o.osr.data(), s->n_obox, o.obT.data(), o.obl.data()};
+            o.osr.data(), s->n_obox, o.obT.data(), o.obl.data(), s->n_ocyl, o.ocT.data(), o.ocrh.data()};
   }
 }
 
@@ -113,7 +115,7 @@ struct ip_server {
     ip_problem *p = nullptr;
     ip_cells *c = nullptr;
     int rc = ip_problem_create(ctx, &q.f, &q.sp, q.seeds.data(), q.n_seeds, q.k, &p);
-    if (rc == IP_OK) rc = ip_trace(ctx, p, q.budget, q.prec, 0, &c);
+    if (rc == IP_OK) rc = ip_trace(ctx, p, q.budget, q.prec, q.flags & ~(uint32_t)IP_KEEP_CELLS, &c);
     if (rc == IP_OK && q.has_scene) rc = ip_check_cells(ctx, c, &q.sc, &r->n_free);
     if (rc == IP_OK) {
       uint64_t dg[2] = {0, 0};
@@ -203,6 +205,8 @@ int ip_server_create(ip_server **out, int device, uint64_t pool_bytes, int32_t m
     }
     s->streams.push_back(st);
     s->ctxs.push_back(c);
+    // the slots' idle caches together stay within the pool
+    c->cache.limit = s->pool / (uint64_t)max_slots;
   }
   for (int i = 0; i < max_slots; ++i) s->workers.emplace_back([s, i] { s->worker(i); });
   *out = s;

@@ -311,8 +311,15 @@ __device__ __forceinline__ bool edge_point(const LatDev &L, const PolyDev &Q, co
   double da = Q.B64, db = Q.B64;
   const bool exact = !cert || (ba < 0.0f && bb < 0.0f);
   if (!exact) {
-    if (ba >= 0.0f) fa = poly64_any<D>(Q, xa, &da);
-    if (bb >= 0.0f) fb = poly64_any<D>(Q, xb, &db);
+    if (Q.ok) {
+      // polynomial f: FP64 monomial values with their bounds
+      if (ba >= 0.0f) fa = poly64_any<D>(Q, xa, &da);
+      if (bb >= 0.0f) fb = poly64_any<D>(Q, xb, &db);
+    } else {
+      // no monomial form (RBF): the stored FP32-tier values with theirs
+      if (ba >= 0.0f) da = (double)ba;
+      if (bb >= 0.0f) db = (double)bb;
+    }
   }
   const double t = fa / (fa - fb);
 #pragma unroll
@@ -990,11 +997,14 @@ __global__ __launch_bounds__(kBlock) void batch_vertices_kernel(LatDev Lf, LatDe
   }
 }
 
-// Intersection points of the edges keys[lo .. hi) from the canonical FP64
-// values of their ends, looked up in the batch vertex table.
-template <int D>
+// Intersection points of the edges keys[lo .. hi) from the values of their
+// ends in the batch vertex table: canonical FP64 values, or (CERT) the
+// FP32-tier values with their bounds vb, an edge whose point the bound
+// cannot place within tolerance listed in redo (by its index in keys).
+template <int D, bool CERT>
 __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo, uint64_t hi, const VEnt *vt,
-                                    uint64_t vt_mask, double *pts, int64_t ld, PolyDev Q) {
+                                    const float *vb, uint64_t vt_mask, double *pts, int64_t ld, PolyDev Q,
+                                    uint64_t *redo, Counters *ctr) {
   for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (uint64_t)gridDim.x * blockDim.x) {
     int32_t a[D], b[D];
     uint32_t R;
@@ -1006,9 +1016,11 @@ __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo,
     const double fa = ha >= 0 ? vt[ha].f : NAN;
     const double fb = hb >= 0 ? vt[hb].f : NAN;
     double p[D];
-    edge_point<D>(L, Q, a, b, fa, fb, false, -1.0f, -1.0f, p);
+    const float ba = CERT && ha >= 0 ? vb[ha] : -1.0f, bb = CERT && hb >= 0 ? vb[hb] : -1.0f;
+    const bool ok = edge_point<D>(L, Q, a, b, fa, fb, CERT, ba, bb, p);
 #pragma unroll
     for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = p[j];
+    if (CERT && !ok) redo[atomicAdd(&ctr->n_aux, 1ull)] = i;
   }
 }
 
@@ -1636,11 +1648,12 @@ int lehmer_bits(int d) {
 }
 
 // Grows the SoA point buffer (columns of length ld) to hold hi rows, keeping
-// the first lo rows.
+// the first lo rows: to at least twice its size while batches append, to
+// exactly hi rows for the final size (exact).
 template <int D>
-int grow_points(ip_ctx *ctx, uint64_t lo, uint64_t hi, double *&pts, uint64_t &ld) {
+int grow_points(ip_ctx *ctx, uint64_t lo, uint64_t hi, double *&pts, uint64_t &ld, bool exact = false) {
   if (hi <= ld) return IP_OK;
-  const uint64_t nld = std::max<uint64_t>(hi, ld * 2);
+  const uint64_t nld = exact ? hi : std::max<uint64_t>(hi, ld * 2);
   double *np_ = nullptr;
   IP_TRY(alloc(ctx, (void **)&np_, nld * D * 8));
   if (pts && lo) {
@@ -1713,7 +1726,7 @@ struct BatchSink {
     if (n > dcap || !dkeys) IP_TRY(reserve_direct(std::max<uint64_t>(n, 1), n_dir));
     if (n_set) IP_TRY_HIP(ctx, hipMemcpyAsync(dkeys + n_dir, skeys, n_set * 8, hipMemcpyDeviceToDevice, ctx->stream));
     if (with_pts) {
-      IP_TRY(grow_points<D>(ctx, n_dir, std::max<uint64_t>(n, 1), dpts, dld));
+      IP_TRY(grow_points<D>(ctx, n_dir, std::max<uint64_t>(n, 1), dpts, dld, true));
       if (n_set)
         for (int j = 0; j < D; ++j)
           IP_TRY_HIP(ctx, hipMemcpyAsync(dpts + (uint64_t)j * dld + n_dir, spts + (uint64_t)j * sld, n_set * 8,
@@ -1830,6 +1843,10 @@ struct DevTmp {
 // values with the certified placement check, then the canonical FP64 values
 // at both ends of every edge the check rejects.
 template <int D>
+int redo_points(ip_ctx *ctx, const ip_problem *p, const uint64_t *keys, const uint64_t *redo, uint64_t nredo,
+                double *pts, uint64_t ld, int64_t &n_fallback);
+
+template <int D>
 int sub_points(ip_ctx *ctx, const ip_problem *p, const uint64_t *keys, uint64_t lo, uint64_t hi, double *pts,
                uint64_t ld, Timer &tp, ip_stats &st, int64_t &n_fallback) {
   if (hi <= lo) return IP_OK;
@@ -1843,7 +1860,14 @@ int sub_points(ip_ctx *ctx, const ip_problem *p, const uint64_t *keys, uint64_t 
   IP_TRY_HIP(ctx, hipGetLastError());
   IP_TRY(tp.stop(ctx));
   IP_TRY(read_ctr(ctx));
-  const uint64_t nredo = ctx->ctr_host->n_aux;
+  return redo_points<D>(ctx, p, keys, redo, ctx->ctr_host->n_aux, pts, ld, n_fallback);
+}
+
+// The points of the edges listed in redo (indices into keys), from canonical
+// FP64 values at both ends.
+template <int D>
+int redo_points(ip_ctx *ctx, const ip_problem *p, const uint64_t *keys, const uint64_t *redo, uint64_t nredo,
+                double *pts, uint64_t ld, int64_t &n_fallback) {
   if (nredo == 0) return IP_OK;
   DevTmp vraw(ctx), fr(ctx);
   IP_TRY(vraw.get(nredo * 2 * D * 4));
@@ -1996,9 +2020,10 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
 // that fits the budget fixes the batch size.
 template <int D>
 int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig_all, uint64_t nsig,
-                    uint64_t nc, uint64_t budget, ip_stats &st, ip_cells *res) {
+                    uint64_t nc, uint64_t budget, bool cert, ip_stats &st, ip_cells *res) {
   const int k = p->k, NP = a.NP, NE = a.NE;
-  const uint64_t slot_bytes = sizeof(VEnt) + 4;
+  // a slot: VEnt, eval-list entry and, certified, its bound and fallback entry
+  const uint64_t slot_bytes = sizeof(VEnt) + 4 + (cert ? 8 : 0);
   if (budget == 0) budget = 4ull << 30;
   uint64_t vcap_b = 0;
   for (uint64_t cc = 1024; cc <= (1ull << 32); cc <<= 1)
@@ -2018,6 +2043,14 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   f.vt = (VEnt *)ctx->vtf.keys.p;
   f.eval = (uint32_t *)ctx->vtf.eval.p;
   f.vt_cap = vcap;
+  f.cert = cert;
+  if (cert) {
+    IP_TRY(ip_ensure(ctx, ctx->vtf.vals, vcap * 4));
+    IP_TRY(ip_ensure(ctx, ctx->vtf.fb, vcap * 4));
+    f.vb = (float *)ctx->vtf.vals.p;
+    f.fb = (uint32_t *)ctx->vtf.fb.p;
+    f.fb_cap = ctx->vtf.fb.bytes / 4;
+  }
   uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
   BatchSink g(ctx);
   IP_TRY(init_sink<D>(g, nc, k));
@@ -2063,17 +2096,37 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
     // points of this batch's new edges, from the batch vertex table
     IP_TRY(grow_points<D>(ctx, dir_done, dir_hi, g.dpts, g.dld));
     IP_TRY(grow_points<D>(ctx, set_done, set_hi, g.spts, g.sld));
-    IP_TRY(tp.start(ctx, &st.ms_points));
-    if (dir_hi > dir_done)
-      hipLaunchKernelGGL((batch_points_kernel<D>), dim3(grid_for(dir_hi - dir_done)), dim3(kBlock), 0, ctx->stream,
-                         p->fine, (const uint64_t *)g.dkeys, dir_done, dir_hi, (const VEnt *)f.vt, vcap - 1, g.dpts,
-                         (int64_t)g.dld, p->poly);
-    if (set_hi > set_done)
-      hipLaunchKernelGGL((batch_points_kernel<D>), dim3(grid_for(set_hi - set_done)), dim3(kBlock), 0, ctx->stream,
-                         p->fine, (const uint64_t *)g.skeys, set_done, set_hi, (const VEnt *)f.vt, vcap - 1, g.spts,
-                         (int64_t)g.sld, p->poly);
-    IP_TRY_HIP(ctx, hipGetLastError());
-    IP_TRY(tp.stop(ctx));
+    struct Part {
+      const uint64_t *keys;
+      uint64_t lo, hi;
+      double *pts;
+      uint64_t ld;
+    };
+    const Part parts[2] = {{g.dkeys, dir_done, dir_hi, g.dpts, g.dld}, {g.skeys, set_done, set_hi, g.spts, g.sld}};
+    for (const Part &q : parts) {
+      if (q.hi <= q.lo) continue;
+      uint64_t *redo = nullptr;
+      if (cert) {
+        IP_TRY(ip_ensure(ctx, ctx->scratch, (q.hi - q.lo) * 8));
+        redo = (uint64_t *)ctx->scratch.p;
+        IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
+      }
+      IP_TRY(tp.start(ctx, &st.ms_points));
+      if (cert)
+        hipLaunchKernelGGL((batch_points_kernel<D, true>), dim3(grid_for(q.hi - q.lo)), dim3(kBlock), 0, ctx->stream,
+                           p->fine, q.keys, q.lo, q.hi, (const VEnt *)f.vt, (const float *)f.vb, vcap - 1, q.pts,
+                           (int64_t)q.ld, p->poly, redo, ctx->ctr_dev);
+      else
+        hipLaunchKernelGGL((batch_points_kernel<D, false>), dim3(grid_for(q.hi - q.lo)), dim3(kBlock), 0, ctx->stream,
+                           p->fine, q.keys, q.lo, q.hi, (const VEnt *)f.vt, (const float *)nullptr, vcap - 1, q.pts,
+                           (int64_t)q.ld, p->poly, (uint64_t *)nullptr, ctx->ctr_dev);
+      IP_TRY_HIP(ctx, hipGetLastError());
+      IP_TRY(tp.stop(ctx));
+      if (cert) {
+        IP_TRY(read_ctr(ctx));
+        IP_TRY(redo_points<D>(ctx, p, q.keys, redo, ctx->ctr_host->n_aux, q.pts, q.ld, f.n_fallback));
+      }
+    }
     dir_done = dir_hi;
     set_done = set_hi;
   }
@@ -2095,6 +2148,8 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   st.n_cells = (int64_t)n;
   st.n_batches = batches;
   st.regrows += f.regrows;
+  st.n_fallback += f.n_fallback;
+  st.n_settled64 += f.n_settled64;
   return IP_OK;
 }
 
@@ -2195,10 +2250,10 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
                   tpf_hold.as<uint64_t>(),
                   cvt, cvt_cap - 1};
   int rc;
-  if (cert)
+  if (cert && p->poly.ok)
     rc = subdivide_fused<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, st, res);
   else
-    rc = subdivide_table<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, st, res);
+    rc = subdivide_table<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, cert, st, res);
   (void)hipStreamSynchronize(ctx->stream);
   st.regrows += s.regrows;
   st.n_fallback += s.n_fallback;
@@ -2245,7 +2300,7 @@ int direct_points(Run &s, uint64_t n, uint64_t *keys, double *pts, ip_stats &st)
 
 template <int D>
 int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_cells *res) {
-  const bool cert = prec == IP_FP32_CERTIFY && p->poly.ok;
+  const bool cert = prec == IP_FP32_CERTIFY && ip_has_fp32_form(p);
   if (p->k != 1) return trace_batch<D>(ctx, p, budget, cert, res);
   Run s;
   s.ctx = ctx;
@@ -2375,6 +2430,166 @@ int region_eval_T(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, int64_t
   return IP_OK;
 }
 
+// Iterative intersection points (Sec. V-B; Sec. VI: the point is refined
+// by an iteration until a desired accuracy), ITERS false-position steps with
+// the Illinois modification on every traced edge, a fixed count so that the
+// lanes of a wave stay in step.  The bracket starts as the edge (a the
+// smaller endpoint); each step evaluates f at the false-position point m,
+// moves the end whose sign bit s = !(f < 0) equals s(m), and halves the value
+// kept at the other end when the same end moved twice in a row; the result
+// is the false-position point of the final bracket.  CANON: f in the
+// canonical FP64 order (the support vectors as wave-uniform scalar loads),
+// so the points equal the oracle's bit for bit; otherwise f from the FP64
+// monomial form (FP32-certified mode, points within the stated tolerance).
+// R edges per lane share each support-vector load.
+template <int D, int P, int R, bool CANON>
+__global__ __launch_bounds__(256) void refine_kernel(LatDev L, const uint64_t *__restrict__ keys, uint64_t n,
+                                                     double *pts, int64_t ld, FDev F, PolyDev Q, int iters) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * R;
+  for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * R; base < n; base += stride) {
+    double a[R][D], b[R][D], m[R][D], fa[R], fb[R], fm[R];
+    int last[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t i = base + r < n ? base + r : n - 1;
+      int32_t va[D], vb[D];
+      uint32_t Rm;
+      eunpack<D>(L, keys[i], va, &Rm);
+#pragma unroll
+      for (int j = 0; j < D; ++j) vb[j] = va[j] + (int32_t)((Rm >> j) & 1u);
+      lat_coords<D>(L, va, a[r]);
+      lat_coords<D>(L, vb, b[r]);
+      last[r] = 0;
+    }
+    // f at the R points held in x[r]: canonical order or monomial form
+    auto feval = [&](double (*x)[D], double *out) {
+      if (CANON && F.kernel == IP_KERNEL_RBF) {
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        for (int64_t s = 0; s < F.S; ++s) {
+          const double *rec = F.rec + s * 8;
+          double sv[D];
+#pragma unroll
+          for (int j = 0; j < D; ++j) sv[j] = rec[j];
+          const double al = rec[D];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] = rbf_term<D>(sv, al, F.gamma, x[r], acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[r] = acc[r] + F.bias;
+      } else if (CANON) {
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        for (int64_t s = 0; s < F.S; ++s) {
+          const double *rec = F.rec + s * 8;
+          double sv[D];
+#pragma unroll
+          for (int j = 0; j < D; ++j) sv[j] = rec[j];
+          const double al = rec[D];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            double dot = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) dot = fma(sv[j], x[r][j], dot);
+            const double t = fma(F.gamma, dot, F.coef0);
+            double tp = t;
+            if (P > 0) {
+#pragma unroll
+              for (int q = 1; q < P; ++q) tp = tp * t;
+            } else {
+              for (int q = 1; q < F.p; ++q) tp = tp * t;
+            }
+            acc[r] = fma(al, tp, acc[r]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[r] = acc[r] + F.bias;
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          double bnd;
+          out[r] = poly64<D, (P > 0 ? P : 4)>(Q, x[r], &bnd);
+        }
+      }
+    };
+    feval(a, fa);
+    feval(b, fb);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double t = fa[r] / (fa[r] - fb[r]);
+#pragma unroll
+        for (int j = 0; j < D; ++j) m[r][j] = fma(t, b[r][j] - a[r][j], a[r][j]);
+      }
+      feval(m, fm);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!(fm[r] < 0.0) == !(fa[r] < 0.0)) {
+#pragma unroll
+          for (int j = 0; j < D; ++j) a[r][j] = m[r][j];
+          fa[r] = fm[r];
+          if (last[r] == -1) fb[r] = 0.5 * fb[r];
+          last[r] = -1;
+        } else {
+#pragma unroll
+          for (int j = 0; j < D; ++j) b[r][j] = m[r][j];
+          fb[r] = fm[r];
+          if (last[r] == 1) fa[r] = 0.5 * fa[r];
+          last[r] = 1;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (base + r >= n) continue;
+      const double t = fa[r] / (fa[r] - fb[r]);
+#pragma unroll
+      for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)(base + r)] = fma(t, b[r][j] - a[r][j], a[r][j]);
+    }
+  }
+}
+
+template <int D, bool CANON>
+void launch_refine(ip_ctx *ctx, const ip_problem *p, const ip_cells *c, int iters) {
+  constexpr int R = 2;
+  const uint64_t n = (uint64_t)c->n;
+  const uint64_t blocks = std::min<uint64_t>((n + 256 * R - 1) / (256 * R), 65536);
+  const int P = CANON ? p->f.p : p->poly.p;
+#define IP_RF(PP)                                                                                              \
+  hipLaunchKernelGGL((refine_kernel<D, PP, R, CANON>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, p->fine, \
+                     (const uint64_t *)c->keys, n, c->pts, c->ld, p->f, p->poly, iters)
+  switch (P) {
+    case 1: IP_RF(1); break;
+    case 2: IP_RF(2); break;
+    case 3: IP_RF(3); break;
+    case 4: IP_RF(4); break;
+    default: IP_RF(0); break;
+  }
+#undef IP_RF
+}
+
+// Refine the points of the traced cells in place (no effect for iters = 0).
+template <int D>
+int refine_T(ip_ctx *ctx, const ip_problem *p, int32_t prec, int iters, ip_cells *c) {
+  c->st.refine_iters = iters;
+  if (iters <= 0 || c->n == 0) return IP_OK;
+  // the FP32-certified mode refines with the FP64 monomial form when f has
+  // one (polynomial), else with the canonical values
+  const bool canon = !(prec == IP_FP32_CERTIFY && p->poly.ok);
+  Timer tr;
+  IP_TRY(tr.start(ctx, &c->st.ms_refine));
+  if (canon)
+    launch_refine<D, true>(ctx, p, c, iters);
+  else
+    launch_refine<D, false>(ctx, p, c, iters);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  IP_TRY(tr.stop(ctx));
+  IP_TRY(tr.flush(ctx));
+  return IP_OK;
+}
+
 }  // namespace
 
 int ip_region_eval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, int64_t n, int32_t *y, double *f,
@@ -2392,14 +2607,14 @@ int ip_region_eval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, i
 
 int ip_trace_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, uint32_t flags,
                   ip_cells *out) {
-  (void)flags;
+  const int iters = (int)((flags >> 4) & 15u);
   switch (p->d) {
-    case 2: return trace_T<2>(ctx, p, budget, prec, out);
-    case 3: return trace_T<3>(ctx, p, budget, prec, out);
-    case 4: return trace_T<4>(ctx, p, budget, prec, out);
-    case 5: return trace_T<5>(ctx, p, budget, prec, out);
-    case 6: return trace_T<6>(ctx, p, budget, prec, out);
-    case 7: return trace_T<7>(ctx, p, budget, prec, out);
+    case 2: IP_TRY(trace_T<2>(ctx, p, budget, prec, out)); return refine_T<2>(ctx, p, prec, iters, out);
+    case 3: IP_TRY(trace_T<3>(ctx, p, budget, prec, out)); return refine_T<3>(ctx, p, prec, iters, out);
+    case 4: IP_TRY(trace_T<4>(ctx, p, budget, prec, out)); return refine_T<4>(ctx, p, prec, iters, out);
+    case 5: IP_TRY(trace_T<5>(ctx, p, budget, prec, out)); return refine_T<5>(ctx, p, prec, iters, out);
+    case 6: IP_TRY(trace_T<6>(ctx, p, budget, prec, out)); return refine_T<6>(ctx, p, prec, iters, out);
+    case 7: IP_TRY(trace_T<7>(ctx, p, budget, prec, out)); return refine_T<7>(ctx, p, prec, iters, out);
     default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
   }
 }

@@ -24,7 +24,8 @@ PI = math.pi
 
 @dataclass
 class Manifold:
-    """f(x) = sum_i alpha_i (gamma <s_i, x> + coef0)^p + bias."""
+    """f(x) = sum_i alpha_i K(s_i, x) + bias with the polynomial kernel
+    K = (gamma <s_i, x> + coef0)^p or the RBF kernel K = exp(-gamma |x - s_i|^2)."""
 
     d: int
     p: int
@@ -33,6 +34,7 @@ class Manifold:
     bias: float
     sv: np.ndarray      # (S, d) float64
     alpha: np.ndarray   # (S,) float64
+    kernel: str = "poly"  # "poly" or "rbf"
 
     @property
     def S(self) -> int:
@@ -72,6 +74,8 @@ class Scene:
     osph_r: np.ndarray = field(default_factory=lambda: np.zeros(0))
     obox_T: np.ndarray = field(default_factory=lambda: np.zeros((0, 12)))
     obox_l: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    ocyl_T: np.ndarray = field(default_factory=lambda: np.zeros((0, 12)))   # axis = local z
+    ocyl_rh: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))   # radius, height
 
 
 @dataclass
@@ -117,6 +121,13 @@ def box(d: int, half: float = PI) -> Domain:
 # --------------------------------------------------------------------------
 def _f0(fm: Manifold, X: np.ndarray, chunk: int = 8192) -> np.ndarray:
     out = np.empty(X.shape[0])
+    if fm.kernel == "rbf":
+        s2 = (fm.sv ** 2).sum(1)
+        for a in range(0, X.shape[0], chunk):
+            Xa = X[a:a + chunk]
+            d2 = np.maximum((Xa ** 2).sum(1)[:, None] + s2[None, :] - 2.0 * (Xa @ fm.sv.T), 0.0)
+            out[a:a + chunk] = np.exp(-fm.gamma * d2) @ fm.alpha
+        return out
     for a in range(0, X.shape[0], chunk):
         t = fm.gamma * (X[a:a + chunk] @ fm.sv.T) + fm.coef0
         tp = t.copy()
@@ -152,6 +163,26 @@ def sphere_manifold(d: int, R: float, center=None) -> Manifold:
     sv = np.eye(d)
     return Manifold(d=d, p=2, gamma=1.0, coef0=-c, bias=-R * R,
                     sv=np.ascontiguousarray(sv), alpha=np.ones(d))
+
+
+def rbf_manifold(d, S, rng, dom: Domain, gamma=None, width=0.6) -> Manifold:
+    """RBF-kernel decision function: S support vectors uniform in the box,
+    alpha ~ N(0, 1); gamma = 1 / (2 (width * box half-width)^2) unless given,
+    so one kernel reaches about `width` of the half-width."""
+    sv = rng.uniform(dom.lo, dom.hi, size=(S, d))
+    a = rng.standard_normal(S)
+    half = float(np.max(dom.hi - dom.lo)) / 2.0
+    g = 1.0 / (2.0 * (width * half) ** 2) if gamma is None else gamma
+    return Manifold(d=d, p=1, gamma=float(g), coef0=0.0, bias=0.0, sv=np.ascontiguousarray(sv),
+                    alpha=np.ascontiguousarray(a), kernel="rbf")
+
+
+def rbf_sphere_manifold(d: int, R: float, gamma: float = 1.0, center=None) -> Manifold:
+    """exp(-gamma |x - c|^2) - exp(-gamma R^2): one support vector, zero set
+    the sphere of radius R around c, positive inside."""
+    c = np.zeros(d) if center is None else np.asarray(center, float)
+    return Manifold(d=d, p=1, gamma=float(gamma), coef0=0.0, bias=-math.exp(-gamma * R * R),
+                    sv=np.ascontiguousarray(c[None, :]), alpha=np.ones(1), kernel="rbf")
 
 
 def closed_quadratic_bias(fm: Manifold, dom: Domain, rng, n_probe=20000) -> float:
@@ -257,7 +288,8 @@ _SPATIAL_AXES = [2, 1, 1, 2, 1, 2, 1]
 
 def spatial_arm_scene(rng, n_links, link=0.3, capsule_r=None, spheres_per_link=0,
                       sphere_r=0.05, n_osph=8, osph_r=(0.1, 0.3), n_obox=0,
-                      obox_l=(0.1, 0.4), obst_ball=None) -> Scene:
+                      obox_l=(0.1, 0.4), obst_ball=None, n_ocyl=0, ocyl_r=(0.05, 0.2),
+                      ocyl_h=(0.2, 0.8)) -> Scene:
     """Spatial nR arm: axes z,y,y,z,y,z,...; links of length `link` along z.
 
     Obstacle centres are drawn in the reach ball (radii between 0.58 and 1
@@ -290,6 +322,10 @@ def spatial_arm_scene(rng, n_links, link=0.3, capsule_r=None, spheres_per_link=0
     if n_obox:
         sc.obox_T = np.stack([_T(_random_rotation(rng), t) for t in in_ball(n_obox)])
         sc.obox_l = rng.uniform(obox_l[0], obox_l[1], size=(n_obox, 3))
+    if n_ocyl:
+        sc.ocyl_T = np.stack([_T(_random_rotation(rng), t) for t in in_ball(n_ocyl)])
+        sc.ocyl_rh = np.stack([rng.uniform(ocyl_r[0], ocyl_r[1], n_ocyl),
+                               rng.uniform(ocyl_h[0], ocyl_h[1], n_ocyl)], 1)
     return sc
 
 
@@ -328,6 +364,30 @@ def cubic_case(d, S, lam, eps, seed=0, n_seeds=8, k=1, scene=None) -> Workload:
     lat = make_lattice(d, lam, rng)
     seeds = bisection_seeds(fm, dom, rng, n_seeds)
     return Workload(f"cubic_d{d}_S{S}", fm, lat, dom, seeds, k, scene)
+
+
+def rbf_sphere_case(d: int, R: float, lam: float, gamma: float = 1.0, seed: int = 0,
+                    half=None) -> Workload:
+    """The one-support-vector RBF sphere; a closed component for the pins."""
+    rng = np.random.default_rng(seed)
+    dom = box(d, half if half is not None else R + 4 * lam * d + 0.5)
+    fm = rbf_sphere_manifold(d, R, gamma)
+    lat = make_lattice(d, lam, rng)
+    u = rng.standard_normal((1, d))
+    seeds = R * u / np.linalg.norm(u, axis=1, keepdims=True)
+    return Workload(f"rbf_sphere_d{d}", fm, lat, dom, np.ascontiguousarray(seeds))
+
+
+def rbf_case(d, S, lam, eps, seed=0, n_seeds=8, k=1, width=0.6, scene=None) -> Workload:
+    """RBF-kernel decision function (the kernel the paper's SVM is trained
+    with), S support vectors, bias at the eps-quantile of the kernel sum."""
+    rng = np.random.default_rng(seed)
+    dom = box(d)
+    fm = rbf_manifold(d, S, rng, dom, width=width)
+    fm.bias = quantile_bias(fm, dom, rng, eps, n_probe=100000)
+    lat = make_lattice(d, lam, rng)
+    seeds = bisection_seeds(fm, dom, rng, n_seeds)
+    return Workload(f"rbf_d{d}_S{S}", fm, lat, dom, seeds, k, scene)
 
 
 def config_c1(seed=0) -> Workload:

@@ -30,10 +30,17 @@ _ip = C.POINTER(C.c_int32)
 _vp = C.c_void_p
 
 
+IP_KERNEL_POLY, IP_KERNEL_RBF = 0, 1
+
+
 class ip_fparams(C.Structure):
     _fields_ = [("d", C.c_int32), ("degree", C.c_int32), ("n_sv", C.c_int64),
                 ("gamma", C.c_double), ("coef0", C.c_double), ("bias", C.c_double),
-                ("sv", _dp), ("alpha", _dp)]
+                ("sv", _dp), ("alpha", _dp), ("kernel", C.c_int32)]
+
+
+def _kernel_code(f):
+    return IP_KERNEL_RBF if getattr(f, "kernel", "poly") == "rbf" else IP_KERNEL_POLY
 
 
 class ip_space(C.Structure):
@@ -47,7 +54,8 @@ class ip_scene(C.Structure):
                 ("n_lcap", C.c_int32), ("lcap_link", _ip), ("lcap_p0", _dp), ("lcap_p1", _dp),
                 ("lcap_r", _dp),
                 ("n_osph", C.c_int32), ("osph_c", _dp), ("osph_r", _dp),
-                ("n_obox", C.c_int32), ("obox_T", _dp), ("obox_l", _dp)]
+                ("n_obox", C.c_int32), ("obox_T", _dp), ("obox_l", _dp),
+                ("n_ocyl", C.c_int32), ("ocyl_T", _dp), ("ocyl_rh", _dp)]
 
 
 class ip_stats(C.Structure):
@@ -59,7 +67,8 @@ class ip_stats(C.Structure):
                 ("ms_points", C.c_double), ("ms_check", C.c_double), ("ms_subdivide", C.c_double),
                 ("subdivide_launches", C.c_int64), ("n_edge_hits", C.c_int64),
                 ("n_coarse_edges", C.c_int64), ("n_shared_probes", C.c_int64),
-                ("ms_sigma", C.c_double), ("n_ncofaces", C.c_int64), ("n_hip_malloc", C.c_int64), ("hip_malloc_bytes", C.c_int64)]
+                ("ms_sigma", C.c_double), ("n_ncofaces", C.c_int64), ("n_hip_malloc", C.c_int64), ("hip_malloc_bytes", C.c_int64),
+                ("ms_refine", C.c_double), ("refine_iters", C.c_int32), ("pad0", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,6 +89,11 @@ class ip_result(C.Structure):
 
 
 IP_KEEP_CELLS = 1
+
+
+def IP_REFINE(n: int) -> int:
+    """ip_trace flag: n (0..15) iterations of the iterative intersection."""
+    return (int(n) & 15) << 4
 
 _P = C.POINTER
 _sig = {
@@ -172,7 +186,7 @@ def ip_last_error(ctx) -> str:
 def ip_problem_create(ctx, f, lat, dom, seeds, coarse_k=1):
     """f: inputs.Manifold, lat: inputs.Lattice, dom: inputs.Domain."""
     keep = []
-    fp = ip_fparams(f.d, f.p, f.S, f.gamma, f.coef0, f.bias, _d(keep, f.sv), _d(keep, f.alpha))
+    fp = ip_fparams(f.d, f.p, f.S, f.gamma, f.coef0, f.bias, _d(keep, f.sv), _d(keep, f.alpha), _kernel_code(f))
     sp = ip_space(f.d, _d(keep, lat.M), _d(keep, lat.Minv), _d(keep, lat.o), _d(keep, dom.lo),
                   _d(keep, dom.hi))
     seeds = np.ascontiguousarray(seeds, dtype=np.float64)
@@ -251,7 +265,8 @@ def _scene_struct(sc, keep):
                     len(sc.lcap_r), _i(keep, sc.lcap_link), _d(keep, sc.lcap_p0),
                     _d(keep, sc.lcap_p1), _d(keep, sc.lcap_r),
                     len(sc.osph_r), _d(keep, sc.osph_c), _d(keep, sc.osph_r),
-                    len(sc.obox_l), _d(keep, sc.obox_T), _d(keep, sc.obox_l))
+                    len(sc.obox_l), _d(keep, sc.obox_T), _d(keep, sc.obox_l),
+                    len(sc.ocyl_rh), _d(keep, sc.ocyl_T), _d(keep, sc.ocyl_rh))
 
 
 def ip_check(ctx, scene, q_dev_ptr: int, n: int, ld: int, verdict_dev_ptr: int):
@@ -337,10 +352,10 @@ class Problem:
 
 
 class Cells:
-    def __init__(self, ctx: Context, prob: Problem, budget=0, precision=IP_FP64):
+    def __init__(self, ctx: Context, prob: Problem, budget=0, precision=IP_FP64, flags=0):
         self.ctx = ctx
         self.d = prob.d
-        self.h = ip_trace(ctx.h, prob.h, budget, precision)
+        self.h = ip_trace(ctx.h, prob.h, budget, precision, flags)
         self.n_free = None
 
     @property
@@ -389,7 +404,7 @@ def ip_server_submit(server, wl, precision=IP_FP64, scene=None, budget=0, mem_by
     """Queue workload wl (inputs.Workload); returns the request id."""
     keep = []
     f = wl.f
-    fp = ip_fparams(f.d, f.p, f.S, f.gamma, f.coef0, f.bias, _d(keep, f.sv), _d(keep, f.alpha))
+    fp = ip_fparams(f.d, f.p, f.S, f.gamma, f.coef0, f.bias, _d(keep, f.sv), _d(keep, f.alpha), _kernel_code(f))
     sp = ip_space(f.d, _d(keep, wl.lat.M), _d(keep, wl.lat.Minv), _d(keep, wl.lat.o),
                   _d(keep, wl.dom.lo), _d(keep, wl.dom.hi))
     seeds = np.ascontiguousarray(wl.seeds, dtype=np.float64)

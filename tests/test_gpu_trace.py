@@ -132,7 +132,7 @@ def _check_gpu(ip, ctx, scene, q):
     return vd.cpu().numpy()[:n]
 
 
-@pytest.mark.parametrize("which", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("which", ["c1", "c2", "c3", "c3_scene", "cylinders"])
 def test_check_verdicts_bitwise(ip, ctx, which):
     rng = np.random.default_rng(11)
     if which == "c1":
@@ -142,9 +142,19 @@ def test_check_verdicts_bitwise(ip, ctx, which):
     elif which == "c2":
         sc = I.spatial_arm_scene(np.random.default_rng(100), 5, capsule_r=0.05, n_osph=8)
         d = 5
-    else:
+    elif which == "c3":
         sc = I.spatial_arm_scene(np.random.default_rng(200), 6, spheres_per_link=3,
                                  sphere_r=0.05, n_osph=8, n_obox=8)
+        d = 6
+    elif which == "c3_scene":
+        # the benchmark's cluttered scene (obstacles around the shoulder)
+        sc = I.spatial_arm_scene(np.random.default_rng(I.C3_SCENE_STREAM), 6, spheres_per_link=3,
+                                 sphere_r=0.05, n_osph=8, n_obox=8, obst_ball=I.C3_OBST_BALL)
+        d = 6
+    else:
+        # spheres, boxes and cylinders (Appendix A), many spheres per link
+        sc = I.spatial_arm_scene(np.random.default_rng(300), 6, spheres_per_link=8, sphere_r=0.04,
+                                 n_osph=4, n_obox=4, n_ocyl=8, obst_ball=((0.0, 0.0, 0.3), 1.2))
         d = 6
     n = 20000 + 77
     q = rng.uniform(-np.pi, np.pi, size=(n, d))

@@ -213,3 +213,71 @@ def test_closed_box_keeps_edges_ending_exactly_on_lo_and_hi():
                    any(abs(e[0][j] + ((e[1] >> j) & 1)) == n_side for j in range(3))]
     # an open box would drop exactly these
     assert len(on_boundary) >= 24
+
+
+# --------------------------------------------------------------------------
+# Sphere vs cylinder (Appendix A)
+# --------------------------------------------------------------------------
+def _cyl_dist2(c, T, rc, h):
+    """Squared distance from c to the solid cylinder: radial and axial
+    clamps in the cylinder frame (the textbook closest point)."""
+    Tm = np.asarray(T).reshape(3, 4)
+    p = Tm[:, :3].T @ (np.asarray(c, float) - Tm[:, 3])
+    rho = math.hypot(p[0], p[1])
+    return max(rho - rc, 0.0) ** 2 + max(abs(p[2]) - h / 2, 0.0) ** 2
+
+
+def test_sphere_cylinder_matches_clamp_distance():
+    """Random poses, sizes and centres, away from exact contact.  Catches a
+    missing fold into the first octant (the far half of the cylinder), the
+    padded test with the wrong radius sum, and the ring region taken for the
+    flat face or the side (their distances differ there)."""
+    rng = np.random.default_rng(12)
+    checked = 0
+    for _ in range(6000):
+        T = I._T(I._random_rotation(rng), rng.uniform(-1, 1, 3))
+        rc, h = rng.uniform(0.05, 0.8), rng.uniform(0.1, 1.5)
+        c = rng.uniform(-2, 2, 3)
+        r = rng.uniform(0.01, 0.7)
+        d2 = _cyl_dist2(c, T, rc, h)
+        if abs(d2 - r * r) < 1e-9:
+            continue
+        assert O.sphere_cylinder(c, r, T, rc, h) == (d2 <= r * r)
+        checked += 1
+    assert checked > 5900
+
+
+def test_sphere_cylinder_exact_contacts():
+    """Touching collides (Appendix A: no collision only beyond the radius),
+    on each region, with dyadic sizes so the contacts are exact: flat face,
+    curved side, and the rim (ring region) at the 3-4-5 distance 1.25."""
+    T = I._T()
+    rc, h = 1.0, 2.0
+    # flat face z = 1
+    assert O.sphere_cylinder([0.25, 0.0, 1.5], 0.5, T, rc, h) == 1
+    assert O.sphere_cylinder([0.25, 0.0, 1.5], 0.4375, T, rc, h) == 0
+    # curved side rho = 1
+    assert O.sphere_cylinder([1.5, 0.0, 0.25], 0.5, T, rc, h) == 1
+    assert O.sphere_cylinder([0.0, -1.5, 0.25], 0.4375, T, rc, h) == 0
+    # rim: rho - rc = 0.75, z - h/2 = 1, distance 1.25
+    assert O.sphere_cylinder([1.75, 0.0, 2.0], 1.25, T, rc, h) == 1
+    assert O.sphere_cylinder([0.0, 1.75, -2.0], 1.25, T, rc, h) == 1
+    assert O.sphere_cylinder([1.75, 0.0, 2.0], 1.1875, T, rc, h) == 0
+    # inside
+    assert O.sphere_cylinder([0.1, 0.2, 0.3], 0.01, T, rc, h) == 1
+
+
+def test_link_spheres_against_an_obstacle_cylinder():
+    """The 6R arm turned onto +x (joint 1 a quarter turn about y): a vertical
+    cylinder whose side is 0.03 (collides) or 0.07 (free) from the link
+    sphere at (1.05, 0, 0.3) (r = 0.05); a mirrored one on -x stays free."""
+    q1 = np.array([0, math.pi / 2, 0, 0, 0, 0])
+    for gap, hit in ((0.03, 1), (0.07, 0)):
+        rc = 0.1
+        sc = _arm_with()
+        # beside the sphere at (1.05, 0, 0.3), along +y
+        sc.ocyl_T = np.stack([I._T(None, (1.05, gap + rc, 0.3))])
+        sc.ocyl_rh = np.array([[rc, 0.4]])
+        assert O.check(sc, [q1])[0] == hit
+        sc.ocyl_T = np.stack([I._T(None, (-1.05, gap + rc, 0.3))])
+        assert O.check(sc, [q1])[0] == 0
