@@ -266,6 +266,139 @@ def latency_summary(res):
             "requests": len(res)}
 
 
+def request_sizes(res):
+    """Per-request cells and admitted (projected) bytes, as quantiles."""
+    q = [0, 10, 50, 90, 100]
+    n = np.array([r["n_cells"] for r in res], dtype=float)
+    b = np.array([r["admitted_bytes"] for r in res], dtype=float)
+    return {"cells_quantiles": dict(zip(map(str, q), np.percentile(n, q).round().astype(int).tolist())),
+            "admitted_gib_quantiles": dict(zip(map(str, q), np.round(np.percentile(b, q) / 2 ** 30, 4).tolist())),
+            "cells_by_d": {str(d): int(sum(r["n_cells"] for r in res if r["d"] == d)) for d in sorted({r["d"] for r in res})}}
+
+
+def leg(ip, wl, prec, steps, flags=0, budget=0):
+    """Warm-up plus `steps` timed traces (and checks, with a scene) of wl."""
+    import torch
+    ctx = ip.Context(0)
+    prob = ip.Problem(ctx, wl)
+    try:
+        def one():
+            c = ip.Cells(ctx, prob, budget=budget, precision=prec, flags=flags)
+            if wl.scene is not None:
+                c.check(wl.scene)
+            st = c.stats()
+            c.close()
+            return st
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [one() for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+    finally:
+        prob.close()
+        ctx.close()
+    st = sts[-1]
+    return {"simplices_per_s": st["n_cells"] / el, "ms_per_step": round(el * 1e3, 3), "cells": st["n_cells"],
+            "vertices_evaluated": st["n_vertices"], "fp64_canonical_evals": st["n_fallback"],
+            "settled_by_fp64_monomial": st["n_settled64"],
+            "fallback_rate": st["n_fallback"] / max(1, st["n_vertices"]),
+            "phases_ms": {"trace": phase(sts, "ms_total"), "refine": phase(sts, "ms_refine"),
+                          "check": phase(sts, "ms_check")}}
+
+
+def cfree_leg(ip, wl, prec, budget, n_free, steps=3):
+    """Trace + check + the C_free points to pinned host memory, per step."""
+    import torch
+    if wl.scene is None:
+        return None
+    host = torch.empty(max(1, n_free * wl.f.d), dtype=torch.float64, pin_memory=True)
+    ctx = ip.Context(0)
+    prob = ip.Problem(ctx, wl)
+    try:
+        def one():
+            c = ip.Cells(ctx, prob, budget=budget, precision=prec)
+            nf = c.check(wl.scene)
+            assert nf * wl.f.d <= host.numel()
+            t0 = time.perf_counter()
+            ip.ip_cells_download_free(ctx.h, c.h, host.data_ptr())
+            t_copy = time.perf_counter() - t0
+            n = c.n
+            c.close()
+            return n, nf, t_copy
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [one() for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+    finally:
+        prob.close()
+        ctx.close()
+    n, nf, _ = res[-1]
+    t_copy = float(np.mean([r[2] for r in res]))
+    return {"simplices_per_s": n / el, "ms_per_step": round(el * 1e3, 3), "free_points": nf,
+            "d2h_ms": round(t_copy * 1e3, 3), "d2h_gbs": round(nf * wl.f.d * 8 / t_copy / 1e9, 2)}
+
+
+def extra_legs(ip, wls, main_wl):
+    """The other workloads of the suite, one line each: the d=5 arm (C2), the
+    precision stress at its scale (C5, with its FP64 fallback rate), an
+    RBF-kernel manifold, the iterative intersection on the benchmark
+    workload, and the seed search on the benchmark's f."""
+    import torch
+    out = {}
+    for name, wl in wls.items():
+        print(f"[bench] leg {name}: d={wl.f.d} S={wl.f.S} k={wl.k} kernel={wl.f.kernel}", file=sys.stderr, flush=True)
+        out[name] = {"workload": wl.name,
+                     "fp32_certify": leg(ip, wl, ip.IP_FP32_CERTIFY, 3),
+                     "fp64": leg(ip, wl, ip.IP_FP64, 2)}
+    # iterative intersection: 4 false-position steps on every cell of the
+    # benchmark workload (FP32-certified mode: FP64 monomial values)
+    print("[bench] leg refine4", file=sys.stderr, flush=True)
+    r = leg(ip, main_wl, ip.IP_FP32_CERTIFY, 3, flags=ip.IP_REFINE(4), budget=64 << 30)
+    from math import comb
+    d, p = main_wl.f.d, main_wl.f.p
+    per_edge = 6 * (5 * (comb(d + p, p) - 1) + 2) + 2 * 2 * d * d + 5 * (3 * d + 2)
+    ms = r["phases_ms"]["refine"]
+    tfs = per_edge * r["cells"] / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    r["refine_kernel"] = {"bound": "alu", "achieved": round(tfs, 3), "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(tfs / VECTOR_PEAK_TFLOPS, 4), "flops_per_cell": per_edge, "ms": ms}
+    out["refine4_bench_workload"] = r
+    # seed search: 2^20 starts, 20 Newton steps each, canonical FP64 f + grad
+    print("[bench] leg seeds", file=sys.stderr, flush=True)
+    n, iters = 1 << 20, 20
+    ctx = ip.Context(0)
+    prob = ip.Problem(ctx, main_wl)
+    try:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(3)
+        lo = torch.tensor(main_wl.dom.lo, device="cuda")
+        hi = torch.tensor(main_wl.dom.hi, device="cuda")
+        q0 = (lo + (hi - lo) * torch.rand((n, d), generator=g, device="cuda", dtype=torch.float64)).contiguous()
+        q = torch.empty_like(q0)
+        fq = torch.empty(n, dtype=torch.float64, device="cuda")
+        ip.ip_seed_search(ctx.h, prob.h, q0.data_ptr(), n, iters, q.data_ptr(), fq.data_ptr())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ip.ip_seed_search(ctx.h, prob.h, q0.data_ptr(), n, iters, q.data_ptr(), fq.data_ptr())
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        scale = float(np.abs(main_wl.f.alpha).sum()) * 1e-9
+        on = int((fq.abs() < scale).sum())
+    finally:
+        prob.close()
+        ctx.close()
+    per_sv = 4 * d + p + 5
+    tfs = n * (iters + 1) * main_wl.f.S * per_sv / el / 1e12
+    out["seed_search_bench_f"] = {"starts": n, "iters": iters, "ms": round(el * 1e3, 3),
+                                  "starts_per_s": n / el, "on_manifold": on,
+                                  "kernel": {"bound": "alu", "achieved": round(tfs, 3), "peak": VECTOR_PEAK_TFLOPS,
+                                             "unit": "TFLOP/s", "frac": round(tfs / VECTOR_PEAK_TFLOPS, 4),
+                                             "flops_per_sv_step": per_sv}}
+    return out
+
+
 def _gen_requests(span):
     from paper_2406_04795_amd import inputs as I
     return [I.serving_request(i) for i in range(*span)]
@@ -283,6 +416,7 @@ def main():
     ap.add_argument("--serve", type=int, default=256, help="serving requests (0: skip)")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", type=int, default=1, help="run the other workloads' lines (0: skip)")
     ap.add_argument("--workload-cache", default="",
                     help="pickle of the generated workload: loaded if present, else written (profiling runs)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -314,6 +448,11 @@ def main():
             import pickle
             with open(args.workload_cache, "wb") as fh:
                 pickle.dump(wl, fh)
+    extras = {}
+    if args.legs:
+        from paper_2406_04795_amd import inputs as I
+        extras = {"c2_d5": I.config_c2(eps=3e-4), "c5_stress_d5": I.config_c5(),
+                  "rbf_d5": I.rbf_case(5, 500, 0.15, 0.1, seed=1, n_seeds=4)}
     reqs = []
     if args.serve:
         from concurrent.futures import ProcessPoolExecutor
@@ -422,15 +561,20 @@ def main():
     for prec in precs:
         out["fp32_certify" if prec == ip.IP_FP32_CERTIFY else "fp64"] = summary(prec)
 
+    # the same step with the C_free points copied to pinned host memory (the
+    # paper's pipeline hands them to the host): PCIe-inclusive, not `value`
+    out["with_cfree_to_host"] = cfree_leg(ip, wl, main_prec, budget, nf)
+    if extras:
+        out["legs"] = extra_legs(ip, extras, wl)
     if reqs:
-        # isolated capacity: requests one at a time, back to back
-        iso = serving(ip, reqs[:16], 1, 0.0, ip.IP_FP32_CERTIFY)
+        # isolated capacity: every request alone, back to back
+        iso = serving(ip, reqs, 1, 0.0, ip.IP_FP32_CERTIFY)
         t_service = float(np.mean([r["t_done"] - r["t_start"] for r in iso]))
         rate = 0.7 / t_service
         print(f"[bench] serving: isolated service {t_service * 1e3:.1f} ms, arrival rate {rate:.1f}/s",
               file=sys.stderr, flush=True)
         srv = {"requests": len(reqs), "slots": args.slots, "arrival_rate_per_s": round(rate, 2),
-               "isolated_service_ms": round(t_service * 1e3, 3)}
+               "isolated_service_ms": round(t_service * 1e3, 3), "request_sizes": request_sizes(iso)}
         for key, slots, prec in (("fp32_certify", args.slots, ip.IP_FP32_CERTIFY),
                                  ("fp64", args.slots, ip.IP_FP64),
                                  ("queue_only_fp32", 1, ip.IP_FP32_CERTIFY)):

@@ -249,6 +249,11 @@ int ip_check_cells(ip_ctx *ctx, ip_cells *c, const ip_scene *scene, int64_t *n_f
 /* Host copies of the verdicts (n bytes) and free points (n_free x d). */
 int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict,
                             double *free_pts);
+/* The free points to the host as they lie on the device, one column per
+ * coordinate (free_soa[j * n_free + i]): d copies, no host-side transpose,
+ * so that pinned host memory (hipHostMalloc) receives them at the link's
+ * rate (Sec. V-B: only the C_free points go back to the host). */
+int ip_cells_download_free(ip_ctx *ctx, const ip_cells *c, double *free_soa);
 
 /* f at lattice vertices (device v_dev: n x d int32 -> device f_dev: n).
  * IP_FP64: canonical FP64.  IP_FP32_CERTIFY: FP32 with the bound, FP64 for
@@ -256,6 +261,22 @@ int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict,
  * bound used (0 for FP64 results). */
 int ip_feval(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n,
              int32_t precision, double *f_dev, double *bound_dev);
+
+/* Seeds (Sec. V-A: the seeds are points on the manifold found by a
+ * nonlinear program that minimises |f| from a given configuration): from
+ * each start q0 (device, n x d row-major), `iters` (0..1000) minimum-norm
+ * Newton steps on f in FP64,
+ *   g = grad f(q) and f(q) in the canonical order of ip_fparams, with
+ *     POLY: w_i = (alpha_i t_i^(p-1)) (p gamma), g_j = fma chain of w_i s_ij;
+ *     RBF:  w_i = (alpha_i e_i) (-2 gamma),    g_j = fma chain of w_i (q_j - s_ij);
+ *   n2 = fma chain of g_j^2; a zero n2 ends the steps; c = f / n2;
+ *   q_j = fma(-c, g_j, q_j), then clamped into the domain box;
+ * then q_dev (n x d) receives the final points and f_dev (n) f there.  The
+ * caller keeps the points with |f| small enough as seeds. */
+int ip_seed_search(ip_ctx *ctx, const ip_problem *p, const double *q0_dev, int64_t n, int32_t iters,
+                   double *q_dev, double *f_dev);
+/* Replace the problem's seeds (host, n_seeds x d, copied). */
+int ip_problem_set_seeds(ip_ctx *ctx, ip_problem *p, const double *seeds, int64_t n_seeds);
 
 /* The first certified tier of batch subdivision (Sec. V-B, Eq. 1-2 with the
  * FP32 certification), on given coarse simplices, for inspection: the fused
@@ -293,11 +314,17 @@ int ip_feval_noalloc(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int
  * each retraining of the manifold produces a new trace + check request).
  * A server owns max_slots slots, each a context with its own HIP stream and
  * workspace, and one host thread per slot.  Requests queue in arrival order
- * and are admitted to a free slot when the sum of the projected device bytes
- * of the running requests plus the new one fits pool_bytes (a request larger
- * than the pool runs alone).  Admitted requests run concurrently on their
- * streams, so their kernels overlap on the device; a request's result does
- * not depend on what else runs.
+ * and join as slots free up.  A request that takes a slot first projects its
+ * own device bytes: it traces its manifold on a coarsened lattice (its own
+ * coarse lattice in batch mode, the fine one coarsened by 4 otherwise); with
+ * nc crossing edges there and coarsening kc, about N = 1.25 nc kc^(d-1) fine
+ * cells, projected at N (8 + 16 d + 57) bytes + 64 MiB.  It starts its
+ * trace once that projection plus those of the requests already tracing fits
+ * pool_bytes (a request larger than the pool runs when nothing else
+ * traces); a request's caller can give mem_bytes instead.  Admitted requests
+ * run concurrently on their streams, so their kernels overlap on the device;
+ * a request's result does not depend on what else runs.  Each slot's idle
+ * device cache is limited to pool_bytes / max_slots.
  * ------------------------------------------------------------------------ */
 typedef struct ip_server ip_server;
 
@@ -312,7 +339,8 @@ typedef struct {
   int32_t precision;         /* IP_FP64 or IP_FP32_CERTIFY */
   const ip_scene *scene;     /* host, copied; NULL = trace only */
   uint64_t batch_budget;     /* as for ip_trace */
-  uint64_t mem_bytes;        /* projected device bytes (admission); 0 = pool / slots */
+  uint64_t mem_bytes;        /* device bytes to admit the request by; 0 = the
+                                library's projection (above) */
   uint32_t flags;            /* IP_KEEP_CELLS, and IP_REFINE(n) for ip_trace */
 } ip_request;
 
@@ -328,6 +356,9 @@ typedef struct {
   double *free_pts;          /* host, n_free x d (NULL without a scene) */
   ip_cells *cells;           /* with IP_KEEP_CELLS; download with ctx = NULL */
   char error[160];
+  uint64_t admitted_bytes;   /* the projection (or mem_bytes) it was admitted by */
+  int64_t n_probe_edges;     /* crossing edges of the projection trace (0 with mem_bytes) */
+  double t_admit;            /* when its trace was admitted (server clock) */
 } ip_result;
 
 int ip_server_create(ip_server **out, int device, uint64_t pool_bytes, int32_t max_slots);

@@ -71,6 +71,9 @@ def lib():
         L.orc_f.restype = C.c_double
         L.orc_f.argtypes = [C.POINTER(_F), _dp]
         L.orc_f_batch.argtypes = [C.POINTER(_F), C.POINTER(_Space), C.c_int64, _ip, _dp]
+        L.orc_f_grad.restype = C.c_double
+        L.orc_f_grad.argtypes = [C.POINTER(_F), _dp, _dp]
+        L.orc_seed_search.argtypes = [C.POINTER(_F), C.POINTER(_Space), C.c_int64, _dp, C.c_int32, _dp, _dp]
         L.orc_coords.argtypes = [C.POINTER(_Space), _ip, _dp]
         L.orc_locate.argtypes = [C.POINTER(_Space), C.c_int32, _dp, _ip, _ip]
         L.orc_cofaces2.restype = C.c_int64
@@ -175,6 +178,25 @@ def f_at(wl_f, x):
     c = _Ctx(wl_f)
     x, px = _d(x)
     return lib().orc_f(C.byref(c.f), px)
+
+
+def f_grad(wl_f, x):
+    c = _Ctx(wl_f)
+    x, px = _d(x)
+    g = np.zeros(wl_f.d)
+    v = lib().orc_f_grad(C.byref(c.f), px, g.ctypes.data_as(_dp))
+    return v, g
+
+
+def seed_search(wl, q0, iters):
+    """Minimum-norm Newton steps towards f = 0 from the rows of q0."""
+    c = _Ctx(wl.f, wl.lat, wl.dom)
+    q0, pq0 = _d(np.atleast_2d(q0))
+    q = np.zeros_like(q0)
+    fq = np.zeros(q0.shape[0])
+    _check(lib().orc_seed_search(C.byref(c.f), C.byref(c.sp), q0.shape[0], pq0, iters,
+                                 q.ctypes.data_as(_dp), fq.ctypes.data_as(_dp)), "seed_search")
+    return q, fq
 
 
 def locate(lat, y, coarse_k=1):

@@ -11,6 +11,10 @@
  * Parity status per function (the pins live in the test suite):
  *   orc_coords, orc_f            pinned (closed forms, sphere level set;
  *                                RBF: numpy value, one-SV sphere level set)
+ *   orc_f_grad                   pinned (central differences of orc_f)
+ *   orc_seed_search              pinned (sphere: the radial projection;
+ *                                affine f: the orthogonal projection in one
+ *                                step; clamping into the box)
  *   orc_exp                      pinned (library exp within 2 ulp, exact at 0,
  *                                0 below the normal range)
  *   orc_locate                   pinned (barycentric containment)
@@ -226,6 +230,68 @@ double orc_f(const orc_fparams *f, const double *x) {
     acc = fma(f->alpha[i], tp, acc);
   }
   return acc + f->bias;
+}
+
+double orc_f_grad(const orc_fparams *f, const double *x, double *g) {
+  const int d = f->d;
+  double acc = 0.0;
+  for (int j = 0; j < d; ++j) g[j] = 0.0;
+  if (f->kernel == ORC_RBF) {
+    const double m2g = -2.0 * f->gamma;
+    for (int64_t i = 0; i < f->S; ++i) {
+      const double *s = f->sv + i * d;
+      double df[ORC_MAXD], d2 = 0.0;
+      for (int j = 0; j < d; ++j) {
+        df[j] = x[j] - s[j];
+        d2 = fma(df[j], df[j], d2);
+      }
+      double e = orc_exp(-(f->gamma * d2));
+      acc = fma(f->alpha[i], e, acc);
+      double w = (f->alpha[i] * e) * m2g;
+      for (int j = 0; j < d; ++j) g[j] = fma(w, df[j], g[j]);
+    }
+    return acc + f->bias;
+  }
+  const double pg = (double)f->p * f->gamma;
+  for (int64_t i = 0; i < f->S; ++i) {
+    const double *s = f->sv + i * d;
+    double dot = 0.0;
+    for (int j = 0; j < d; ++j) dot = fma(s[j], x[j], dot);
+    double t = fma(f->gamma, dot, f->coef0);
+    double tp1 = 1.0;
+    if (f->p > 1) {
+      tp1 = t;
+      for (int r = 2; r < f->p; ++r) tp1 = tp1 * t;
+    }
+    acc = fma(f->alpha[i], tp1 * t, acc);
+    double w = (f->alpha[i] * tp1) * pg;
+    for (int j = 0; j < d; ++j) g[j] = fma(w, s[j], g[j]);
+  }
+  return acc + f->bias;
+}
+
+int orc_seed_search(const orc_fparams *f, const orc_space *sp, int64_t n,
+                    const double *q0, int32_t iters, double *q, double *fq) {
+  const int d = sp->d;
+  if (iters < 0) return -2;
+  for (int64_t i = 0; i < n; ++i) {
+    double x[ORC_MAXD], g[ORC_MAXD];
+    for (int j = 0; j < d; ++j) x[j] = q0[i * d + j];
+    for (int it = 0; it < iters; ++it) {
+      double fv = orc_f_grad(f, x, g);
+      double n2 = 0.0;
+      for (int j = 0; j < d; ++j) n2 = fma(g[j], g[j], n2);
+      if (!(n2 > 0.0)) break;
+      double c = fv / n2;
+      for (int j = 0; j < d; ++j) {
+        double v = fma(-c, g[j], x[j]);
+        x[j] = v < sp->lo[j] ? sp->lo[j] : (v > sp->hi[j] ? sp->hi[j] : v);
+      }
+    }
+    for (int j = 0; j < d; ++j) q[i * d + j] = x[j];
+    fq[i] = orc_f(f, x);
+  }
+  return 0;
 }
 
 void orc_f_batch(const orc_fparams *f, const orc_space *sp, int64_t n,

@@ -99,6 +99,23 @@ int64_t orc_ncofaces(int32_t d, const int32_t *v, uint32_t mask, int32_t *out);
 int32_t orc_canonical(int32_t d, const int32_t *v, int32_t nparts,
                       const uint32_t *parts, int32_t *vc, uint32_t *pc);
 
+/* f and its gradient at x in the canonical order: per support vector in
+ * index order, POLY: dot and t as in orc_f, t^(p-1) by repeated
+ * multiplication (1 for p = 1), t^p = t^(p-1) t, acc = fma(alpha, t^p, acc),
+ * w = (alpha t^(p-1)) (p gamma), g_j = fma(w, s_j, g_j); RBF: d_j = x_j - s_j,
+ * d2 and e as in orc_f, acc = fma(alpha, e, acc), w = (alpha e) (-2 gamma),
+ * g_j = fma(w, d_j, g_j).  Returns f = acc + bias. */
+double orc_f_grad(const orc_fparams *f, const double *x, double *g);
+
+/* Seeds by minimising |f| from given configurations (Sec. V-A: the seeds are
+ * points on the manifold found by a nonlinear program that minimises the
+ * absolute value of f from a configuration): `iters` minimum-norm Newton
+ * steps q <- q - (f / |grad f|^2) grad f (n2 = fma chain of g_j^2, c = f / n2,
+ * q_j = fma(-c, g_j, q_j)), each followed by clamping q into the domain box;
+ * a zero gradient ends the steps.  Writes the final q (n x d) and f(q). */
+int orc_seed_search(const orc_fparams *f, const orc_space *sp, int64_t n,
+                    const double *q0, int32_t iters, double *q, double *fq);
+
 /* Direct trace (Sec. V-A, Figs. 3-4): the closure of the seeds' intersecting
  * edges under "shares a 2-simplex".  Output sorted lexicographically by
  * (v, mask).  coarse_k >= 1 traces the lattice refined by k: vertex u of the

@@ -432,6 +432,8 @@ int ip_problem_create(ip_ctx *ctx, const ip_fparams *f, const ip_space *sp, cons
   p->k = coarse_k;
   int rc = build_lattice(ctx, sp, 1, &p->fine);
   if (rc == IP_OK) rc = build_lattice(ctx, sp, coarse_k, &p->coarse);
+  p->probe_k = coarse_k >= 2 ? coarse_k : 4;
+  if (rc == IP_OK) rc = build_lattice(ctx, sp, p->probe_k, &p->probe);
   if (rc != IP_OK) {
     delete p;
     return rc;
@@ -708,6 +710,18 @@ int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict, do
   return IP_OK;
 }
 
+int ip_cells_download_free(ip_ctx *ctx, const ip_cells *c, double *free_soa) {
+  if (!ctx && c) ctx = c->ctx;
+  if (!ctx) return IP_EINVAL;
+  if (!c || !c->verdict || (c->n_free > 0 && !free_soa))
+    return ip_fail(ctx, IP_EINVAL, "ip_cells_download_free: cells have not been checked");
+  for (int j = 0; j < c->d && c->n_free > 0; ++j)
+    IP_TRY_HIP(ctx, hipMemcpyAsync(free_soa + (size_t)j * c->n_free, c->free_pts + (size_t)j * c->n,
+                                   (size_t)c->n_free * 8, hipMemcpyDeviceToHost, ctx->stream));
+  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return IP_OK;
+}
+
 int ip_feval(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev, int64_t n, int32_t precision, double *f_dev,
              double *bound_dev) {
   if (!ctx) return IP_EINVAL;
@@ -726,6 +740,37 @@ int ip_region_eval(ip_ctx *ctx, const ip_problem *p, const int32_t *simplex_dev,
   if (!p->poly.ok) return ip_fail(ctx, IP_EINVAL, "ip_region_eval: no FP32 form for this degree");
   IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
   return ip_region_eval_impl(ctx, p, simplex_dev, n, y_dev, f_dev, bound_dev, n_points);
+}
+
+int ip_seed_search(ip_ctx *ctx, const ip_problem *p, const double *q0_dev, int64_t n, int32_t iters, double *q_dev,
+                   double *f_dev) {
+  if (!ctx) return IP_EINVAL;
+  if (!p || n < 0 || iters < 0 || iters > 1000 || (n > 0 && (!q0_dev || !q_dev || !f_dev)))
+    return ip_fail(ctx, IP_EINVAL, "ip_seed_search: bad arguments");
+  if (p->ctx != ctx) return ip_fail(ctx, IP_EINVAL, "problem belongs to another context");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  if (n == 0) return IP_OK;
+  return ip_seed_search_impl(ctx, p, q0_dev, n, iters, q_dev, f_dev);
+}
+
+int ip_problem_set_seeds(ip_ctx *ctx, ip_problem *p, const double *seeds, int64_t n_seeds) {
+  if (!ctx) return IP_EINVAL;
+  if (!p || n_seeds < 1 || !seeds) return ip_fail(ctx, IP_EINVAL, "ip_problem_set_seeds: need at least one seed");
+  if (p->ctx != ctx) return ip_fail(ctx, IP_EINVAL, "problem belongs to another context");
+  if (!finite_all(seeds, n_seeds * p->d)) return ip_fail(ctx, IP_EINVAL, "non-finite seed");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  double *nd = nullptr;
+  IP_TRY_HIP(ctx, hipMalloc((void **)&nd, (size_t)n_seeds * p->d * 8));
+  hipError_t e = hipMemcpyAsync(nd, seeds, (size_t)n_seeds * p->d * 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(nd);
+    return ip_hip(ctx, e, "ip_problem_set_seeds");
+  }
+  if (p->seeds_dev) (void)hipFree(p->seeds_dev);
+  p->seeds_dev = nd;
+  p->n_seeds = n_seeds;
+  return IP_OK;
 }
 
 int ip_cells_key_layout(const ip_cells *c, int32_t *bits, int32_t *vmin) {

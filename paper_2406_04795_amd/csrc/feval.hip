@@ -460,7 +460,102 @@ int dispatch32_p(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32
   return dispatch32<MODE>(ctx, p->poly, L, list, n, vt, vb, vraw, out, bout, fb, fb_ctr, c64);
 }
 
+// Canonical f and gradient at x (the order of ip.h's ip_seed_search): per
+// support vector in index order, read as a wave-uniform record.
+template <int D>
+__device__ __forceinline__ double f_grad(const FDev &F, const double *x, double *g) {
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) g[j] = 0.0;
+  if (F.kernel == IP_KERNEL_RBF) {
+    const double m2g = -2.0 * F.gamma;
+    for (int64_t i = 0; i < F.S; ++i) {
+      const double *rec = F.rec + i * 8;
+      double df[D], d2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        df[j] = x[j] - rec[j];
+        d2 = fma(df[j], df[j], d2);
+      }
+      const double e = exp_own(-(F.gamma * d2));
+      acc = fma(rec[D], e, acc);
+      const double w = (rec[D] * e) * m2g;
+#pragma unroll
+      for (int j = 0; j < D; ++j) g[j] = fma(w, df[j], g[j]);
+    }
+    return acc + F.bias;
+  }
+  const double pg = (double)F.p * F.gamma;
+  for (int64_t i = 0; i < F.S; ++i) {
+    const double *rec = F.rec + i * 8;
+    double dot = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) dot = fma(rec[j], x[j], dot);
+    const double t = fma(F.gamma, dot, F.coef0);
+    double tp1 = 1.0;
+    if (F.p > 1) {
+      tp1 = t;
+      for (int r = 2; r < F.p; ++r) tp1 = tp1 * t;
+    }
+    acc = fma(rec[D], tp1 * t, acc);
+    const double w = (rec[D] * tp1) * pg;
+#pragma unroll
+    for (int j = 0; j < D; ++j) g[j] = fma(w, rec[j], g[j]);
+  }
+  return acc + F.bias;
+}
+
+// Seed search (Sec. V-A: minimise |f| from given configurations), one lane
+// per start: `iters` minimum-norm Newton steps, each clamped into the box;
+// a zero gradient ends a lane's steps.  Then f at the final point.
+template <int D>
+__global__ __launch_bounds__(256) void seed_kernel(FDev F, LatDev L, const double *__restrict__ q0, uint64_t n,
+                                                   int iters, double *__restrict__ q, double *__restrict__ fq) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    double x[D], g[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) x[j] = q0[i * D + j];
+    for (int it = 0; it < iters; ++it) {
+      const double fv = f_grad<D>(F, x, g);
+      double n2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) n2 = fma(g[j], g[j], n2);
+      if (!(n2 > 0.0)) break;
+      const double c = fv / n2;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const double v = fma(-c, g[j], x[j]);
+        x[j] = v < L.lo[j] ? L.lo[j] : (v > L.hi[j] ? L.hi[j] : v);
+      }
+    }
+    const double fv = f_grad<D>(F, x, g);
+#pragma unroll
+    for (int j = 0; j < D; ++j) q[i * D + j] = x[j];
+    fq[i] = fv;
+  }
+}
+
 }  // namespace
+
+int ip_seed_search_impl(ip_ctx *ctx, const ip_problem *p, const double *q0, int64_t n, int32_t iters, double *q,
+                        double *fq) {
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
+#define IP_SD(DD)                                                                                            \
+  hipLaunchKernelGGL((seed_kernel<DD>), dim3(blocks), dim3(256), 0, ctx->stream, p->f, p->fine, q0, (uint64_t)n, \
+                     (int)iters, q, fq)
+  switch (p->d) {
+    case 2: IP_SD(2); break;
+    case 3: IP_SD(3); break;
+    case 4: IP_SD(4); break;
+    case 5: IP_SD(5); break;
+    case 6: IP_SD(6); break;
+    case 7: IP_SD(7); break;
+    default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
+  }
+#undef IP_SD
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
+}
 
 bool ip_has_fp32_form(const ip_problem *p) {
   return p->f.kernel == IP_KERNEL_RBF ? p->rbf.ok != 0 : p->poly.ok != 0;

@@ -629,6 +629,9 @@ struct ip_problem {
   int32_t k = 1;
   LatDev fine;      // fine lattice (mul = 1)
   LatDev coarse;    // coarse lattice (mul = k); equal to fine when k = 1
+  LatDev probe;     // lattice of the memory projection: the coarse one, or
+                    // the fine one coarsened by 4 for a direct trace
+  int32_t probe_k = 4;
   FDev f;
   double *rec_dev = nullptr;
   double *seeds_dev = nullptr;
@@ -684,6 +687,11 @@ int ip_feval_noalloc_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *v_dev
                           double *f_dev, double *bound_dev);
 int ip_region_eval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, int64_t n, int32_t *y, double *f,
                         double *bound, int32_t *np_out);
+// Projected device bytes of tracing and checking p (the serving loop's
+// admission): a trace on the probe lattice gives the coarse crossing count.
+int ip_project_impl(ip_ctx *ctx, const ip_problem *p, uint64_t *bytes, int64_t *n_coarse);
+int ip_seed_search_impl(ip_ctx *ctx, const ip_problem *p, const double *q0, int64_t n, int32_t iters, double *q,
+                        double *fq);
 // True when f has a certified FP32 form (polynomial of degree <= 4, or RBF).
 bool ip_has_fp32_form(const ip_problem *p);
 // Looks up this device's address of the ip_feval_noalloc scratch (once per

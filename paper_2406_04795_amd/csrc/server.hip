@@ -1,8 +1,11 @@
 // Serving loop (include/ip.h, ip_server_*): a queue of proof requests, slots
 // that each own a context (HIP stream + workspace) and a host thread, and
-// admission by projected device memory.  Requests on different slots run on
-// different streams, so their kernels overlap on the device; a request joins
-// as soon as a slot and memory are free, not when a whole batch finishes.
+// admission in two steps: a request takes the next free slot and projects
+// its device bytes there (a trace on a coarsened lattice), then starts its
+// trace once the projection fits the pool beside the traces already
+// running.  Requests on different slots run on different streams, so their
+// kernels overlap on the device; a request joins as soon as a slot and
+// memory are free, not when a whole batch of requests finishes.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -101,12 +104,31 @@ struct ip_server {
   std::deque<uint64_t> queue;
   std::map<uint64_t, std::unique_ptr<Job>> jobs;
   uint64_t next_id = 1;
-  uint64_t in_use = 0;
-  int running = 0;
+  uint64_t in_use = 0;   // admitted bytes of the requests tracing now
+  int tracing = 0;
+  std::condition_variable cv_mem;
   bool stop = false;
   std::chrono::steady_clock::time_point t0;
 
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+
+  // Waits until `bytes` fits the pool beside the traces running (or nothing
+  // traces), then books them.
+  void admit(uint64_t bytes, ip_result *r) {
+    std::unique_lock<std::mutex> lk(mu);
+    cv_mem.wait(lk, [&] { return stop || tracing == 0 || in_use + bytes <= pool; });
+    in_use += bytes;
+    ++tracing;
+    r->t_admit = now();
+  }
+  void release_bytes(uint64_t bytes) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      in_use -= bytes;
+      --tracing;
+    }
+    cv_mem.notify_all();
+  }
 
   void run_job(ip_ctx *ctx, Job &job) {
     ip_result *r = job.res;
@@ -115,6 +137,14 @@ struct ip_server {
     ip_problem *p = nullptr;
     ip_cells *c = nullptr;
     int rc = ip_problem_create(ctx, &q.f, &q.sp, q.seeds.data(), q.n_seeds, q.k, &p);
+    uint64_t bytes = q.bytes;
+    if (rc == IP_OK && bytes == 0) rc = ip_project_impl(ctx, p, &bytes, &r->n_probe_edges);
+    bool admitted = false;
+    if (rc == IP_OK) {
+      r->admitted_bytes = bytes;
+      admit(bytes, r);
+      admitted = true;
+    }
     if (rc == IP_OK) rc = ip_trace(ctx, p, q.budget, q.prec, q.flags & ~(uint32_t)IP_KEEP_CELLS, &c);
     if (rc == IP_OK && q.has_scene) rc = ip_check_cells(ctx, c, &q.sc, &r->n_free);
     if (rc == IP_OK) {
@@ -142,6 +172,8 @@ struct ip_server {
     r->status = rc;
     if (c) ip_cells_free(c);
     if (p) ip_problem_free(p);
+    r->t_done = now();
+    if (admitted) release_bytes(bytes);
   }
 
   void worker(int slot) {
@@ -152,27 +184,17 @@ struct ip_server {
       Job *job = nullptr;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] {
-          if (stop) return true;
-          if (queue.empty()) return false;
-          const uint64_t b = jobs[queue.front()]->req.bytes;
-          return in_use + b <= pool || running == 0;
-        });
+        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
         if (stop) return;
         id = queue.front();
         queue.pop_front();
         job = jobs[id].get();
-        in_use += job->req.bytes;
-        ++running;
         job->res->t_start = now();
       }
       run_job(ctx, *job);
       {
         std::lock_guard<std::mutex> lk(mu);
-        job->res->t_done = now();
         job->done = true;
-        in_use -= job->req.bytes;
-        --running;
       }
       cv_done.notify_all();
       cv_work.notify_all();
@@ -220,7 +242,7 @@ int ip_server_submit(ip_server *s, const ip_request *req, uint64_t *id) {
   auto job = std::unique_ptr<Job>(new (std::nothrow) Job());
   if (!job) return IP_ENOMEM;
   own(req, job->req);
-  job->req.bytes = req->mem_bytes ? req->mem_bytes : s->pool / std::max<size_t>(1, s->ctxs.size());
+  job->req.bytes = req->mem_bytes;  // 0: projected by the slot that takes it
   job->res = new (std::nothrow) ip_result();
   if (!job->res) return IP_ENOMEM;
   memset(job->res, 0, sizeof(ip_result));
@@ -275,6 +297,7 @@ void ip_server_destroy(ip_server *s) {
     s->queue.clear();
   }
   s->cv_work.notify_all();
+  s->cv_mem.notify_all();
   for (auto &t : s->workers)
     if (t.joinable()) t.join();
   for (auto &kv : s->jobs) {

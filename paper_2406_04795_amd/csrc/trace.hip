@@ -2592,6 +2592,52 @@ int refine_T(ip_ctx *ctx, const ip_problem *p, int32_t prec, int iters, ip_cells
 
 }  // namespace
 
+namespace {
+
+// Memory projection: the crossing edges on the probe lattice (coarsened by
+// kc) number about N / kc^(d-1) for N fine cells (the crossing count scales
+// with the zero set's area over the scale^(d-1)); each fine cell then holds
+// its key (8 B), two point copies (16 d B: points and free points), its
+// verdict (1 B), a traced-edge record (16 B) and its share of the vertex
+// table (40 B), with a 25 % margin and 64 MiB of fixed workspace.
+template <int D>
+int project_T(ip_ctx *ctx, const ip_problem *p, uint64_t *bytes, int64_t *n_coarse) {
+  Run s;
+  s.ctx = ctx;
+  s.p = p;
+  s.tb = &ctx->vtc;
+  s.L = p->probe;
+  s.cert = false;
+  IP_TRY(vt_init(s, 1ull << 16));
+  ip_stats st = {};
+  uint64_t nc = 0;
+  const int rc = trace_direct<D>(s, st, &nc);
+  if (s.out) {
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx, s.out);
+  }
+  IP_TRY(rc);
+  double cells = (double)nc * 1.25;
+  for (int q = 0; q < D - 1; ++q) cells *= p->probe_k;
+  *bytes = (uint64_t)(cells * (8.0 + 16.0 * D + 1.0 + 16.0 + 40.0)) + (64ull << 20);
+  *n_coarse = (int64_t)nc;
+  return IP_OK;
+}
+
+}  // namespace
+
+int ip_project_impl(ip_ctx *ctx, const ip_problem *p, uint64_t *bytes, int64_t *n_coarse) {
+  switch (p->d) {
+    case 2: return project_T<2>(ctx, p, bytes, n_coarse);
+    case 3: return project_T<3>(ctx, p, bytes, n_coarse);
+    case 4: return project_T<4>(ctx, p, bytes, n_coarse);
+    case 5: return project_T<5>(ctx, p, bytes, n_coarse);
+    case 6: return project_T<6>(ctx, p, bytes, n_coarse);
+    case 7: return project_T<7>(ctx, p, bytes, n_coarse);
+    default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
+  }
+}
+
 int ip_region_eval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, int64_t n, int32_t *y, double *f,
                         double *bound, int32_t *np_out) {
   switch (p->d) {

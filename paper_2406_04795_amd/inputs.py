@@ -489,11 +489,82 @@ def subbox_case(d, S, lam, target_cells, seed=0, p=3, eps=3e-3, k=1, scene=None)
     return Workload(f"subbox_d{d}_S{S}_lam{lam:.3f}", fm, lat, dom, seeds, k, scene)
 
 
+def _poly_grad_hess(fm: Manifold, x):
+    t = fm.gamma * (fm.sv @ x) + fm.coef0
+    g = (fm.alpha * fm.p * fm.gamma * t ** (fm.p - 1)) @ fm.sv
+    w = fm.alpha * fm.p * (fm.p - 1) * fm.gamma ** 2 * t ** (fm.p - 2)
+    H = (fm.sv.T * w) @ fm.sv
+    return g, H
+
+
+def planted_blob(fm: Manifold, dom: Domain, rng, area, n_probe=20000, iters=40, n_dirs=20000):
+    """Bias and centre that make {f < 0} a small blob of about the given
+    boundary area around an interior local minimum x* of the kernel sum f0:
+    Newton steps from the lowest probe (kept inside 0.9 of the box).  Near x*
+    the blob {f0 < f0(x*) + delta} is the ellipsoid with semi-axes
+    a_i = sqrt(2 delta / lambda_i) (lambda_i the Hessian's eigenvalues); its
+    area is prod(a) times the mean over unit vectors u of sqrt(sum u_i^2 /
+    a_i^2) times the unit sphere's area, which fixes delta (for input sizing
+    only)."""
+    d = fm.d
+    X = rng.uniform(dom.lo * 0.9, dom.hi * 0.9, size=(n_probe, d))
+    x = X[np.argmin(_f0(fm, X))].copy()
+    lo, hi = dom.lo * 0.9, dom.hi * 0.9
+    for _ in range(iters):
+        g, H = _poly_grad_hess(fm, x)
+        ev, V = np.linalg.eigh(H)
+        step = -(V @ ((V.T @ g) / np.maximum(ev, 1e-9 * max(1.0, abs(ev).max()))))
+        x = np.clip(x + step, lo, hi)
+    _, H = _poly_grad_hess(fm, x)
+    lam_i = np.maximum(np.linalg.eigvalsh(H), 1e-12)
+    a1 = lam_i ** -0.5                       # semi-axes at 2 delta = 1
+    u = rng.standard_normal((n_dirs, d))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    sphere_area = 2 * math.pi ** (d / 2) / math.gamma(d / 2)
+    area1 = float(np.prod(a1) * np.mean(np.sqrt((u ** 2 / a1 ** 2).sum(1))) * sphere_area)
+    two_delta = (area / area1) ** (2.0 / (d - 1))
+    return -(float(_f0(fm, x[None])[0]) + 0.5 * two_delta), x
+
+
+def fullbox_case(d, S, lam, target_cells, seed=0, p=3, k=1, scene=None, n_seeds=4) -> Workload:
+    """Degree-p kernel over the whole box [-pi, pi]^d, N(0,1) coefficients,
+    with {f < 0} a planted blob whose boundary crosses about target_cells
+    edges at scale lam: area A = target lam^(d-1) / C_d (planted_blob).
+    Seeds: bisection from the blob's centre outwards along random
+    directions."""
+    rng = np.random.default_rng(seed)
+    dom = box(d)
+    fm = random_manifold(d, S, p, rng, dom, alpha="normal")
+    A = target_cells * lam ** (d - 1) / _edge_density(d)
+    fm.bias, xc = planted_blob(fm, dom, rng, A)
+    # a length on the blob's scale for the seed rays
+    r = (A / (2 * math.pi ** (d / 2) / math.gamma(d / 2))) ** (1.0 / (d - 1))
+    seeds = []
+    for _ in range(n_seeds):
+        u = rng.standard_normal(d)
+        u /= np.linalg.norm(u)
+        a, step = xc.copy(), 2 * r
+        b = np.clip(xc + step * u, dom.lo, dom.hi)
+        while feval_np(fm, b[None])[0] < 0 and step < 20.0:
+            step *= 2
+            b = np.clip(xc + step * u, dom.lo, dom.hi)
+        for _ in range(60):
+            m = 0.5 * (a + b)
+            if feval_np(fm, m[None])[0] < 0:
+                a = m
+            else:
+                b = m
+        seeds.append(0.5 * (a + b))
+    lat = make_lattice(d, lam, rng)
+    return Workload(f"fullbox_d{d}_S{S}_lam{lam:.3f}", fm, lat, dom, np.ascontiguousarray(seeds), k, scene)
+
+
 def serving_request(i, seed=0, cells=(1e5, 2e6)):
     """Proof request i of the serving workload: d in {4,5,6}, S log-uniform
-    in [100, 2000], scale uniform in [0.06, 0.12], degree 3, target size
-    log-uniform in `cells`, its own scene and seed 1000 + i; coarse factor
-    k = 2 for d = 6 below scale 0.09, else direct."""
+    in [100, 2000], scale uniform in [0.06, 0.12], degree 3, over the whole
+    box, the bias sized for a target cell count log-uniform in `cells`, its
+    own scene and seed 1000 + i; coarse factor k = 2 for d = 6 below scale
+    0.09, else direct."""
     rng = np.random.default_rng((seed, i))
     d = int(rng.integers(4, 7))
     S = int(round(math.exp(rng.uniform(math.log(100), math.log(2000)))))
@@ -501,8 +572,9 @@ def serving_request(i, seed=0, cells=(1e5, 2e6)):
     target = float(math.exp(rng.uniform(math.log(cells[0]), math.log(cells[1]))))
     k = 2 if (d == 6 and lam < 0.09) else 1
     srng = np.random.default_rng(1000 + i)
-    sc = spatial_arm_scene(srng, d, spheres_per_link=2, sphere_r=0.05, n_osph=6, n_obox=4)
-    return subbox_case(d, S, lam, target, seed=1000 + i, k=k, scene=sc)
+    sc = spatial_arm_scene(srng, d, spheres_per_link=2, sphere_r=0.05, n_osph=6, n_obox=4,
+                           obst_ball=((0.0, 0.0, 0.3), 0.9))
+    return fullbox_case(d, S, lam, target, seed=1000 + i, k=k, scene=sc)
 
 
 def serving_requests(n=256, seed=0, cells=(1e5, 2e6)):

@@ -85,7 +85,8 @@ class ip_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("d", C.c_int32), ("stats", ip_stats),
                 ("n_cells", C.c_int64), ("n_free", C.c_int64), ("digest", C.c_uint64 * 2),
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
-                ("free_pts", _dp), ("cells", C.c_void_p), ("error", C.c_char * 160)]
+                ("free_pts", _dp), ("cells", C.c_void_p), ("error", C.c_char * 160),
+                ("admitted_bytes", C.c_uint64), ("n_probe_edges", C.c_int64), ("t_admit", C.c_double)]
 
 
 IP_KEEP_CELLS = 1
@@ -115,10 +116,13 @@ _sig = {
     "ip_check": (C.c_int, [_vp, _P(ip_scene), _vp, C.c_int64, C.c_int64, _vp]),
     "ip_check_cells": (C.c_int, [_vp, _vp, _P(ip_scene), _P(C.c_int64)]),
     "ip_cells_download_check": (C.c_int, [_vp, _vp, C.POINTER(C.c_uint8), _dp]),
+    "ip_cells_download_free": (C.c_int, [_vp, _vp, _vp]),
     "ip_feval": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, _vp, _vp]),
     "ip_feval_noalloc": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, _vp, _vp]),
     "ip_region_eval": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp, _P(C.c_int32)]),
     "ip_cells_key_layout": (C.c_int, [_vp, _P(C.c_int32), _P(C.c_int32)]),
+    "ip_seed_search": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, _vp, _vp]),
+    "ip_problem_set_seeds": (C.c_int, [_vp, _vp, _dp, C.c_int64]),
     "ip_server_create": (C.c_int, [_P(_vp), C.c_int, C.c_uint64, C.c_int32]),
     "ip_server_submit": (C.c_int, [_vp, _P(ip_request), _P(C.c_uint64)]),
     "ip_server_poll": (C.c_int, [_vp, C.c_uint64, _P(_P(ip_result))]),
@@ -292,6 +296,11 @@ def ip_cells_download_check(ctx, cells, d, n_free):
     return ver, fp
 
 
+def ip_cells_download_free(ctx, cells, host_ptr: int):
+    """Free points as d host columns of n_free doubles at host_ptr."""
+    _chk(ctx, _lib.ip_cells_download_free(ctx, cells, host_ptr))
+
+
 def ip_feval(ctx, prob, v_dev_ptr: int, n: int, precision, f_dev_ptr: int, bound_dev_ptr: int = 0):
     _chk(ctx, _lib.ip_feval(ctx, prob, v_dev_ptr, n, precision, f_dev_ptr, bound_dev_ptr or None))
 
@@ -303,6 +312,15 @@ def ip_region_eval(ctx, prob, simplex_dev_ptr: int, n: int, y_dev_ptr: int = 0, 
     _chk(ctx, _lib.ip_region_eval(ctx, prob, simplex_dev_ptr or None, n, y_dev_ptr or None, f_dev_ptr or None,
                                   bound_dev_ptr or None, C.byref(np_out)))
     return np_out.value
+
+
+def ip_seed_search(ctx, prob, q0_dev_ptr: int, n: int, iters: int, q_dev_ptr: int, f_dev_ptr: int):
+    _chk(ctx, _lib.ip_seed_search(ctx, prob, q0_dev_ptr, n, iters, q_dev_ptr, f_dev_ptr))
+
+
+def ip_problem_set_seeds(ctx, prob, seeds):
+    seeds = np.ascontiguousarray(seeds, dtype=np.float64)
+    _chk(ctx, _lib.ip_problem_set_seeds(ctx, prob, seeds.ctypes.data_as(_dp), seeds.shape[0]))
 
 
 def ip_cells_key_layout(cells, d):
@@ -420,7 +438,8 @@ def _take_result(rp):
     r = rp.contents
     out = {"status": r.status, "d": r.d, "stats": r.stats.as_dict(), "n_cells": r.n_cells,
            "n_free": r.n_free, "digest": (r.digest[0], r.digest[1]), "t_submit": r.t_submit,
-           "t_start": r.t_start, "t_done": r.t_done, "error": r.error.decode(errors="replace")}
+           "t_start": r.t_start, "t_done": r.t_done, "error": r.error.decode(errors="replace"),
+           "admitted_bytes": r.admitted_bytes, "n_probe_edges": r.n_probe_edges, "t_admit": r.t_admit}
     if r.free_pts and r.n_free > 0:
         out["free_pts"] = np.ctypeslib.as_array(r.free_pts, shape=(r.n_free * r.d,)).reshape(
             r.n_free, r.d).copy()

@@ -67,13 +67,45 @@ def test_results_same_alone_and_in_mix(ip):
     assert starts[3] < dones[0]
 
 
-def test_admission_by_memory(ip):
-    reqs = _mix()[:4]
-    # every request projects the whole pool: they must run one at a time
-    res = _run(ip, reqs, 4, pool=1 << 30, mem=1 << 30)
-    spans = sorted((r["t_start"], r["t_done"]) for r in res)
+def _no_overlap(res):
+    spans = sorted((r["t_admit"], r["t_done"]) for r in res)
     for (s0, d0), (s1, d1) in zip(spans, spans[1:]):
         assert s1 >= d0
+
+
+def test_admission_by_memory(ip):
+    reqs = _mix()[:4]
+    # every request is given the whole pool: their traces run one at a time
+    res = _run(ip, reqs, 4, pool=1 << 30, mem=1 << 30)
+    assert all(r["admitted_bytes"] == 1 << 30 and r["n_probe_edges"] == 0 for r in res)
+    _no_overlap(res)
+
+
+def test_admission_by_projection(ip):
+    """The library projects each request's bytes from a coarse trace and
+    admits by that: with a pool below any two projections the traces run one
+    at a time, with a pool above all of them they overlap; the projections
+    are the same in both runs."""
+    reqs = _mix()
+    big = _run(ip, reqs, 4, pool=1 << 40)
+    proj = [r["admitted_bytes"] for r in big]
+    assert all(r["status"] == 0 for r in big)
+    assert sum(r["n_probe_edges"] > 0 for r in big) >= 3
+    # the projection is the documented one: 1.25 nc kc^(d-1) cells at
+    # 8 + 16 d + 57 bytes each, plus 64 MiB
+    for (wl, _, _), r in zip(reqs, big):
+        d = wl.f.d
+        kc = wl.k if wl.k >= 2 else 4
+        want = int(1.25 * r["n_probe_edges"] * kc ** (d - 1) * (8 + 16 * d + 57)) + (64 << 20)
+        assert abs(r["admitted_bytes"] - want) <= 1 + want * 1e-12
+    starts = sorted(r["t_admit"] for r in big)
+    dones = sorted(r["t_done"] for r in big)
+    assert starts[1] < dones[0]
+    small = _run(ip, reqs, 4, pool=2 * min(proj) - 1)
+    assert [r["admitted_bytes"] for r in small] == proj
+    _no_overlap(small)
+    for a, b in zip(big, small):
+        assert a["digest"] == b["digest"] and a["n_cells"] == b["n_cells"]
 
 
 def test_kept_cells_match_oracle(ip):
