@@ -250,25 +250,28 @@ def serving(ip, reqs, slots, rate, precision, seed=1):
         res = [ip.ip_server_wait(srv, i) for i in ids]
     finally:
         ip.ip_server_destroy(srv)
-    bad = [r["error"] for r in res if r["status"] != 0]
+    bad = [(i, r["error"]) for i, r in enumerate(res) if r["status"] != 0]
     if bad:
-        raise RuntimeError(f"serving requests failed: {bad[:3]}")
+        print(f"[bench] {len(bad)} serving requests failed: {bad[:3]}", file=sys.stderr, flush=True)
     return res
 
 
 def latency_summary(res):
+    """Latency over every request; cells (and so simplices/s) over the ones
+    that finished; failed requests are counted."""
     lat = np.array([r["t_done"] - r["t_submit"] for r in res]) * 1e3
     t_first = min(r["t_submit"] for r in res)
     t_last = max(r["t_done"] for r in res)
     cells = sum(r["n_cells"] for r in res)
     return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3), "simplices_per_s": cells / (t_last - t_first),
-            "requests": len(res)}
+            "requests": len(res), "failed": sum(r["status"] != 0 for r in res)}
 
 
 def request_sizes(res):
     """Per-request cells and admitted (projected) bytes, as quantiles."""
     q = [0, 10, 50, 90, 100]
+    res = [r for r in res if r["status"] == 0]
     n = np.array([r["n_cells"] for r in res], dtype=float)
     b = np.array([r["admitted_bytes"] for r in res], dtype=float)
     return {"cells_quantiles": dict(zip(map(str, q), np.percentile(n, q).round().astype(int).tolist())),
@@ -569,7 +572,7 @@ def main():
     if reqs:
         # isolated capacity: every request alone, back to back
         iso = serving(ip, reqs, 1, 0.0, ip.IP_FP32_CERTIFY)
-        t_service = float(np.mean([r["t_done"] - r["t_start"] for r in iso]))
+        t_service = float(np.mean([r["t_done"] - r["t_start"] for r in iso if r["status"] == 0]))
         rate = 0.7 / t_service
         print(f"[bench] serving: isolated service {t_service * 1e3:.1f} ms, arrival rate {rate:.1f}/s",
               file=sys.stderr, flush=True)

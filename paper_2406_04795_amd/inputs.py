@@ -497,44 +497,90 @@ def _poly_grad_hess(fm: Manifold, x):
     return g, H
 
 
-def planted_blob(fm: Manifold, dom: Domain, rng, area, n_probe=20000, iters=40, n_dirs=20000):
+def planted_minimum(fm: Manifold, dom: Domain, rng, tries=50):
+    """Rewrites the coefficients of a polynomial-kernel f0 so that it has a
+    strict local minimum at a random point x0 of the inner half of the box (a
+    random cubic kernel sum usually has none inside the box).  Each
+    coefficient keeps its magnitude and takes the sign of t^(p-2), t the
+    kernel argument at x0, so every term's Hessian is positive semidefinite
+    there; then the smallest correction weighted by alpha_i^2 makes
+    grad f0(x0) = 0 (a d x d solve).  Draws x0 again until the Hessian is
+    clearly positive definite.  Returns x0 and the Hessian there (input
+    generation only)."""
+    p, g = fm.p, fm.gamma
+    mag = np.abs(fm.alpha).copy()
+    for _ in range(tries):
+        x0 = rng.uniform(dom.lo * 0.5, dom.hi * 0.5)
+        t = g * (fm.sv @ x0) + fm.coef0
+        a = mag * np.sign(t) ** (p - 2)
+        B = (fm.sv * (p * g * t ** (p - 1))[:, None]).T     # grad f0(x0) = B a
+        W = a * a
+        try:
+            lam = np.linalg.solve((B * W) @ B.T, B @ a)
+        except np.linalg.LinAlgError:
+            continue
+        a = a - W * (B.T @ lam)
+        fm.alpha = np.ascontiguousarray(a)
+        gr, H = _poly_grad_hess(fm, x0)
+        ev = np.linalg.eigvalsh(H)
+        if ev[0] > 1e-3 * ev[-1] and np.linalg.norm(gr) <= 1e-9 * np.abs(H).max():
+            return x0, H
+    raise RuntimeError("no interior minimum could be planted")
+
+
+def planted_blob(fm: Manifold, dom: Domain, rng, area, n_dirs=20000, n_rays=2000, tries=4):
     """Bias and centre that make {f < 0} a small blob of about the given
-    boundary area around an interior local minimum x* of the kernel sum f0:
-    Newton steps from the lowest probe (kept inside 0.9 of the box).  Near x*
-    the blob {f0 < f0(x*) + delta} is the ellipsoid with semi-axes
+    boundary area around a planted minimum x0 of the kernel sum f0.  Near x0
+    the blob {f0 < f0(x0) + delta} is the ellipsoid with semi-axes
     a_i = sqrt(2 delta / lambda_i) (lambda_i the Hessian's eigenvalues); its
     area is prod(a) times the mean over unit vectors u of sqrt(sum u_i^2 /
-    a_i^2) times the unit sphere's area, which fixes delta (for input sizing
-    only)."""
+    a_i^2) times the unit sphere's area, which fixes delta.  delta is then
+    halved until, along random rays u, h(s) = f0(x0 + s rho(u) u) - f0(x0) -
+    delta (rho(u) the ellipsoid's radius along u) stays below
+    -delta (1 - s^2) / 4 out to s = 0.8 and above delta (s^2 - 1) / 4 from
+    s = 1.2 to 3, inside the box: the boundary then lies within 0.8 and 1.2
+    of the ellipsoid on every ray and the blob is the whole traced component.
+    If delta falls below 2^-30 of its first value x0 is planted anew (input
+    sizing only)."""
     d = fm.d
-    X = rng.uniform(dom.lo * 0.9, dom.hi * 0.9, size=(n_probe, d))
-    x = X[np.argmin(_f0(fm, X))].copy()
-    lo, hi = dom.lo * 0.9, dom.hi * 0.9
-    for _ in range(iters):
-        g, H = _poly_grad_hess(fm, x)
-        ev, V = np.linalg.eigh(H)
-        step = -(V @ ((V.T @ g) / np.maximum(ev, 1e-9 * max(1.0, abs(ev).max()))))
-        x = np.clip(x + step, lo, hi)
-    _, H = _poly_grad_hess(fm, x)
-    lam_i = np.maximum(np.linalg.eigvalsh(H), 1e-12)
-    a1 = lam_i ** -0.5                       # semi-axes at 2 delta = 1
-    u = rng.standard_normal((n_dirs, d))
-    u /= np.linalg.norm(u, axis=1, keepdims=True)
     sphere_area = 2 * math.pi ** (d / 2) / math.gamma(d / 2)
-    area1 = float(np.prod(a1) * np.mean(np.sqrt((u ** 2 / a1 ** 2).sum(1))) * sphere_area)
-    two_delta = (area / area1) ** (2.0 / (d - 1))
-    return -(float(_f0(fm, x[None])[0]) + 0.5 * two_delta), x
+    s = np.concatenate([np.linspace(0.2, 0.8, 7), np.linspace(1.2, 3.0, 19)])
+    env = 0.25 * (s * s - 1.0)
+    for _ in range(tries):
+        x0, H = planted_minimum(fm, dom, rng)
+        lam_i = np.linalg.eigvalsh(H)
+        a1 = lam_i ** -0.5                       # semi-axes at 2 delta = 1
+        u = rng.standard_normal((n_dirs, d))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        area1 = float(np.prod(a1) * np.mean(np.sqrt((u ** 2 / a1 ** 2).sum(1))) * sphere_area)
+        two_delta0 = two_delta = (area / area1) ** (2.0 / (d - 1))
+        f00 = float(_f0(fm, x0[None])[0])
+        ur = u[:n_rays]
+        uHu = np.einsum("ri,ij,rj->r", ur, H, ur)
+        while two_delta > two_delta0 * 2.0 ** -30:
+            rho = np.sqrt(two_delta / uHu)
+            P = x0[None, None, :] + (s[None, :, None] * rho[:, None, None]) * ur[:, None, :]
+            if ((P >= dom.lo) & (P <= dom.hi)).all():
+                delta = 0.5 * two_delta
+                h = _f0(fm, P.reshape(-1, d)).reshape(len(ur), len(s)) - f00 - delta
+                inner = s < 1.0
+                if (h[:, inner] <= delta * env[inner]).all() and (h[:, ~inner] >= delta * env[~inner]).all():
+                    return -(f00 + delta), x0
+            two_delta *= 0.5
+    raise RuntimeError("planted blob does not separate from the rest of {f < 0}")
 
 
-def fullbox_case(d, S, lam, target_cells, seed=0, p=3, k=1, scene=None, n_seeds=4) -> Workload:
-    """Degree-p kernel over the whole box [-pi, pi]^d, N(0,1) coefficients,
-    with {f < 0} a planted blob whose boundary crosses about target_cells
-    edges at scale lam: area A = target lam^(d-1) / C_d (planted_blob).
+def fullbox_case(d, S, lam, target_cells, seed=0, p=3, k=1, scene=None, n_seeds=4, coef0=1.0) -> Workload:
+    """Degree-p kernel over the whole box [-pi, pi]^d, coefficient
+    magnitudes |N(0,1)| with the signs (and a small correction) that plant an
+    interior minimum (planted_minimum), and {f < 0} a blob around it whose
+    boundary crosses about target_cells edges at scale lam: area
+    A = target lam^(d-1) / C_d (planted_blob).
     Seeds: bisection from the blob's centre outwards along random
     directions."""
     rng = np.random.default_rng(seed)
     dom = box(d)
-    fm = random_manifold(d, S, p, rng, dom, alpha="normal")
+    fm = random_manifold(d, S, p, rng, dom, alpha="normal", coef0=coef0)
     A = target_cells * lam ** (d - 1) / _edge_density(d)
     fm.bias, xc = planted_blob(fm, dom, rng, A)
     # a length on the blob's scale for the seed rays
@@ -561,10 +607,12 @@ def fullbox_case(d, S, lam, target_cells, seed=0, p=3, k=1, scene=None, n_seeds=
 
 def serving_request(i, seed=0, cells=(1e5, 2e6)):
     """Proof request i of the serving workload: d in {4,5,6}, S log-uniform
-    in [100, 2000], scale uniform in [0.06, 0.12], degree 3, over the whole
-    box, the bias sized for a target cell count log-uniform in `cells`, its
-    own scene and seed 1000 + i; coarse factor k = 2 for d = 6 below scale
-    0.09, else direct."""
+    in [100, 2000], scale uniform in [0.06, 0.12], degree 3 with coef0 3 (the
+    cubic terms then bend a planted basin less, so it holds larger blobs),
+    over the whole box, the bias sized for a target cell count log-uniform in
+    `cells` (smaller where the basin cannot hold that blob), its own scene
+    and seed 1000 + i; coarse factor k = 2 for d = 6 below scale 0.09, else
+    direct."""
     rng = np.random.default_rng((seed, i))
     d = int(rng.integers(4, 7))
     S = int(round(math.exp(rng.uniform(math.log(100), math.log(2000)))))
@@ -574,7 +622,7 @@ def serving_request(i, seed=0, cells=(1e5, 2e6)):
     srng = np.random.default_rng(1000 + i)
     sc = spatial_arm_scene(srng, d, spheres_per_link=2, sphere_r=0.05, n_osph=6, n_obox=4,
                            obst_ball=((0.0, 0.0, 0.3), 0.9))
-    return fullbox_case(d, S, lam, target, seed=1000 + i, k=k, scene=sc)
+    return fullbox_case(d, S, lam, target, seed=1000 + i, k=k, scene=sc, coef0=3.0)
 
 
 def serving_requests(n=256, seed=0, cells=(1e5, 2e6)):
