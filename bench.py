@@ -92,15 +92,19 @@ def subdivide_flops(st, wl) -> int:
     """Floating-point operations of the fused subdivision launches, from the
     counters of the code that runs: every template point it evaluated
     (n_vertices; in the box, on an active face) costs its FP64 lattice
-    coordinates (d^2 fma) and the nested FP32 value; every coarse simplex
-    costs the coordinates of its d + 1 vertices and the region bound (per
-    non-constant monomial up to p multiplies and an add)."""
+    coordinates (d^2 fma) and the nested FP32 value."""
+    d, p = wl.f.d, wl.f.p
+    return st["n_vertices"] * (2 * d * d + nest_flops(d, p))
+
+
+def prep_flops_per_simplex(wl) -> int:
+    """FP64 operations of the preparation kernel per coarse simplex: the
+    coordinates of its d + 1 vertices (d^2 fma each) and the region bound
+    (per non-constant monomial up to p multiplies and an add).  Its d + 1
+    probes of the coarse vertex table are not counted."""
     from math import comb
     d, p = wl.f.d, wl.f.p
-    m1 = comb(d + p, p) - 1
-    per_pt = 2 * d * d + nest_flops(d, p)
-    per_sigma = (d + 1) * 2 * d * d + (p + 1) * m1
-    return st["n_vertices"] * per_pt + st["n_sigma"] * per_sigma
+    return (d + 1) * 2 * d * d + (p + 1) * (comb(d + p, p) - 1)
 
 
 def check_flops_per_cell(wl) -> int:
@@ -495,7 +499,7 @@ def main():
         s = st[-1]
         return {"simplices_per_s": s["n_cells"] * len(st) / el, "ms_per_step": el * 1e3 / len(st),
                 "phases_ms": {"trace": phase(st, "ms_total"), "search": phase(st, "ms_expand"),
-                              "subdivide": phase(st, "ms_subdivide"), "feval": phase(st, "ms_feval"),
+                              "subdivide": phase(st, "ms_subdivide"), "prep": phase(st, "ms_prep"), "feval": phase(st, "ms_feval"),
                               "points": phase(st, "ms_points"), "check": phase(st, "ms_check")},
                 "edge_hits": s["n_edge_hits"], "edge_set_probes": s["n_shared_probes"],
                 "vertices_evaluated": s["n_vertices"], "fp64_canonical_evals": s["n_fallback"],
@@ -527,6 +531,8 @@ def main():
             flops_per_point=2 * wl.f.d ** 2 + nest_flops(wl.f.d, wl.f.p))
         alu("sub_points_kernel", points_flops_per_cell(wl) * n_cells, phase(stats, "ms_points"),
             flops_per_cell=points_flops_per_cell(wl))
+        alu("sub_prep_kernel", prep_flops_per_simplex(wl) * s_last["n_sigma"], phase(stats, "ms_prep"),
+            flops_per_simplex=prep_flops_per_simplex(wl))
         sg_ms = phase(stats, "ms_sigma")
         gbs = sigma_bytes(s_last) / (sg_ms * 1e-3) / 1e9 if sg_ms > 0 else 0.0
         kernels["sigma_kernel"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,

@@ -169,6 +169,9 @@ typedef struct {
   double ms_refine;      /* time in the iterative intersection kernel */
   int32_t refine_iters;  /* its iterations per edge (flags of ip_trace) */
   int32_t pad0;
+  double ms_prep;        /* batch mode: time in the per-coarse-simplex
+                            preparation (traced coarse edges among its
+                            vertices, tier-1 bound of its template points) */
 } ip_stats;
 
 /* Create a context on HIP device `device`; work is issued on `hip_stream`

@@ -1040,12 +1040,22 @@ __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo,
 //
 // Active faces.  Whether this simplex takes the edges of face tau depends
 // only on the coarse trace (tau traced or not, this simplex canonical for
-// tau or not), not on f.  So the wave first lists its active faces (not
-// traced, or traced with this simplex canonical), then takes the sign of f
-// only at the template points of their edges, and tests only their edges:
-// the template edges are grouped by face, and the active groups are laid
-// end to end in a virtual index space [0, T) that the lanes walk 64 at a
-// time (a bitmap of group starts maps a virtual index to its group).
+// tau or not), not on f.  Both are bit masks over the 2^(d+1) vertex subsets
+// V, formed with scalar operations from two per-simplex facts: the traced
+// coarse edges (i, j) among its vertices (V is traced when it holds one:
+// the union over them of {V : i, j in V}), and the positions p where the
+// root sequence descends (V is canonical when it holds all of them: the
+// ascending-roots rule read position by position).  The wave takes the sign
+// of f only at the template points of active faces' edges, and tests only
+// their edges: the template edges are grouped by face, and the active groups
+// are laid end to end in a virtual index space [0, T) that the lanes walk 64
+// at a time (a bitmap of group starts maps a virtual index to its group).
+//
+// Preparation.  The traced edges among a simplex's vertices (D + 1 probes of
+// the coarse vertex table) and its tier-1 bound (the frame at its D + 1
+// vertices and one pass over the monomials) are computed beforehand by
+// sub_prep_kernel, one lane per coarse simplex, rather than on D + 1 of the
+// wave's 64 lanes.
 //
 // Sign codes.  The signs are kept in LDS as byte codes: 0 (f < 0), 1
 // (f >= 0), 2 (outside the box), 3 (neither certified tier settles the
@@ -1069,12 +1079,11 @@ constexpr int kEdgeStage = 128;
 // Dynamic LDS of one block, as byte offsets (each array 16-byte aligned).
 // Shared by the block: the fine frame (M row-major stride 8, then o, lo, hi),
 // the monomial coefficients (FP64 and FP32), the template points, their
-// face masks, edges and face groups.  Per wave: two append stages, an
-// 8-double scratch (the region bound's |x| maxima, then the coarse edge rows
-// and root sequence), the start bitmap and the list of the active groups,
-// the edge stage, the active point list and the sign codes.
+// face masks, edges and face groups.  Per wave: two append stages, the start
+// bitmap and the list of the active groups, the edge stage, the active point
+// list and the sign codes.
 struct SubLayout {
-  uint32_t stage_s, stage_d, lx, lmat, lcd, lpts, lpf, sbm, lc, est, ledge, lgrp, agl, plist, code, total;
+  uint32_t stage_s, stage_d, lmat, lcd, lpts, lpf, sbm, lc, est, ledge, lgrp, agl, plist, code, total;
 };
 
 __host__ __device__ inline uint32_t sub_take(uint32_t &o, size_t bytes) {
@@ -1091,7 +1100,6 @@ __host__ __device__ inline SubLayout sub_layout(int NP, int NE, int M, int NV) {
   uint32_t o = 0;
   L.stage_s = sub_take(o, (size_t)kWaves * kSubStage * 8);
   L.stage_d = sub_take(o, (size_t)kWaves * kSubStage * 8);
-  L.lx = sub_take(o, (size_t)kWaves * 8 * 8);
   L.lmat = sub_take(o, 88 * 8);
   L.lcd = sub_take(o, (size_t)M * 8);
   L.lpts = sub_take(o, (size_t)NP * 8);
@@ -1139,6 +1147,97 @@ struct SubOut {
   uint64_t dcap;      // capacity of out_d (appends past it are counted, not written)
 };
 
+// What the subdivision of one coarse simplex takes from the coarse trace and
+// the frame: its tier-1 bound B1 and the traced coarse edges among its
+// vertices (byte i: bit j set when edge (i, j), i < j, is traced).
+struct SubPrep {
+  double B1;
+  uint64_t rows;
+};
+
+// One lane per coarse simplex sig[i], i < n (grid-stride).  Vertex i of the simplex is
+// v + 1_{w_0 .. w_{i-1}}; edge (i, j) has direction R = {w_i .. w_{j-1}}
+// from vertex i and is traced when bit R of that vertex's visited-edge mask
+// is set.  The bound: |x_j| is largest at a vertex (fine coordinates
+// k (v + 1_{w_0 .. w_{i-1}})), so with X_j the maximum over the vertices,
+// B1 = K32n sum_m |c_m| X^m + E0 covers every template point (BOUND false:
+// B1 = 0, the FP64 mode).
+template <int D, bool BOUND>
+__global__ __launch_bounds__(kBlock) void sub_prep_kernel(LatDev Lf, LatDev Lc, int LB, int k,
+                                                          const uint64_t *__restrict__ sig, uint64_t n,
+                                                          const VEnt *__restrict__ cvt, uint64_t cvt_mask, PolyDev Q,
+                                                          SubPrep *__restrict__ out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    int32_t v[D], w[D];
+    sig_unpack<D>(Lc, sig[i], LB, v, w);
+    uint64_t rows = 0;
+    double X[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) X[j] = 0.0;
+    int32_t cv[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) cv[c] = v[c];
+    for (int vi = 0; vi <= D; ++vi) {
+      if (vi > 0) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) cv[c] += c == w[vi - 1] ? 1 : 0;
+      }
+      if (BOUND) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          double acc = Lf.o[j];
+#pragma unroll
+          for (int c = 0; c < D; ++c) acc = fma(Lf.M[j * 8 + c], (double)(k * cv[c]), acc);
+          X[j] = fmax(X[j], fabs(acc));
+        }
+      }
+      if (vi == D || !vin_range<D>(Lc, cv)) continue;
+      const int64_t h = vt_find(cvt, cvt_mask, vpack<D>(Lc, cv));
+      if (h < 0) continue;
+      const uint64_t m0 = cvt[h].m[0], m1 = cvt[h].m[1];
+      uint32_t R = 0;
+      for (int j = vi + 1; j <= D; ++j) {
+        R |= 1u << w[j - 1];
+        const uint64_t word = R < 64 ? m0 : m1;
+        if ((word >> (R & 63u)) & 1ull) rows |= 1ull << (8 * vi + j);
+      }
+    }
+    double B1 = 0.0;
+    if (BOUND) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) X[j] = X[j] * (1.0 + 1e-12) + 1e-300;
+      double t = 0.0;
+      for (int m = 0; m < Q.M; ++m) {
+        const uint32_t pk = Q.mono[m];
+        double term = fabs(Q.cd[m]);
+        for (int q = 0; q < (int)(pk & 15u); ++q) {
+          const uint32_t jj = (pk >> (4 + 4 * q)) & 15u;
+          double xj = X[0];
+#pragma unroll
+          for (int j = 1; j < D; ++j) xj = jj == (uint32_t)j ? X[j] : xj;
+          term *= xj;
+        }
+        t += term;
+      }
+      B1 = Q.K32n * (t * (1.0 + 1e-12)) + Q.E0;
+    }
+    out[i] = SubPrep{B1, rows};
+  }
+}
+
+// Bit b of word t set when vertex i belongs to the vertex subset 64 t + b.
+__device__ __forceinline__ uint64_t vertex_pattern(int i, int t) {
+  switch (i) {
+    case 0: return 0xAAAAAAAAAAAAAAAAull;
+    case 1: return 0xCCCCCCCCCCCCCCCCull;
+    case 2: return 0xF0F0F0F0F0F0F0F0ull;
+    case 3: return 0xFF00FF00FF00FF00ull;
+    case 4: return 0xFFFF0000FFFF0000ull;
+    case 5: return 0xFFFFFFFF00000000ull;
+    default: return ((t >> (i - 6)) & 1) ? ~0ull : 0ull;
+  }
+}
+
 // Four waves per SIMD (the LDS allows four blocks per CU): the register cap
 // this sets costs a few spilled registers, fewer than a wave of occupancy.
 template <int D, int P, int MODE>
@@ -1150,7 +1249,8 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
                                                            const uint32_t *__restrict__ tgrp,
                                                            const uint64_t *__restrict__ tpf, PolyDev Q,
                                                            VEnt *fvt, uint64_t fvt_mask, uint32_t *eval_list,
-                                                           const uint32_t *__restrict__ pslot, SubOut so,
+                                                           const uint32_t *__restrict__ pslot,
+                                                           const SubPrep *__restrict__ prep, SubOut so,
                                                            uint32_t *defer, Counters *ctr) {
   constexpr int NV = 1 << (D + 1);        // vertex subsets of a coarse simplex
   constexpr int NVW = (NV + 63) / 64;     // 64-bit words per face mask
@@ -1165,7 +1265,6 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
   const SubLayout Ly = sub_layout(NP, NE, M, NV);
   uint64_t *stage_s = (uint64_t *)(smem + Ly.stage_s) + (size_t)wib * kSubStage;
   uint64_t *stage_d = (uint64_t *)(smem + Ly.stage_d) + (size_t)wib * kSubStage;
-  double *lx = (double *)(smem + Ly.lx) + (size_t)wib * 8;
   // fine frame in LDS: read at wave-uniform addresses, it stays out of the
   // scalar registers
   double *lmat = (double *)(smem + Ly.lmat);
@@ -1218,125 +1317,46 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
     int32_t v[D], w[D], winv[D];
     sig_unpack<D>(Lc, sig[s], LB, v, w);
     perm_inverse<D>(w, winv);
-    // coarse vertex `lane` (lanes 0..D) of the simplex, v + 1_{w_0 .. w_{lane-1}},
-    // and the coarse-table entry at its home slot: loaded here, used after
-    // the region bound, so the load latency hides behind it
-    uint64_t ckey = IP_EMPTY_KEY, hkey = IP_EMPTY_KEY, hm0 = 0, hm1 = 0;
-    if (lane <= D) {
-      int32_t cv[D];
+    const SubPrep pr = prep[s];
+    const double B1 = pr.B1;
+    // face masks (scalar): traced = some traced coarse edge (i, j) inside V;
+    // canonical = V holds every position p whose root is below the root
+    // before it, cyclically (roots w_0 .. w_{D-1}, D); active = not traced,
+    // or canonical; V = 0 and V >= 2^(D+1) never
+    uint32_t desc = 1u;  // p = 0: w_0 < D
 #pragma unroll
-      for (int c = 0; c < D; ++c) cv[c] = v[c] + (winv[c] < lane ? 1 : 0);
-      if (vin_range<D>(Lc, cv)) {
-        ckey = vpack<D>(Lc, cv);
-        const VEnt *e0 = so.cvt + (mix64(ckey) & so.cvt_mask);
-        hkey = e0->key;
-        hm0 = e0->m[0];
-        hm1 = e0->m[1];
-      }
-    }
-    // tier-1 bound for the whole coarse simplex: |x_j| is largest at a
-    // vertex (fine coordinates k (v + 1_{w_0 .. w_{i-1}})), so one bound on
-    // the FP32 sum S_abs covers every template point
-    double B1 = 0.0;
-    if (MODE != 3) {
-      const int vi = lane <= D ? lane : D;
-      int32_t yv[D];
+    for (int q = 1; q < D; ++q) desc |= w[q] < w[q - 1] ? 1u << q : 0u;
+    uint64_t A[NVW], TR[NVW];
 #pragma unroll
-      for (int c = 0; c < D; ++c) yv[c] = k * v[c] + (winv[c] < vi ? k : 0);
-      double xv[D];
-      lat_coords_m<D>(lmat, yv, xv);
-      // max over the D + 1 vertices through LDS (the edge stage is free
-      // until the edge pass): vertex i's |x| at va[i * D + j]
-      static_assert(kEdgeStage * 4 >= (D + 1) * D * 8, "edge stage too small for the vertex coordinates");
-      double *va = (double *)est;
-      if (lane <= D) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) va[lane * D + j] = fabs(xv[j]);
-      }
-      wave_lds_sync();
-      double *X = lx;
-      if (lane < D) {
-        double a = 0.0;
-#pragma unroll
-        for (int i = 0; i <= D; ++i) a = fmax(a, va[i * D + lane]);
-        X[lane] = a * (1.0 + 1e-12) + 1e-300;
-      }
-      wave_lds_sync();
-      B1 = Ql.K32n * region_sabs_bound(Ql, X, lane) + Ql.E0;
-    }
-    // traced coarse edges among the simplex's vertices: vertex i is
-    // v + 1_{w_0 .. w_{i-1}}, edge (i, j) for i < j has direction
-    // R = {w_i .. w_{j-1}} from its smaller end i; row i holds bit j when
-    // that edge is in the coarse trace
-    uint32_t row = 0;
-    if (lane <= D && ckey != IP_EMPTY_KEY) {
-      bool found = hkey == ckey;
-      uint64_t m0 = hm0, m1 = hm1;
-      if (!found && hkey != IP_EMPTY_KEY) {
-        const int64_t h = vt_find(so.cvt, so.cvt_mask, ckey);
-        if (h >= 0) {
-          found = true;
-          m0 = so.cvt[h].m[0];
-          m1 = so.cvt[h].m[1];
+    for (int t = 0; t < NVW; ++t) {
+      uint64_t tr = 0, cn = ~0ull;
+      for (int i = 0; i < D; ++i) {
+        uint32_t r = (uint32_t)(pr.rows >> (8 * i)) & 0xffu;
+        const uint64_t si = vertex_pattern(i, t);
+        while (r) {
+          const int j = __builtin_ctz(r);
+          r &= r - 1u;
+          tr |= si & vertex_pattern(j, t);
         }
       }
-      if (found) {
-        // edge (lane, j): R = the coordinates c with lane <= winv[c] < j
 #pragma unroll
-        for (int j = 1; j <= D; ++j) {
-          if (j <= lane) continue;
-          uint32_t R = 0;
-#pragma unroll
-          for (int c = 0; c < D; ++c) R |= (winv[c] >= lane && winv[c] < j) ? 1u << c : 0u;
-          const uint64_t word = R < 64 ? m0 : m1;
-          if ((word >> (R & 63u)) & 1ull) row |= 1u << j;
-        }
-      }
-    }
-    // rows and the cyclic root sequence (w_0 .. w_{D-1}, D) go to the
-    // wave's LDS scratch (the region-bound area, read above in order) for
-    // the lane-indexed reads below; the start bitmap is cleared
-    uint32_t *lrow = (uint32_t *)lx;
-    int32_t *lseq = (int32_t *)lx + 8;
-    if (lane <= D) {
-      lrow[lane] = row;
-      int32_t wl = D;
-#pragma unroll
-      for (int c = 0; c < D; ++c) wl = winv[c] == lane ? c : wl;
-      lseq[lane] = wl;
+      for (int q = 0; q < D; ++q)
+        if ((desc >> q) & 1u) cn &= vertex_pattern(q, t);
+      uint64_t valid = NV >= 64 ? ~0ull : (1ull << (NV & 63)) - 1ull;
+      if (t == 0) valid &= ~1ull;
+      TR[t] = tr & valid;
+      A[t] = (~tr | cn) & valid;
     }
     for (int i = lane; i < SBW; i += 64) sbm[i] = 0ull;
     wave_lds_sync();
-    // active faces V: traced (V holds a traced coarse edge) and canonical
-    // (this simplex is the canonical n-coface of V) decide; an active face
-    // with edges gets a slot in agl (first edge | virtual start << 15 |
-    // set path << 31) and its virtual start a bit in sbm
-    uint64_t A[NVW];
+    // the active faces with edges get a slot in agl (first edge | virtual
+    // start << 15 | set path << 31) and their virtual starts a bit in sbm
     int T = 0, G = 0;
 #pragma unroll
     for (int t = 0; t < NVW; ++t) {
       const uint32_t V = (uint32_t)(lane + 64 * t);
-      bool trv = false, cnv = false;
-      uint32_t gd = 0;
-      if (V < (uint32_t)NV && V != 0u) {
-        gd = lgrp[V];
-        for (int i = 0; i <= D; ++i)
-          if (((V >> i) & 1u) && (lrow[i] & V)) trv = true;
-        // blocks of V's partition: the roots after each vertex of V up to
-        // the next one, cyclically (root of step p: w_p for p < D, D for p = D)
-        const int start = __ffs((int)V) - 1;
-        int prev = -1;
-        cnv = true;
-        for (int q = 0; q <= D; ++q) {
-          int pidx = start + q;
-          if (pidx > D) pidx -= D + 1;
-          if ((V >> pidx) & 1u) prev = -1;
-          const int r = lseq[pidx];
-          if (r < prev) cnv = false;
-          prev = r;
-        }
-      }
-      const bool act = (gd >> 16) != 0u && (!trv || cnv);
+      const bool act = (A[t] >> lane) & 1ull, trv = (TR[t] >> lane) & 1ull;
+      const uint32_t gd = V < (uint32_t)NV ? lgrp[V] : 0u;
       const uint32_t cnt = act ? gd >> 16 : 0u;
       // exclusive prefix sum of cnt over the lanes, one bit plane at a time;
       // cnt is the upper half of a 32-bit group word, below 2^16, and the
@@ -1347,9 +1367,8 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
         excl += (uint32_t)__popcll(bb & lt_mask) << b;
         tot += (uint32_t)__popcll(bb) << b;
       }
-      const uint64_t ba = __ballot(act);
-      A[t] = ba;
-      if (act) {
+      const uint64_t ba = __ballot(cnt != 0u);
+      if (cnt) {
         const uint32_t vs = (uint32_t)T + excl;
         agl[G + __popcll(ba & lt_mask)] = (gd & 0x7fffu) | (vs << 15) | (trv ? 0u : 0x80000000u);
         atomicOr((uint32_t *)sbm + (vs >> 5), 1u << (vs & 31u));
@@ -1793,10 +1812,25 @@ struct SubArgs {
   uint64_t cvt_mask;
 };
 
+// The preparation of coarse simplices sig[0 .. n) (B1 only with `bound`).
+template <int D>
+int launch_prep(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig, uint64_t n, bool bound,
+                SubPrep *prep) {
+  if (n == 0) return IP_OK;
+  if (bound)
+    hipLaunchKernelGGL((sub_prep_kernel<D, true>), dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, p->fine, p->coarse,
+                       a.LB, p->k, sig, n, a.cvt, a.cvt_mask, p->poly, prep);
+  else
+    hipLaunchKernelGGL((sub_prep_kernel<D, false>), dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, p->fine,
+                       p->coarse, a.LB, p->k, sig, n, a.cvt, a.cvt_mask, p->poly, prep);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
+}
+
 template <int D, int MODE>
 int launch_sub(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig, const uint32_t *list,
                uint64_t n, VEnt *fvt, uint64_t fvt_mask, uint32_t *eval, const BatchSink &g, uint32_t *defer,
-               const uint32_t *pslot = nullptr) {
+               const SubPrep *prep, const uint32_t *pslot = nullptr) {
   if (n == 0) return IP_OK;
   const size_t lds = sub_layout(a.NP, a.NE, MODE == 3 ? 0 : p->poly.M, 1 << (D + 1)).total;
   const uint64_t blocks = std::min<uint64_t>((n + kWaves - 1) / kWaves, kSubGrid);
@@ -1804,7 +1838,7 @@ int launch_sub(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_
 #define IP_SUB(PP)                                                                                                  \
   hipLaunchKernelGGL((subdivide_kernel<D, PP, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, ctx->stream,     \
                      p->fine, p->coarse, a.LB, p->k, sig, list, n, a.tpts, a.NP, a.tedge, a.NE, a.tgrp, a.tpf, p->poly, \
-                     fvt, fvt_mask, eval, pslot, so, defer, ctx->ctr_dev)
+                     fvt, fvt_mask, eval, pslot, prep, so, defer, ctx->ctr_dev)
   if (MODE == 3) {
     IP_SUB(1);
     IP_TRY_HIP(ctx, hipGetLastError());
@@ -1898,29 +1932,35 @@ int init_sink(BatchSink &g, uint64_t nc, int k) {
 
 // Subdivision of the coarse simplices sig[0 .. nsig) in the FP32-certified
 // mode (subdivide_kernel MODE 0-2): no vertex table, so the per-batch
-// workspace is one 4-byte deferred-list entry per coarse simplex, plus the
-// fallback vertex table for the points no certified tier settles (sized
-// from their count).
+// workspace is one 4-byte deferred-list entry and one preparation record per
+// coarse simplex, plus the fallback vertex table for the points no
+// certified tier settles (sized from their count).
 template <int D>
 int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig_all, uint64_t nsig,
                     uint64_t nc, uint64_t budget, ip_stats &st, ip_cells *res) {
   const int NP = a.NP, NE = a.NE;
   if (budget == 0) budget = 4ull << 30;
-  uint64_t B = std::min<uint64_t>(budget / 4, 0xffffffffull);
+  uint64_t B = std::min<uint64_t>(budget / (4 + sizeof(SubPrep)), 0xffffffffull);
   if (B == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
   if (B > nsig) B = nsig ? nsig : 1;
   IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * 4));
   uint32_t *defer = (uint32_t *)ctx->vt_aux.p;
+  DevTmp prep_hold(ctx);
+  IP_TRY(prep_hold.get(B * sizeof(SubPrep)));
+  SubPrep *prep = prep_hold.as<SubPrep>();
   BatchSink g(ctx);
   IP_TRY(init_sink<D>(g, nc, p->k));
   Counters *c = ctx->ctr_host;
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
   int64_t regrows = 0, n_fallback = 0, n_settled64 = 0, n_pts = 0, batches = 0;
-  Timer tf, tx, tp, ts;
+  Timer tf, tx, tp, ts, tq;
   for (uint64_t b0 = 0; b0 < nsig; b0 += B) {
     const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
     const uint64_t *sig = sig_all + b0;
     ++batches;
+    IP_TRY(tq.start(ctx, &st.ms_prep));
+    IP_TRY(launch_prep<D>(ctx, p, a, sig, nb, true, prep));
+    IP_TRY(tq.stop(ctx));
     IP_TRY(run_with_replay(ctx, g, regrows, [&]() -> int {
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_unsettled));
@@ -1929,7 +1969,7 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_shared));
       IP_TRY(ts.start(ctx, &st.ms_subdivide));
-      IP_TRY((launch_sub<D, 0>(ctx, p, a, sig, nullptr, nb, nullptr, 0, nullptr, g, defer)));
+      IP_TRY((launch_sub<D, 0>(ctx, p, a, sig, nullptr, nb, nullptr, 0, nullptr, g, defer, prep)));
       ++st.subdivide_launches;
       return ts.stop(ctx);
     }));
@@ -1950,7 +1990,7 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
       IP_TRY(zero_fail_flags(ctx));
       IP_TRY(tx.start(ctx, &st.ms_expand));
-      IP_TRY((launch_sub<D, 1>(ctx, p, a, sig, defer, n_def, fvt, fcap - 1, eval, g, nullptr)));
+      IP_TRY((launch_sub<D, 1>(ctx, p, a, sig, defer, n_def, fvt, fcap - 1, eval, g, nullptr, prep)));
       IP_TRY(tx.stop(ctx));
       IP_TRY(read_ctr(ctx));
       if (c->vt_fail) return ip_fail(ctx, IP_ENOMEM, "fallback vertex table overflow");
@@ -1963,7 +2003,7 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
         IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
         IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_shared));
         IP_TRY(ts.start(ctx, &st.ms_subdivide));
-        IP_TRY((launch_sub<D, 2>(ctx, p, a, sig, defer, n_def, fvt, fcap - 1, nullptr, g, nullptr)));
+        IP_TRY((launch_sub<D, 2>(ctx, p, a, sig, defer, n_def, fvt, fcap - 1, nullptr, g, nullptr, prep)));
         ++st.subdivide_launches;
         return ts.stop(ctx);
       }));
@@ -1993,6 +2033,7 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   IP_TRY(tx.flush(ctx));
   IP_TRY(tp.flush(ctx));
   IP_TRY(ts.flush(ctx));
+  IP_TRY(tq.flush(ctx));
   res->d = D;
   res->B = p->fine.B;
   for (int j = 0; j < 8; ++j) res->vmin[j] = p->fine.vmin[j];
@@ -2022,12 +2063,15 @@ template <int D>
 int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig_all, uint64_t nsig,
                     uint64_t nc, uint64_t budget, bool cert, ip_stats &st, ip_cells *res) {
   const int k = p->k, NP = a.NP, NE = a.NE;
-  // a slot: VEnt, eval-list entry and, certified, its bound and fallback entry
+  // a slot: VEnt, eval-list entry and, certified, its bound and fallback
+  // entry; per coarse simplex (one per 2 NP slots) its preparation record
   const uint64_t slot_bytes = sizeof(VEnt) + 4 + (cert ? 8 : 0);
   if (budget == 0) budget = 4ull << 30;
   uint64_t vcap_b = 0;
   for (uint64_t cc = 1024; cc <= (1ull << 32); cc <<= 1)
-    if (cc * slot_bytes + (cc / 2) * 4 <= budget && cc >= 2 * (uint64_t)NP) vcap_b = cc;
+    if (cc * slot_bytes + (cc / 2) * 4 + cc / (2 * (uint64_t)NP) * sizeof(SubPrep) <= budget &&
+        cc >= 2 * (uint64_t)NP)
+      vcap_b = cc;
   if (vcap_b == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
   uint64_t B = vcap_b / (2 * (uint64_t)NP);
   if (B > nsig) B = nsig ? nsig : 1;
@@ -2052,17 +2096,23 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
     f.fb_cap = ctx->vtf.fb.bytes / 4;
   }
   uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
+  DevTmp prep_hold(ctx);
+  IP_TRY(prep_hold.get(B * sizeof(SubPrep)));
+  SubPrep *prep = prep_hold.as<SubPrep>();
   BatchSink g(ctx);
   IP_TRY(init_sink<D>(g, nc, k));
   Counters *c = ctx->ctr_host;
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
-  Timer tf, tx, tp, ts;
+  Timer tf, tx, tp, ts, tq;
   int64_t batches = 0;
   uint64_t dir_done = 0, set_done = 0;
   for (uint64_t b0 = 0; b0 < nsig; b0 += B) {
     const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
     const uint64_t *sig = sig_all + b0;
     ++batches;
+    IP_TRY(tq.start(ctx, &st.ms_prep));
+    IP_TRY(launch_prep<D>(ctx, p, a, sig, nb, false, prep));
+    IP_TRY(tq.stop(ctx));
     IP_TRY(fill_vt(ctx, f.vt, vcap));
     IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_eval));
     IP_TRY(tx.start(ctx, &st.ms_expand));
@@ -2081,7 +2131,7 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_shared));
       IP_TRY(ts.start(ctx, &st.ms_subdivide));
-      IP_TRY((launch_sub<D, 3>(ctx, p, a, sig, nullptr, nb, f.vt, vcap - 1, nullptr, g, nullptr, pslot)));
+      IP_TRY((launch_sub<D, 3>(ctx, p, a, sig, nullptr, nb, f.vt, vcap - 1, nullptr, g, nullptr, prep, pslot)));
       ++st.subdivide_launches;
       return ts.stop(ctx);
     }));
@@ -2135,6 +2185,7 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   IP_TRY(tx.flush(ctx));
   IP_TRY(tp.flush(ctx));
   IP_TRY(ts.flush(ctx));
+  IP_TRY(tq.flush(ctx));
   const uint64_t n = dir_done + set_done;
   res->d = D;
   res->B = p->fine.B;

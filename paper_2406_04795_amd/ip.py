@@ -68,7 +68,8 @@ class ip_stats(C.Structure):
                 ("subdivide_launches", C.c_int64), ("n_edge_hits", C.c_int64),
                 ("n_coarse_edges", C.c_int64), ("n_shared_probes", C.c_int64),
                 ("ms_sigma", C.c_double), ("n_ncofaces", C.c_int64), ("n_hip_malloc", C.c_int64), ("hip_malloc_bytes", C.c_int64),
-                ("ms_refine", C.c_double), ("refine_iters", C.c_int32), ("pad0", C.c_int32)]
+                ("ms_refine", C.c_double), ("refine_iters", C.c_int32), ("pad0", C.c_int32),
+                ("ms_prep", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
