@@ -1078,12 +1078,13 @@ constexpr int kEdgeStage = 128;
 
 // Dynamic LDS of one block, as byte offsets (each array 16-byte aligned).
 // Shared by the block: the fine frame (M row-major stride 8, then o, lo, hi),
-// the monomial coefficients (FP64 and FP32), the template points, their
-// face masks, edges and face groups.  Per wave: two append stages, the start
-// bitmap and the list of the active groups, the edge stage, the active point
-// list and the sign codes.
+// the monomial coefficients (FP64 and FP32), the template points with their
+// face masks, the faces' point masks, the edges and face groups.  Per wave:
+// two append stages, the start bitmap, the sign masks over the points and
+// the list of the active groups, the edge stage, the active point list and
+// the sign codes.
 struct SubLayout {
-  uint32_t stage_s, stage_d, lmat, lcd, lpts, lpf, sbm, lc, est, ledge, lgrp, agl, plist, code, total;
+  uint32_t stage_s, stage_d, lmat, lcd, lpts, lpf, lpv, sbm, lc, est, ledge, lgrp, lmask, agl, plist, code, total;
 };
 
 __host__ __device__ inline uint32_t sub_take(uint32_t &o, size_t bytes) {
@@ -1095,7 +1096,7 @@ __host__ __device__ inline uint32_t sub_take(uint32_t &o, size_t bytes) {
 // NP template points, NE template edges, M monomials (0: no coefficients),
 // NV = 2^(d+1) vertex subsets.
 __host__ __device__ inline SubLayout sub_layout(int NP, int NE, int M, int NV) {
-  const int NVW = (NV + 63) / 64, SBW = (NE + 63) / 64;
+  const int NVW = (NV + 63) / 64, NPW = (NP + 63) / 64, SBW = (NE + 63) / 64;
   SubLayout L;
   uint32_t o = 0;
   L.stage_s = sub_take(o, (size_t)kWaves * kSubStage * 8);
@@ -1104,11 +1105,13 @@ __host__ __device__ inline SubLayout sub_layout(int NP, int NE, int M, int NV) {
   L.lcd = sub_take(o, (size_t)M * 8);
   L.lpts = sub_take(o, (size_t)NP * 8);
   L.lpf = sub_take(o, (size_t)NP * NVW * 8);
+  L.lpv = sub_take(o, (size_t)NV * NPW * 8);
   L.sbm = sub_take(o, (size_t)kWaves * SBW * 8);
   L.lc = sub_take(o, (size_t)M * 4);
   L.est = sub_take(o, (size_t)kWaves * kEdgeStage * 4);
   L.ledge = sub_take(o, (size_t)NE * 4);
   L.lgrp = sub_take(o, (size_t)NV * 4);
+  L.lmask = sub_take(o, (size_t)kWaves * 2 * NPW * 8);
   L.agl = sub_take(o, (size_t)kWaves * NV * 4);
   L.plist = sub_take(o, (size_t)kWaves * NP * 2);
   L.code = sub_take(o, (size_t)kWaves * NP);
@@ -1247,7 +1250,8 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
                                                            const uint64_t *__restrict__ tpts, int NP,
                                                            const uint32_t *__restrict__ tedge, int NE,
                                                            const uint32_t *__restrict__ tgrp,
-                                                           const uint64_t *__restrict__ tpf, PolyDev Q,
+                                                           const uint64_t *__restrict__ tpf,
+                                                           const uint64_t *__restrict__ tpv, PolyDev Q,
                                                            VEnt *fvt, uint64_t fvt_mask, uint32_t *eval_list,
                                                            const uint32_t *__restrict__ pslot,
                                                            const SubPrep *__restrict__ prep, SubOut so,
@@ -1262,6 +1266,7 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   const int M = MODE == 3 ? 0 : Q.M;
   const int SBW = (NE + 63) / 64;
+  const int NPW = (NP + 63) / 64;
   const SubLayout Ly = sub_layout(NP, NE, M, NV);
   uint64_t *stage_s = (uint64_t *)(smem + Ly.stage_s) + (size_t)wib * kSubStage;
   uint64_t *stage_d = (uint64_t *)(smem + Ly.stage_d) + (size_t)wib * kSubStage;
@@ -1271,7 +1276,11 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
   double *lcd = (double *)(smem + Ly.lcd);
   uint64_t *lpts = (uint64_t *)(smem + Ly.lpts);
   uint64_t *lpf = (uint64_t *)(smem + Ly.lpf);
+  uint64_t *lpv = (uint64_t *)(smem + Ly.lpv);
   uint64_t *sbm = (uint64_t *)(smem + Ly.sbm) + (size_t)wib * SBW;
+  // per wave: the points with f < 0 and those with f >= 0
+  uint64_t *mneg = (uint64_t *)(smem + Ly.lmask) + (size_t)wib * 2 * NPW;
+  uint64_t *mpos = mneg + NPW;
   float *lc = (float *)(smem + Ly.lc);
   uint32_t *est = (uint32_t *)(smem + Ly.est) + (size_t)wib * kEdgeStage;
   uint32_t *ledge = (uint32_t *)(smem + Ly.ledge);
@@ -1301,6 +1310,7 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
   Ql.cd = lcd;
   for (int i = threadIdx.x; i < NE; i += kBlock) ledge[i] = tedge[i];
   for (int i = threadIdx.x; i < NV; i += kBlock) lgrp[i] = tgrp[i];
+  for (int i = threadIdx.x; i < NV * NPW; i += kBlock) lpv[i] = tpv[i];
   __syncthreads();
   int sn = 0, snd = 0;
   auto put_s = [&](unsigned long long pos, uint64_t key) { so.out_s[pos] = key; };
@@ -1347,36 +1357,8 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
       TR[t] = tr & valid;
       A[t] = (~tr | cn) & valid;
     }
-    for (int i = lane; i < SBW; i += 64) sbm[i] = 0ull;
-    wave_lds_sync();
-    // the active faces with edges get a slot in agl (first edge | virtual
-    // start << 15 | set path << 31) and their virtual starts a bit in sbm
-    int T = 0, G = 0;
-#pragma unroll
-    for (int t = 0; t < NVW; ++t) {
-      const uint32_t V = (uint32_t)(lane + 64 * t);
-      const bool act = (A[t] >> lane) & 1ull, trv = (TR[t] >> lane) & 1ull;
-      const uint32_t gd = V < (uint32_t)NV ? lgrp[V] : 0u;
-      const uint32_t cnt = act ? gd >> 16 : 0u;
-      // exclusive prefix sum of cnt over the lanes, one bit plane at a time;
-      // cnt is the upper half of a 32-bit group word, below 2^16, and the
-      // explicit bound keeps the loop finite whatever the word holds
-      uint32_t excl = 0, tot = 0;
-      for (int b = 0; b < 16 && __ballot((cnt >> b) != 0u); ++b) {
-        const uint64_t bb = __ballot((cnt >> b) & 1u);
-        excl += (uint32_t)__popcll(bb & lt_mask) << b;
-        tot += (uint32_t)__popcll(bb) << b;
-      }
-      const uint64_t ba = __ballot(cnt != 0u);
-      if (cnt) {
-        const uint32_t vs = (uint32_t)T + excl;
-        agl[G + __popcll(ba & lt_mask)] = (gd & 0x7fffu) | (vs << 15) | (trv ? 0u : 0x80000000u);
-        atomicOr((uint32_t *)sbm + (vs >> 5), 1u << (vs & 31u));
-      }
-      T += (int)tot;
-      G += __popcll(ba);
-    }
-    // active template points: an end of an edge of an active face
+    // active template points: an end of an edge of an active face; every
+    // code starts at 2
     int NPA = 0;
     for (int p0 = 0; p0 < NP; p0 += 64) {
       const int pt = p0 + lane;
@@ -1386,6 +1368,7 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
 #pragma unroll
         for (int t = 0; t < NVW; ++t) hit |= lpf[pt * NVW + t] & A[t];
         a = hit != 0ull;
+        code[pt] = 2;
       }
       const uint64_t bal = __ballot(a);
       if (a) plist[NPA + __popcll(bal & lt_mask)] = (uint16_t)pt;
@@ -1443,6 +1426,58 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
       if (lane == 0) defer[atomicAdd(&ctr->n_aux, 1ull)] = (uint32_t)s;
       wave_lds_sync();
       continue;
+    }
+    wave_lds_sync();
+    // sign masks over the template points (f < 0, f >= 0)
+    for (int q = 0; q < NPW; ++q) {
+      const int pt = 64 * q + lane;
+      const uint32_t c = pt < NP ? code[pt] : 2u;
+      const uint64_t ng = __ballot(c == 0u), ps = __ballot(c == 1u);
+      if (lane == 0) {
+        mneg[q] = ng;
+        mpos[q] = ps;
+      }
+    }
+    for (int i = lane; i < SBW; i += 64) sbm[i] = 0ull;
+    wave_lds_sync();
+    // an active face whose edge ends carry both signs gets a slot in agl
+    // (first edge | virtual start << 15 | set path << 31) and its virtual
+    // start a bit in sbm; one with a single sign has no intersecting edge
+    int T = 0, G = 0;
+#pragma unroll
+    for (int t = 0; t < NVW; ++t) {
+      const uint32_t V = (uint32_t)(lane + 64 * t);
+      const bool trv = (TR[t] >> lane) & 1ull;
+      bool act = (A[t] >> lane) & 1ull;
+      uint32_t gd = 0;
+      if (act) {
+        gd = lgrp[V];
+        uint64_t hn = 0, hp = 0;
+        for (int q = 0; q < NPW; ++q) {
+          const uint64_t pv = lpv[V * NPW + q];
+          hn |= pv & mneg[q];
+          hp |= pv & mpos[q];
+        }
+        act = hn != 0ull && hp != 0ull;
+      }
+      const uint32_t cnt = act ? gd >> 16 : 0u;
+      // exclusive prefix sum of cnt over the lanes, one bit plane at a time;
+      // cnt is the upper half of a 32-bit group word, below 2^16, and the
+      // explicit bound keeps the loop finite whatever the word holds
+      uint32_t excl = 0, tot = 0;
+      for (int b = 0; b < 16 && __ballot((cnt >> b) != 0u); ++b) {
+        const uint64_t bb = __ballot((cnt >> b) & 1u);
+        excl += (uint32_t)__popcll(bb & lt_mask) << b;
+        tot += (uint32_t)__popcll(bb) << b;
+      }
+      const uint64_t ba = __ballot(cnt != 0u);
+      if (cnt) {
+        const uint32_t vs = (uint32_t)T + excl;
+        agl[G + __popcll(ba & lt_mask)] = (gd & 0x7fffu) | (vs << 15) | (trv ? 0u : 0x80000000u);
+        atomicOr((uint32_t *)sbm + (vs >> 5), 1u << (vs & 31u));
+      }
+      T += (int)tot;
+      G += __popcll(ba);
     }
     // edge pass over the active groups: sign test from LDS; the edges to
     // emit (owner) or to dedup (no owner) are staged by index, and their keys
@@ -1594,13 +1629,15 @@ __global__ void sub_redo_kernel(LatDev L, const uint64_t *keys, const uint64_t *
 // coarse-simplex vertices whose barycentric weight is positive at either end
 // (Eq. 1: vertex 0 weighs k - u_0, vertex i in 1..d-1 weighs u_{i-1} - u_i,
 // vertex d weighs u_{d-1}), i.e. the smallest face holding the edge.  Edges
-// are grouped by face: grp[V] = first edge of face V | edge count << 16, and
-// pf[p * NVW + t] holds bit V - 64 t for every face V of an edge at point p.
+// are grouped by face: grp[V] = first edge of face V | edge count << 16,
+// pf[p * NVW + t] holds bit V - 64 t for every face V of an edge at point p,
+// and pv[V * NPW + t] bit p - 64 t for every end p of an edge of face V.
 struct Template {
   std::vector<uint64_t> pts;
   std::vector<uint32_t> edges;
   std::vector<uint32_t> grp;
   std::vector<uint64_t> pf;
+  std::vector<uint64_t> pv;
 };
 
 Template make_template(int d, int k) {
@@ -1648,13 +1685,18 @@ Template make_template(int d, int k) {
       const int b = index_of(y);
       by_face[support(P[a]) | support(y)].push_back((uint32_t)a | ((uint32_t)b << 12) | (R << 24));
     }
+  const size_t NPW = (P.size() + 63) / 64;
   T.grp.assign(NV, 0u);
   T.pf.assign(P.size() * NVW, 0ull);
+  T.pv.assign((size_t)NV * NPW, 0ull);
   for (int V = 0; V < NV; ++V) {
     T.grp[V] = (uint32_t)T.edges.size() | ((uint32_t)by_face[V].size() << 16);
     for (uint32_t te : by_face[V]) {
       T.edges.push_back(te);
-      for (uint32_t q : {te & 0xfffu, (te >> 12) & 0xfffu}) T.pf[q * NVW + V / 64] |= 1ull << (V % 64);
+      for (uint32_t q : {te & 0xfffu, (te >> 12) & 0xfffu}) {
+        T.pf[q * NVW + V / 64] |= 1ull << (V % 64);
+        T.pv[(size_t)V * NPW + q / 64] |= 1ull << (q % 64);
+      }
     }
   }
   return T;
@@ -1808,6 +1850,7 @@ struct SubArgs {
   int NE;
   const uint32_t *tgrp;
   const uint64_t *tpf;
+  const uint64_t *tpv;
   const VEnt *cvt;
   uint64_t cvt_mask;
 };
@@ -1837,7 +1880,8 @@ int launch_sub(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_
   const SubOut so = g.sub_out(a.cvt, a.cvt_mask);
 #define IP_SUB(PP)                                                                                                  \
   hipLaunchKernelGGL((subdivide_kernel<D, PP, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, ctx->stream,     \
-                     p->fine, p->coarse, a.LB, p->k, sig, list, n, a.tpts, a.NP, a.tedge, a.NE, a.tgrp, a.tpf, p->poly, \
+                     p->fine, p->coarse, a.LB, p->k, sig, list, n, a.tpts, a.NP, a.tedge, a.NE, a.tgrp, a.tpf, a.tpv,    \
+                     p->poly,                                                                                      \
                      fvt, fvt_mask, eval, pslot, prep, so, defer, ctx->ctr_dev)
   if (MODE == 3) {
     IP_SUB(1);
@@ -2280,7 +2324,7 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
     release(ctx, sig_tab);
     sig_tab = nullptr;
   }
-  DevTmp sig_hold(ctx), tpts_hold(ctx), tedge_hold(ctx), tgrp_hold(ctx), tpf_hold(ctx);
+  DevTmp sig_hold(ctx), tpts_hold(ctx), tedge_hold(ctx), tgrp_hold(ctx), tpf_hold(ctx), tpv_hold(ctx);
   sig_hold.p = sig_list;
   st.n_sigma = (int64_t)nsig;
   st.n_coarse_edges = (int64_t)nc;
@@ -2292,14 +2336,15 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   IP_TRY(tedge_hold.get(T.edges.size() * 4));
   IP_TRY(tgrp_hold.get(T.grp.size() * 4));
   IP_TRY(tpf_hold.get(T.pf.size() * 8));
+  IP_TRY(tpv_hold.get(T.pv.size() * 8));
   IP_TRY_HIP(ctx, hipMemcpyAsync(tpts_hold.p, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   IP_TRY_HIP(ctx,
              hipMemcpyAsync(tedge_hold.p, T.edges.data(), T.edges.size() * 4, hipMemcpyHostToDevice, ctx->stream));
   IP_TRY_HIP(ctx, hipMemcpyAsync(tgrp_hold.p, T.grp.data(), T.grp.size() * 4, hipMemcpyHostToDevice, ctx->stream));
   IP_TRY_HIP(ctx, hipMemcpyAsync(tpf_hold.p, T.pf.data(), T.pf.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  IP_TRY_HIP(ctx, hipMemcpyAsync(tpv_hold.p, T.pv.data(), T.pv.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   const SubArgs a{LB, tpts_hold.as<uint64_t>(), NP, tedge_hold.as<uint32_t>(), NE, tgrp_hold.as<uint32_t>(),
-                  tpf_hold.as<uint64_t>(),
-                  cvt, cvt_cap - 1};
+                  tpf_hold.as<uint64_t>(), tpv_hold.as<uint64_t>(), cvt, cvt_cap - 1};
   int rc;
   if (cert && p->poly.ok)
     rc = subdivide_fused<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, st, res);
