@@ -23,14 +23,15 @@ struct SceneDev {
   int32_t has_box;
   const double *joint_T;      // nj x 12
   const int32_t *joint_axis;  // nj
+  const int32_t *joint_pure;  // nj: 1 when the joint's rotation part is exactly the identity
   const int32_t *lsph_off;    // nj + 1
   const double *lsph;         // [cx cy cz r] per sphere, grouped by link
   const int32_t *lcap_off;    // nj + 1
   const double *lcap;         // [p0 p1 r pad] (8 doubles) per capsule, by link
   int32_t n_osph, n_obox, n_ocyl, pad;
   const double *osph;         // [cx cy cz r]
-  const double *obox;         // [T(12) l(3) pad] (16 doubles)
-  const double *ocyl;         // [T(12) rc h pad pad] (16 doubles)
+  const double *obox;         // [T(12) l(3) rb] (16 doubles), rb: radius of a ball about the centre holding the box
+  const double *ocyl;         // [T(12) rc h rb pad] (16 doubles), rb as for boxes
   const double *lbound;       // per link [cx cy cz R]: a ball in the link frame
                               // holding all of the link's geometry (R < 0: none)
   double eps;                 // margin of the culling test
@@ -92,27 +93,40 @@ __device__ __forceinline__ void compose(const double *A, const double *B, double
   }
 }
 
-__device__ __forceinline__ void rotation(int axis, double s, double c, double *R) {
+// One link of the forward kinematics, T <- T * J * R(axis, q), R the
+// rotation by q about axis 0, 1 or 2 (x, y, z): the same values as the full
+// 3x4 products compose(compose(T, J), R) with the products by the exact
+// zeros and ones of R and of an identity rotation part of J (pure) left out
+// (each left-out term adds an exact zero).
+__device__ __forceinline__ void fk_step(double *T, const double *J, bool pure, int axis, double s, double c) {
+  double A[12];
+  if (pure) {
 #pragma unroll
-  for (int i = 0; i < 12; ++i) R[i] = 0.0;
-  if (axis == 0) {
-    R[0] = 1.0;
-    R[5] = c;
-    R[6] = -s;
-    R[9] = s;
-    R[10] = c;
-  } else if (axis == 1) {
-    R[0] = c;
-    R[2] = s;
-    R[5] = 1.0;
-    R[8] = -s;
-    R[10] = c;
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) A[r * 4 + k] = T[r * 4 + k];
+      A[r * 4 + 3] = fma(T[r * 4 + 2], J[11], fma(T[r * 4 + 1], J[7], fma(T[r * 4 + 0], J[3], T[r * 4 + 3])));
+    }
   } else {
-    R[0] = c;
-    R[1] = -s;
-    R[4] = s;
-    R[5] = c;
-    R[10] = 1.0;
+    compose(T, J, A);
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double a0 = A[r * 4 + 0], a1 = A[r * 4 + 1], a2 = A[r * 4 + 2];
+    if (axis == 0) {
+      T[r * 4 + 0] = a0;
+      T[r * 4 + 1] = fma(a2, s, a1 * c);
+      T[r * 4 + 2] = fma(a2, c, -(a1 * s));
+    } else if (axis == 1) {
+      T[r * 4 + 0] = fma(a2, -s, a0 * c);
+      T[r * 4 + 1] = a1;
+      T[r * 4 + 2] = fma(a2, c, a0 * s);
+    } else {
+      T[r * 4 + 0] = fma(a1, s, a0 * c);
+      T[r * 4 + 1] = fma(a1, c, -(a0 * s));
+      T[r * 4 + 2] = a2;
+    }
+    T[r * 4 + 3] = A[r * 4 + 3];
   }
 }
 
@@ -206,7 +220,14 @@ __device__ __forceinline__ bool sphere_cyl(const double *c, double r, const doub
 // Culling: can a ball (centre c, radius R) reach obstacle b?  A false
 // answer proves that every sphere or capsule inside the ball misses the
 // obstacle by more than the margin eps, far beyond the rounding of the exact
-// predicates, so skipping their tests leaves every verdict unchanged.
+// predicates, so skipping their tests leaves every verdict unchanged.  Boxes
+// and cylinders are first tested against a ball holding them (centre x,
+// radius rb): farther than R + rb, the ball cannot reach them.
+__device__ __forceinline__ bool ball_near_ball(const double *c, double R, double x, double y, double z, double rb) {
+  const double rr = R + rb;
+  return !(sq3(c[0] - x, c[1] - y, c[2] - z) > rr * rr);
+}
+
 __device__ __forceinline__ bool ball_near_sphere(const double *c, double R, const double *o) {
   const double rr = R + o[3];
   return !(sq3(c[0] - o[0], c[1] - o[1], c[2] - o[2]) > rr * rr);
@@ -266,11 +287,9 @@ __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__
     bool hit = !valid;
     double T[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
     for (int li = 0; li < d; ++li) {
-      double sn_, cs_, A[12], Rm[12];
+      double sn_, cs_;
       sincos_own(q[(int64_t)li * ld + ii], &sn_, &cs_);
-      compose(T, S.joint_T + 12 * li, A);
-      rotation(S.joint_axis[li], sn_, cs_, Rm);
-      compose(A, Rm, T);
+      fk_step(T, S.joint_T + 12 * li, S.joint_pure[li] != 0, S.joint_axis[li], sn_, cs_);
       const double *lb = S.lbound + 4 * li;
       if (!(lb[3] >= 0.0)) continue;
       double cb[3];
@@ -285,10 +304,18 @@ __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__
         const int nbx = nbx_all - b0 < 0 ? 0 : (nbx_all - b0 < nb ? nbx_all - b0 : nb);
         for (int b = 0; b < nsb; ++b)
           near |= (uint64_t)ball_near_sphere(cb, Rb, S.osph + 4 * (b0 + b)) << b;
-        for (int b = nsb; b < nbx; ++b)
-          near |= (uint64_t)ball_near_box(cb, Rb, S.obox + 16 * (b0 + b - nsb_all)) << b;
-        for (int b = nbx; b < nb; ++b)
-          near |= (uint64_t)ball_near_cyl(cb, Rb, S.ocyl + 16 * (b0 + b - nbx_all)) << b;
+        for (int b = nsb; b < nbx; ++b) {
+          const double *B = S.obox + 16 * (b0 + b - nsb_all);
+          bool nr = ball_near_ball(cb, Rb, B[3], B[7], B[11], B[15]);
+          if (__ballot(nr)) nr = nr && ball_near_box(cb, Rb, B);
+          near |= (uint64_t)nr << b;
+        }
+        for (int b = nbx; b < nb; ++b) {
+          const double *Cy = S.ocyl + 16 * (b0 + b - nbx_all);
+          bool nr = ball_near_ball(cb, Rb, Cy[3], Cy[7], Cy[11], Cy[14]);
+          if (__ballot(nr)) nr = nr && ball_near_cyl(cb, Rb, Cy);
+          near |= (uint64_t)nr << b;
+        }
         if (hit) near = 0;
         const uint64_t any = wave_or64(near);
         if (!any) continue;
@@ -349,11 +376,9 @@ __global__ __launch_bounds__(256) void check_sphere_kernel(SceneDev S, int n_lsp
       while (li + 1 < S.nj && S.lsph_off[li + 1] <= a) ++li;
       double T[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
       for (int j = 0; j <= li; ++j) {
-        double sn_, cs_, A[12], Rm[12];
+        double sn_, cs_;
         sincos_own(q[(int64_t)j * ld + c], &sn_, &cs_);
-        compose(T, S.joint_T + 12 * j, A);
-        rotation(S.joint_axis[j], sn_, cs_, Rm);
-        compose(A, Rm, T);
+        fk_step(T, S.joint_T + 12 * j, S.joint_pure[j] != 0, S.joint_axis[j], sn_, cs_);
       }
       const double *sp = S.lsph + 4 * a;
       double cw[3];
@@ -521,10 +546,13 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   }
   std::vector<double> osph(4 * (size_t)sc->n_osph), obox(16 * (size_t)sc->n_obox),
       ocyl(16 * (size_t)sc->n_ocyl, 0.0);
+  // bounding-ball radii, rounded up (the culling margin covers the rest)
   for (int b = 0; b < sc->n_ocyl; ++b) {
     for (int j = 0; j < 12; ++j) ocyl[16 * b + j] = sc->ocyl_T[12 * b + j];
-    ocyl[16 * b + 12] = sc->ocyl_rh[2 * b];
-    ocyl[16 * b + 13] = sc->ocyl_rh[2 * b + 1];
+    const double rc = sc->ocyl_rh[2 * b], h = sc->ocyl_rh[2 * b + 1];
+    ocyl[16 * b + 12] = rc;
+    ocyl[16 * b + 13] = h;
+    ocyl[16 * b + 14] = std::sqrt(rc * rc + 0.25 * h * h) * (1.0 + 1e-12);
   }
   for (int b = 0; b < sc->n_osph; ++b) {
     for (int j = 0; j < 3; ++j) osph[4 * b + j] = sc->osph_c[3 * b + j];
@@ -533,7 +561,8 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   for (int b = 0; b < sc->n_obox; ++b) {
     for (int j = 0; j < 12; ++j) obox[16 * b + j] = sc->obox_T[12 * b + j];
     for (int j = 0; j < 3; ++j) obox[16 * b + 12 + j] = sc->obox_l[3 * b + j];
-    obox[16 * b + 15] = 0.0;
+    const double *l = sc->obox_l + 3 * b;
+    obox[16 * b + 15] = 0.5 * std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]) * (1.0 + 1e-12);
   }
   // per-link bounding balls (link frame): centre at the middle of the
   // geometry's extent, radius covering every sphere and capsule of the link
@@ -596,6 +625,13 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   size_t n_dbl = blob.size();
   std::vector<int32_t> ints;
   ints.insert(ints.end(), sc->joint_axis, sc->joint_axis + nj);
+  size_t o_jp = ints.size();
+  for (int i = 0; i < nj; ++i) {
+    const double *J = sc->joint_T + 12 * i;
+    const bool pure = J[0] == 1.0 && J[1] == 0.0 && J[2] == 0.0 && J[4] == 0.0 && J[5] == 1.0 && J[6] == 0.0 &&
+                      J[8] == 0.0 && J[9] == 0.0 && J[10] == 1.0;
+    ints.push_back(pure ? 1 : 0);
+  }
   size_t o_lso = ints.size();
   ints.insert(ints.end(), lsph_off.begin(), lsph_off.end());
   size_t o_lco = ints.size();
@@ -612,6 +648,7 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   out->has_box = sc->n_obox > 0;
   out->joint_T = db + o_jT;
   out->joint_axis = ib;
+  out->joint_pure = ib + o_jp;
   out->lsph_off = ib + o_lso;
   out->lsph = db + o_ls;
   out->lcap_off = ib + o_lco;
