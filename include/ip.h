@@ -194,7 +194,11 @@ void ip_problem_free(ip_problem *p);
 
 /* Trace (Sec. V-A locate + breadth-first search; Sec. V-B batches).
  * batch_budget_bytes bounds the per-batch device workspace in batch mode
- * (0 = library default); the traced set does not depend on it.
+ * (0 = library default); the traced set does not depend on it.  In the
+ * FP32-certified mode with a polynomial kernel a batch takes
+ * 12 + 16 ceil(2^(d+1) / 64) bytes per coarse simplex (a deferred-list entry,
+ * its tier-1 bound and two face masks); in the other modes the vertex table
+ * of the batch's template points sets the size.
  * precision: IP_FP64 or IP_FP32_CERTIFY.  flags: IP_REFINE(n) or 0.
  * The result holds the traced edges and their intersection points
  * p = x_a + t (x_b - x_a), t = f_a / (f_a - f_b), a the smaller endpoint.

@@ -1041,21 +1041,21 @@ __global__ void batch_points_kernel(LatDev L, const uint64_t *keys, uint64_t lo,
 // Active faces.  Whether this simplex takes the edges of face tau depends
 // only on the coarse trace (tau traced or not, this simplex canonical for
 // tau or not), not on f.  Both are bit masks over the 2^(d+1) vertex subsets
-// V, formed with scalar operations from two per-simplex facts: the traced
-// coarse edges (i, j) among its vertices (V is traced when it holds one:
-// the union over them of {V : i, j in V}), and the positions p where the
-// root sequence descends (V is canonical when it holds all of them: the
-// ascending-roots rule read position by position).  The wave takes the sign
-// of f only at the template points of active faces' edges, and tests only
-// their edges: the template edges are grouped by face, and the active groups
-// are laid end to end in a virtual index space [0, T) that the lanes walk 64
-// at a time (a bitmap of group starts maps a virtual index to its group).
+// V, formed from two per-simplex facts: the traced coarse edges (i, j) among
+// its vertices (V is traced when it holds one: the union over them of
+// {V : i, j in V}), and the positions p where the root sequence descends (V
+// is canonical when it holds all of them: the ascending-roots rule read
+// position by position).  The wave takes the sign of f only at the template
+// points of active faces' edges, and tests only the edges of active faces
+// whose points carry both signs: the template edges are grouped by face, and
+// those groups are laid end to end in a virtual index space [0, T) that the
+// lanes walk 64 at a time (a bitmap of group starts maps a virtual index to
+// its group).
 //
-// Preparation.  The traced edges among a simplex's vertices (D + 1 probes of
-// the coarse vertex table) and its tier-1 bound (the frame at its D + 1
-// vertices and one pass over the monomials) are computed beforehand by
-// sub_prep_kernel, one lane per coarse simplex, rather than on D + 1 of the
-// wave's 64 lanes.
+// Preparation.  The masks and the tier-1 bound of a simplex (D + 1 probes of
+// the coarse vertex table, the frame at its D + 1 vertices, one pass over
+// the monomials) are computed beforehand by sub_prep_kernel, one lane per
+// coarse simplex, rather than on D + 1 of the wave's 64 lanes.
 //
 // Sign codes.  The signs are kept in LDS as byte codes: 0 (f < 0), 1
 // (f >= 0), 2 (outside the box), 3 (neither certified tier settles the
@@ -1150,26 +1150,46 @@ struct SubOut {
   uint64_t dcap;      // capacity of out_d (appends past it are counted, not written)
 };
 
+// Bit b of word t set when vertex i belongs to the vertex subset 64 t + b.
+__host__ __device__ constexpr uint64_t vertex_pattern(int i, int t) {
+  return i == 0   ? 0xAAAAAAAAAAAAAAAAull
+         : i == 1 ? 0xCCCCCCCCCCCCCCCCull
+         : i == 2 ? 0xF0F0F0F0F0F0F0F0ull
+         : i == 3 ? 0xFF00FF00FF00FF00ull
+         : i == 4 ? 0xFFFF0000FFFF0000ull
+         : i == 5 ? 0xFFFFFFFF00000000ull
+                  : (((t >> (i - 6)) & 1) ? ~0ull : 0ull);
+}
+
 // What the subdivision of one coarse simplex takes from the coarse trace and
-// the frame: its tier-1 bound B1 and the traced coarse edges among its
-// vertices (byte i: bit j set when edge (i, j), i < j, is traced).
+// the frame: its tier-1 bound B1 and two masks over the 2^(D+1) vertex
+// subsets V of the simplex (bit V - 64 t of word t): A, the active faces,
+// and TR, the traced ones.
+template <int D>
 struct SubPrep {
+  static constexpr int NVW = ((1 << (D + 1)) + 63) / 64;
   double B1;
-  uint64_t rows;
+  uint64_t A[NVW], TR[NVW];
 };
 
-// One lane per coarse simplex sig[i], i < n (grid-stride).  Vertex i of the simplex is
-// v + 1_{w_0 .. w_{i-1}}; edge (i, j) has direction R = {w_i .. w_{j-1}}
-// from vertex i and is traced when bit R of that vertex's visited-edge mask
-// is set.  The bound: |x_j| is largest at a vertex (fine coordinates
-// k (v + 1_{w_0 .. w_{i-1}})), so with X_j the maximum over the vertices,
-// B1 = K32n sum_m |c_m| X^m + E0 covers every template point (BOUND false:
-// B1 = 0, the FP64 mode).
+// One lane per coarse simplex sig[i], i < n (grid-stride).  Vertex i of the
+// simplex is v + 1_{w_0 .. w_{i-1}}; edge (i, j) has direction
+// R = {w_i .. w_{j-1}} from vertex i and is traced when bit R of that
+// vertex's visited-edge mask is set.  Face V is traced when it holds a
+// traced edge (i, j): the union over them of {V : i, j in V}.  It is
+// canonical when it holds every position p whose root is below the root
+// before it, cyclically (roots w_0 .. w_{D-1}, D; p = 0 always): the
+// ascending-roots rule read position by position.  Active = not traced, or
+// canonical; V = 0 never.  The bound: |x_j| is largest at a vertex (fine
+// coordinates k (v + 1_{w_0 .. w_{i-1}})), so with X_j the maximum over the
+// vertices, B1 = K32n sum_m |c_m| X^m + E0 covers every template point
+// (BOUND false: B1 = 0, the FP64 mode).
 template <int D, bool BOUND>
 __global__ __launch_bounds__(kBlock) void sub_prep_kernel(LatDev Lf, LatDev Lc, int LB, int k,
                                                           const uint64_t *__restrict__ sig, uint64_t n,
                                                           const VEnt *__restrict__ cvt, uint64_t cvt_mask, PolyDev Q,
-                                                          SubPrep *__restrict__ out) {
+                                                          SubPrep<D> *__restrict__ out) {
+  constexpr int NV = 1 << (D + 1), NVW = SubPrep<D>::NVW;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     int32_t v[D], w[D];
     sig_unpack<D>(Lc, sig[i], LB, v, w);
@@ -1205,7 +1225,27 @@ __global__ __launch_bounds__(kBlock) void sub_prep_kernel(LatDev Lf, LatDev Lc, 
         if ((word >> (R & 63u)) & 1ull) rows |= 1ull << (8 * vi + j);
       }
     }
-    double B1 = 0.0;
+    SubPrep<D> r;
+    uint32_t desc = 1u;
+#pragma unroll
+    for (int q = 1; q < D; ++q) desc |= w[q] < w[q - 1] ? 1u << q : 0u;
+#pragma unroll
+    for (int t = 0; t < NVW; ++t) {
+      uint64_t tr = 0, cn = ~0ull;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a + 1; b <= D; ++b)
+          if ((rows >> (8 * a + b)) & 1ull) tr |= vertex_pattern(a, t) & vertex_pattern(b, t);
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+        if ((desc >> q) & 1u) cn &= vertex_pattern(q, t);
+      uint64_t valid = NV >= 64 ? ~0ull : (1ull << (NV & 63)) - 1ull;
+      if (t == 0) valid &= ~1ull;
+      r.TR[t] = tr & valid;
+      r.A[t] = (~tr | cn) & valid;
+    }
+    r.B1 = 0.0;
     if (BOUND) {
 #pragma unroll
       for (int j = 0; j < D; ++j) X[j] = X[j] * (1.0 + 1e-12) + 1e-300;
@@ -1222,23 +1262,16 @@ __global__ __launch_bounds__(kBlock) void sub_prep_kernel(LatDev Lf, LatDev Lc, 
         }
         t += term;
       }
-      B1 = Q.K32n * (t * (1.0 + 1e-12)) + Q.E0;
+      r.B1 = Q.K32n * (t * (1.0 + 1e-12)) + Q.E0;
     }
-    out[i] = SubPrep{B1, rows};
+    out[i] = r;
   }
 }
 
-// Bit b of word t set when vertex i belongs to the vertex subset 64 t + b.
-__device__ __forceinline__ uint64_t vertex_pattern(int i, int t) {
-  switch (i) {
-    case 0: return 0xAAAAAAAAAAAAAAAAull;
-    case 1: return 0xCCCCCCCCCCCCCCCCull;
-    case 2: return 0xF0F0F0F0F0F0F0F0ull;
-    case 3: return 0xFF00FF00FF00FF00ull;
-    case 4: return 0xFFFF0000FFFF0000ull;
-    case 5: return 0xFFFFFFFF00000000ull;
-    default: return ((t >> (i - 6)) & 1) ? ~0ull : 0ull;
-  }
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int j) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Four waves per SIMD (the LDS allows four blocks per CU): the register cap
@@ -1254,7 +1287,7 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
                                                            const uint64_t *__restrict__ tpv, PolyDev Q,
                                                            VEnt *fvt, uint64_t fvt_mask, uint32_t *eval_list,
                                                            const uint32_t *__restrict__ pslot,
-                                                           const SubPrep *__restrict__ prep, SubOut so,
+                                                           const SubPrep<D> *__restrict__ prep, SubOut so,
                                                            uint32_t *defer, Counters *ctr) {
   constexpr int NV = 1 << (D + 1);        // vertex subsets of a coarse simplex
   constexpr int NVW = (NV + 63) / 64;     // 64-bit words per face mask
@@ -1321,42 +1354,36 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
   uint32_t hits = 0, shits = 0, n64 = 0, npts = 0, nuns = 0;
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const uint64_t n_waves = ((uint64_t)gridDim.x * kBlock) >> 6;
+  // MODE 0 and 3 walk sig[0 .. n); MODE 1 and 2 walk the deferred list.
+  // Each lane holds the index, key and preparation record of one of the
+  // wave's next 64 simplices (loaded together, so their latency is paid once
+  // per 64); the wave reads the current one out of lane jn.
+  uint32_t st_s = 0;
+  uint64_t st_key = 0;
+  SubPrep<D> st_p = {};
+  int jn = 64;
   for (uint64_t it = wave; it < n; it += n_waves) {
-    // MODE 0 and 3 walk sig[0 .. n); MODE 1 and 2 walk the deferred list
-    const uint64_t s = (MODE == 0 || MODE == 3) ? it : (uint64_t)list[it];
+    if (jn == 64) {
+      const uint64_t itj = it + (uint64_t)lane * n_waves;
+      if (itj < n) {
+        st_s = (MODE == 0 || MODE == 3) ? (uint32_t)itj : list[itj];
+        st_key = sig[st_s];
+        st_p = prep[st_s];
+      }
+      jn = 0;
+    }
+    const uint64_t s = (uint32_t)__builtin_amdgcn_readlane((int)st_s, jn);
     int32_t v[D], w[D], winv[D];
-    sig_unpack<D>(Lc, sig[s], LB, v, w);
+    sig_unpack<D>(Lc, readlane64(st_key, jn), LB, v, w);
     perm_inverse<D>(w, winv);
-    const SubPrep pr = prep[s];
-    const double B1 = pr.B1;
-    // face masks (scalar): traced = some traced coarse edge (i, j) inside V;
-    // canonical = V holds every position p whose root is below the root
-    // before it, cyclically (roots w_0 .. w_{D-1}, D); active = not traced,
-    // or canonical; V = 0 and V >= 2^(D+1) never
-    uint32_t desc = 1u;  // p = 0: w_0 < D
-#pragma unroll
-    for (int q = 1; q < D; ++q) desc |= w[q] < w[q - 1] ? 1u << q : 0u;
+    const double B1 = __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(st_p.B1), jn));
     uint64_t A[NVW], TR[NVW];
 #pragma unroll
     for (int t = 0; t < NVW; ++t) {
-      uint64_t tr = 0, cn = ~0ull;
-      for (int i = 0; i < D; ++i) {
-        uint32_t r = (uint32_t)(pr.rows >> (8 * i)) & 0xffu;
-        const uint64_t si = vertex_pattern(i, t);
-        while (r) {
-          const int j = __builtin_ctz(r);
-          r &= r - 1u;
-          tr |= si & vertex_pattern(j, t);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < D; ++q)
-        if ((desc >> q) & 1u) cn &= vertex_pattern(q, t);
-      uint64_t valid = NV >= 64 ? ~0ull : (1ull << (NV & 63)) - 1ull;
-      if (t == 0) valid &= ~1ull;
-      TR[t] = tr & valid;
-      A[t] = (~tr | cn) & valid;
+      A[t] = readlane64(st_p.A[t], jn);
+      TR[t] = readlane64(st_p.TR[t], jn);
     }
+    ++jn;
     // active template points: an end of an edge of an active face; every
     // code starts at 2
     int NPA = 0;
@@ -1858,7 +1885,7 @@ struct SubArgs {
 // The preparation of coarse simplices sig[0 .. n) (B1 only with `bound`).
 template <int D>
 int launch_prep(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig, uint64_t n, bool bound,
-                SubPrep *prep) {
+                SubPrep<D> *prep) {
   if (n == 0) return IP_OK;
   if (bound)
     hipLaunchKernelGGL((sub_prep_kernel<D, true>), dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, p->fine, p->coarse,
@@ -1873,7 +1900,7 @@ int launch_prep(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64
 template <int D, int MODE>
 int launch_sub(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig, const uint32_t *list,
                uint64_t n, VEnt *fvt, uint64_t fvt_mask, uint32_t *eval, const BatchSink &g, uint32_t *defer,
-               const SubPrep *prep, const uint32_t *pslot = nullptr) {
+               const SubPrep<D> *prep, const uint32_t *pslot = nullptr) {
   if (n == 0) return IP_OK;
   const size_t lds = sub_layout(a.NP, a.NE, MODE == 3 ? 0 : p->poly.M, 1 << (D + 1)).total;
   const uint64_t blocks = std::min<uint64_t>((n + kWaves - 1) / kWaves, kSubGrid);
@@ -1984,14 +2011,14 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
                     uint64_t nc, uint64_t budget, ip_stats &st, ip_cells *res) {
   const int NP = a.NP, NE = a.NE;
   if (budget == 0) budget = 4ull << 30;
-  uint64_t B = std::min<uint64_t>(budget / (4 + sizeof(SubPrep)), 0xffffffffull);
+  uint64_t B = std::min<uint64_t>(budget / (4 + sizeof(SubPrep<D>)), 0xffffffffull);
   if (B == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
   if (B > nsig) B = nsig ? nsig : 1;
   IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * 4));
   uint32_t *defer = (uint32_t *)ctx->vt_aux.p;
   DevTmp prep_hold(ctx);
-  IP_TRY(prep_hold.get(B * sizeof(SubPrep)));
-  SubPrep *prep = prep_hold.as<SubPrep>();
+  IP_TRY(prep_hold.get(B * sizeof(SubPrep<D>)));
+  SubPrep<D> *prep = prep_hold.as<SubPrep<D>>();
   BatchSink g(ctx);
   IP_TRY(init_sink<D>(g, nc, p->k));
   Counters *c = ctx->ctr_host;
@@ -2113,7 +2140,7 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   if (budget == 0) budget = 4ull << 30;
   uint64_t vcap_b = 0;
   for (uint64_t cc = 1024; cc <= (1ull << 32); cc <<= 1)
-    if (cc * slot_bytes + (cc / 2) * 4 + cc / (2 * (uint64_t)NP) * sizeof(SubPrep) <= budget &&
+    if (cc * slot_bytes + (cc / 2) * 4 + cc / (2 * (uint64_t)NP) * sizeof(SubPrep<D>) <= budget &&
         cc >= 2 * (uint64_t)NP)
       vcap_b = cc;
   if (vcap_b == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
@@ -2141,8 +2168,8 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   }
   uint32_t *pslot = (uint32_t *)ctx->vt_aux.p;
   DevTmp prep_hold(ctx);
-  IP_TRY(prep_hold.get(B * sizeof(SubPrep)));
-  SubPrep *prep = prep_hold.as<SubPrep>();
+  IP_TRY(prep_hold.get(B * sizeof(SubPrep<D>)));
+  SubPrep<D> *prep = prep_hold.as<SubPrep<D>>();
   BatchSink g(ctx);
   IP_TRY(init_sink<D>(g, nc, k));
   Counters *c = ctx->ctr_host;

@@ -91,9 +91,9 @@ def test_fp32_batch_budget_invariance(ip, ctx):
     wl = make()
     wl.k = k
     big = trace(ip, ctx, wl, precision=ip.IP_FP32_CERTIFY)
-    # 20 bytes of workspace per coarse simplex (deferred-list entry and
-    # preparation record): 1024 simplices per batch
-    small = trace(ip, ctx, wl, precision=ip.IP_FP32_CERTIFY, budget=20 * 1024)
+    # 12 + 16 bytes of workspace per coarse simplex at d = 4 (deferred-list
+    # entry, tier-1 bound, two one-word face masks): 1024 simplices per batch
+    small = trace(ip, ctx, wl, precision=ip.IP_FP32_CERTIFY, budget=28 * 1024)
     ns = big[3]["n_sigma"]
     assert small[3]["n_batches"] == (ns + 1023) // 1024 > 1
     assert np.array_equal(big[0], small[0]) and np.array_equal(big[1], small[1])

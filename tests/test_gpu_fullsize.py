@@ -92,9 +92,9 @@ def test_fullsize_fp32_and_fp64_trace_the_same_set(summaries):
 def test_fullsize_budget_split_is_invisible(ip, ctx, full, summaries):
     wl, prob = full
     n32, d32, s32 = summaries["fp32"]
-    # 20 bytes of workspace per coarse simplex in the fused path (its
-    # deferred-list entry and its preparation record): 5 batches
-    budget = 20 * (s32["n_sigma"] // 5 + 1)
+    # 12 + 16 * 2 bytes of workspace per coarse simplex in the fused path at
+    # d = 6 (deferred-list entry, tier-1 bound, two face masks): 5 batches
+    budget = 44 * (s32["n_sigma"] // 5 + 1)
     c = ip.Cells(ctx, prob, budget=budget, precision=ip.IP_FP32_CERTIFY)
     try:
         st = c.stats()
