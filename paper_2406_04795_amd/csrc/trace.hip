@@ -1084,7 +1084,7 @@ constexpr int kEdgeStage = 128;
 // the list of the active groups, the edge stage, the active point list and
 // the sign codes.
 struct SubLayout {
-  uint32_t stage_s, stage_d, lmat, lcd, lpts, lpf, lpv, sbm, lc, est, ledge, lgrp, lmask, agl, plist, code, total;
+  uint32_t lmat, lc, stage_s, stage_d, lpts, lpf, lpv, sbm, est, ledge, lgrp, lmask, agl, plist, code, total;
 };
 
 __host__ __device__ inline uint32_t sub_take(uint32_t &o, size_t bytes) {
@@ -1095,19 +1095,21 @@ __host__ __device__ inline uint32_t sub_take(uint32_t &o, size_t bytes) {
 
 // NP template points, NE template edges, M monomials (0: no coefficients),
 // NV = 2^(d+1) vertex subsets.
+// The frame and the FP32 coefficients come first, at fixed offsets (0 and
+// kSubLc), so that the evaluation reads them with immediate offsets.
+constexpr uint32_t kSubLc = 88 * 8;
 __host__ __device__ inline SubLayout sub_layout(int NP, int NE, int M, int NV) {
   const int NVW = (NV + 63) / 64, NPW = (NP + 63) / 64, SBW = (NE + 63) / 64;
   SubLayout L;
   uint32_t o = 0;
+  L.lmat = sub_take(o, 88 * 8);
+  L.lc = sub_take(o, (size_t)M * 4);
   L.stage_s = sub_take(o, (size_t)kWaves * kSubStage * 8);
   L.stage_d = sub_take(o, (size_t)kWaves * kSubStage * 8);
-  L.lmat = sub_take(o, 88 * 8);
-  L.lcd = sub_take(o, (size_t)M * 8);
   L.lpts = sub_take(o, (size_t)NP * 8);
   L.lpf = sub_take(o, (size_t)NP * NVW * 8);
   L.lpv = sub_take(o, (size_t)NV * NPW * 8);
   L.sbm = sub_take(o, (size_t)kWaves * SBW * 8);
-  L.lc = sub_take(o, (size_t)M * 4);
   L.est = sub_take(o, (size_t)kWaves * kEdgeStage * 4);
   L.ledge = sub_take(o, (size_t)NE * 4);
   L.lgrp = sub_take(o, (size_t)NV * 4);
@@ -1136,7 +1138,7 @@ template <int D>
 __device__ __forceinline__ bool in_box_m(const double *M, const double *x) {
   bool ok = true;
 #pragma unroll
-  for (int j = 0; j < D; ++j) ok = ok && (x[j] >= M[72 + j]) && (x[j] <= M[80 + j]);
+  for (int j = 0; j < D; ++j) ok = ok & (x[j] >= M[72 + j]) & (x[j] <= M[80 + j]);
   return ok;
 }
 
@@ -1303,10 +1305,10 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
   const SubLayout Ly = sub_layout(NP, NE, M, NV);
   uint64_t *stage_s = (uint64_t *)(smem + Ly.stage_s) + (size_t)wib * kSubStage;
   uint64_t *stage_d = (uint64_t *)(smem + Ly.stage_d) + (size_t)wib * kSubStage;
-  // fine frame in LDS: read at wave-uniform addresses, it stays out of the
-  // scalar registers
-  double *lmat = (double *)(smem + Ly.lmat);
-  double *lcd = (double *)(smem + Ly.lcd);
+  // fine frame and FP32 coefficients in LDS at fixed offsets: read at
+  // wave-uniform addresses, they stay out of the scalar registers
+  double *lmat = (double *)smem;
+  float *lc = (float *)(smem + kSubLc);
   uint64_t *lpts = (uint64_t *)(smem + Ly.lpts);
   uint64_t *lpf = (uint64_t *)(smem + Ly.lpf);
   uint64_t *lpv = (uint64_t *)(smem + Ly.lpv);
@@ -1314,7 +1316,6 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
   // per wave: the points with f < 0 and those with f >= 0
   uint64_t *mneg = (uint64_t *)(smem + Ly.lmask) + (size_t)wib * 2 * NPW;
   uint64_t *mpos = mneg + NPW;
-  float *lc = (float *)(smem + Ly.lc);
   uint32_t *est = (uint32_t *)(smem + Ly.est) + (size_t)wib * kEdgeStage;
   uint32_t *ledge = (uint32_t *)(smem + Ly.ledge);
   uint32_t *lgrp = (uint32_t *)(smem + Ly.lgrp);
@@ -1332,15 +1333,9 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
     lmat[72 + threadIdx.x] = Lf.lo[threadIdx.x];
     lmat[80 + threadIdx.x] = Lf.hi[threadIdx.x];
   }
-  // the monomial coefficients, read by every lane at the same index, from
-  // LDS (kept out of the vector registers)
-  for (int i = threadIdx.x; i < M; i += kBlock) {
-    lcd[i] = Q.cd[i];
-    lc[i] = Q.c[i];
-  }
-  PolyDev Ql = Q;
-  Ql.c = lc;
-  Ql.cd = lcd;
+  // the FP32 monomial coefficients, read by every lane at the same index,
+  // from LDS (kept out of the vector registers)
+  for (int i = threadIdx.x; i < M; i += kBlock) lc[i] = Q.c[i];
   for (int i = threadIdx.x; i < NE; i += kBlock) ledge[i] = tedge[i];
   for (int i = threadIdx.x; i < NV; i += kBlock) lgrp[i] = tgrp[i];
   for (int i = threadIdx.x; i < NV * NPW; i += kBlock) lpv[i] = tpv[i];
@@ -1414,16 +1409,19 @@ __global__ __launch_bounds__(kBlock, 4) void subdivide_kernel(LatDev Lf, LatDev 
         } else {
           int32_t y[D];
           template_point_inv<D>(v, winv, k, lpts[pt], y);
-          // an opaque zero offset keeps the frame reads in the loop (hoisted,
-          // the 36 matrix entries would pin 72 vector registers)
+          // an opaque zero base keeps the frame and coefficient reads in the
+          // loop (hoisted, the 36 matrix entries alone would pin 72 vector
+          // registers), each at an immediate offset from it
           int z = 0;
-          asm volatile("" : "+s"(z));
+          asm volatile("" : "+v"(z));
           const double *Mz = lmat + z;
           double x[D];
           lat_coords_m<D>(Mz, y, x);
           if (in_box_m<D>(Mz, x)) {
             double fv;
-            const int tier = cert_eval_region<D, P>(Ql, x, B1, &fv);
+            PolyDev Qz = Q;
+            Qz.c = lc + z;
+            const int tier = cert_eval_region<D, P>(Qz, x, B1, &fv);
             if (MODE == 0) ++npts;
             if (tier < 3) {
               c = fv < 0.0 ? 0u : 1u;
