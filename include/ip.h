@@ -40,7 +40,11 @@ enum {
   IP_FP64 = 0,          /* every f evaluation in FP64, canonical order */
   IP_FP32_CERTIFY = 1   /* FP32 evaluation with an error bound; vertices whose
                            sign the bound cannot settle are re-evaluated in
-                           FP64, so the traced set equals the FP64 one */
+                           FP64, so the traced set equals the FP64 one.
+                           ip_trace of an RBF manifold evaluates in FP64
+                           in this mode too: the FP32 bound of a sum of
+                           exponentials settles signs but not points, so
+                           every traced vertex would need FP64 anyway */
 };
 
 typedef struct ip_ctx ip_ctx;

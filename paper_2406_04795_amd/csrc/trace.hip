@@ -338,12 +338,19 @@ __device__ __forceinline__ bool edge_point(const LatDev &L, const PolyDev &Q, co
 }
 
 // Record an edge whose point must be recomputed from FP64 values: its index
-// goes to redo, the ends that hold FP32 values go to fb.
+// goes to redo, the ends that hold FP32 values go to fb, each vertex once
+// (the first edge to set its bit in the queued-slot bitmap qb lists it).
+__device__ __forceinline__ void queue_fp64(uint64_t slot, const float *vb, uint32_t *fb, uint32_t *qb, Counters *ctr) {
+  if (!(vb[slot] >= 0.0f)) return;
+  const uint32_t bit = 1u << (slot & 31u);
+  if (atomicOr(qb + (slot >> 5), bit) & bit) return;
+  fb[atomicAdd(&ctr->n_fb, 1ull)] = (uint32_t)slot;
+}
 __device__ __forceinline__ void need_fp64(uint64_t i, uint64_t sa, uint64_t sb, const float *vb, uint64_t *redo,
-                                          uint32_t *fb, Counters *ctr) {
+                                          uint32_t *fb, uint32_t *qb, Counters *ctr) {
   redo[atomicAdd(&ctr->n_aux, 1ull)] = i;
-  if (vb[sa] >= 0.0f) fb[atomicAdd(&ctr->n_fb, 1ull)] = (uint32_t)sa;
-  if (vb[sb] >= 0.0f) fb[atomicAdd(&ctr->n_fb, 1ull)] = (uint32_t)sb;
+  queue_fp64(sa, vb, fb, qb, ctr);
+  queue_fp64(sb, vb, fb, qb, ctr);
 }
 
 // Points of the traced edges, f read from the slots carried by the edges.
@@ -352,7 +359,7 @@ __device__ __forceinline__ void need_fp64(uint64_t i, uint64_t sa, uint64_t sb, 
 template <int D, bool REDO>
 __global__ void points_kernel(LatDev L, const OutRec *out, uint64_t n, const VEnt *vt, uint64_t *keys, double *pts,
                               int64_t ld, bool cert, const float *vb, PolyDev Q, uint64_t *redo, uint32_t *fb,
-                              Counters *ctr) {
+                              uint32_t *qb, Counters *ctr) {
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t i = REDO ? redo[q] : q;
     const OutRec o = out[i];
@@ -369,7 +376,7 @@ __global__ void points_kernel(LatDev L, const OutRec *out, uint64_t n, const VEn
                                   cert ? vb[sb] : -1.0f, p);
 #pragma unroll
     for (int j = 0; j < D; ++j) pts[(int64_t)j * ld + (int64_t)i] = p[j];
-    if (!ok) need_fp64(i, sa, sb, vb, redo, fb, ctr);
+    if (!ok) need_fp64(i, sa, sb, vb, redo, fb, qb, ctr);
   }
 }
 
@@ -2388,18 +2395,25 @@ template <int D>
 int direct_points(Run &s, uint64_t n, uint64_t *keys, double *pts, ip_stats &st) {
   ip_ctx *ctx = s.ctx;
   uint64_t *redo = nullptr;
+  DevTmp qb_hold(ctx);
+  uint32_t *qb = nullptr;
   if (s.cert) {
     IP_TRY(ip_ensure(ctx, ctx->scratch, n * 8));
     IP_TRY(ip_ensure(ctx, s.tb->fb, (2 * n + 64) * 4));
     s.fb = (uint32_t *)s.tb->fb.p;
     redo = (uint64_t *)ctx->scratch.p;
+    // queued-slot bitmap over the vertex table, cleared
+    const uint64_t qwords = (s.vt_cap + 63) / 64;
+    IP_TRY(qb_hold.get(qwords * 8));
+    IP_TRY(fill(ctx, qb_hold.p, qwords, 0ull));
+    qb = qb_hold.as<uint32_t>();
     IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
     IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_fb));
   }
   Timer tp;
   IP_TRY(tp.start(ctx, &st.ms_points));
   hipLaunchKernelGGL((points_kernel<D, false>), dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, s.L, s.out, n, s.vt,
-                     keys, pts, (int64_t)n, s.cert, (const float *)s.vb, s.p->poly, redo, s.fb, ctx->ctr_dev);
+                     keys, pts, (int64_t)n, s.cert, (const float *)s.vb, s.p->poly, redo, s.fb, qb, ctx->ctr_dev);
   IP_TRY_HIP(ctx, hipGetLastError());
   IP_TRY(tp.stop(ctx));
   if (s.cert) {
@@ -2410,7 +2424,7 @@ int direct_points(Run &s, uint64_t n, uint64_t *keys, double *pts, ip_stats &st)
       IP_TRY(launch_set_vb(ctx, s.fb, nfb, s.vb, -1.0f));
       hipLaunchKernelGGL((points_kernel<D, true>), dim3(grid_for(nredo)), dim3(kBlock), 0, ctx->stream, s.L, s.out,
                          nredo, s.vt, keys, pts, (int64_t)n, true, (const float *)s.vb, s.p->poly, redo, s.fb,
-                         ctx->ctr_dev);
+                         qb, ctx->ctr_dev);
       IP_TRY_HIP(ctx, hipGetLastError());
       s.n_fallback += (int64_t)nfb;
     }
@@ -2421,7 +2435,11 @@ int direct_points(Run &s, uint64_t n, uint64_t *keys, double *pts, ip_stats &st)
 
 template <int D>
 int trace_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, ip_cells *res) {
-  const bool cert = prec == IP_FP32_CERTIFY && ip_has_fp32_form(p);
+  // RBF manifolds trace in canonical FP64 in either mode: the FP32 tier's
+  // bound, loose through the cancellation in the sum of exponentials, settles
+  // signs but cannot place the intersection points, so every traced vertex
+  // would need its FP64 value as well (ip_feval keeps the FP32 tier)
+  const bool cert = prec == IP_FP32_CERTIFY && p->f.kernel == IP_KERNEL_POLY && ip_has_fp32_form(p);
   if (p->k != 1) return trace_batch<D>(ctx, p, budget, cert, res);
   Run s;
   s.ctx = ctx;
