@@ -34,6 +34,8 @@ struct SceneDev {
   const double *ocyl;         // [T(12) rc h rb pad] (16 doubles), rb as for boxes
   const double *lbound;       // per link [cx cy cz R]: a ball in the link frame
                               // holding all of the link's geometry (R < 0: none)
+  const double *cull;         // per obstacle (spheres, boxes, cylinders) [cx cy cz rb]: a
+                              // ball holding it; padded to a multiple of 4 with far balls
   double eps;                 // margin of the culling test
 };
 
@@ -272,7 +274,7 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
 // and the exact predicates only for those pairs.  Loops run over the scene
 // uniformly across the wave, so the scene is read with scalar loads; the
 // wave stops early once every lane has a hit.
-__global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__restrict__ q, int64_t n, int64_t ld,
+__global__ __launch_bounds__(256, 4) void check_kernel(SceneDev S, const double *__restrict__ q, int64_t n, int64_t ld,
                                                     uint8_t *__restrict__ verdict) {
   const int d = S.nj;
   const int nobs = S.n_osph + S.n_obox + S.n_ocyl;
@@ -297,27 +299,30 @@ __global__ __launch_bounds__(256) void check_kernel(SceneDev S, const double *__
       const double Rb = lb[3] + S.eps;
       for (int b0 = 0; b0 < nobs; b0 += 64) {
         const int nb = nobs - b0 < 64 ? nobs - b0 : 64;
-        // spheres, then boxes, then cylinders: uniform loops, no
-        // per-obstacle branch
+        // every obstacle's ball, four at a time from one contiguous array
+        // (one wave-uniform load of 16 doubles per group); then the boxes
+        // and cylinders that some lane's ball reaches against their exact
+        // distance
         uint64_t near = 0;
         const int nsb = nsb_all - b0 < 0 ? 0 : (nsb_all - b0 < nb ? nsb_all - b0 : nb);
         const int nbx = nbx_all - b0 < 0 ? 0 : (nbx_all - b0 < nb ? nbx_all - b0 : nb);
-        for (int b = 0; b < nsb; ++b)
-          near |= (uint64_t)ball_near_sphere(cb, Rb, S.osph + 4 * (b0 + b)) << b;
-        for (int b = nsb; b < nbx; ++b) {
-          const double *B = S.obox + 16 * (b0 + b - nsb_all);
-          bool nr = ball_near_ball(cb, Rb, B[3], B[7], B[11], B[15]);
-          if (__ballot(nr)) nr = nr && ball_near_box(cb, Rb, B);
-          near |= (uint64_t)nr << b;
+        for (int b = 0; b < nb; b += 4) {
+          const double *cl = S.cull + 4 * (b0 + b);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            near |= (uint64_t)ball_near_ball(cb, Rb, cl[4 * u], cl[4 * u + 1], cl[4 * u + 2], cl[4 * u + 3]) << (b + u);
         }
-        for (int b = nbx; b < nb; ++b) {
-          const double *Cy = S.ocyl + 16 * (b0 + b - nbx_all);
-          bool nr = ball_near_ball(cb, Rb, Cy[3], Cy[7], Cy[11], Cy[14]);
-          if (__ballot(nr)) nr = nr && ball_near_cyl(cb, Rb, Cy);
-          near |= (uint64_t)nr << b;
-        }
+        near &= nb == 64 ? ~0ull : (1ull << nb) - 1ull;
         if (hit) near = 0;
-        const uint64_t any = wave_or64(near);
+        uint64_t any = wave_or64(near);
+        const uint64_t sph = nsb >= 64 ? ~0ull : (1ull << nsb) - 1ull;
+        for (uint64_t hard = any & ~sph; hard; hard &= hard - 1) {
+          const int b = __ffsll((long long)hard) - 1;
+          const bool nr = b < nbx ? ball_near_box(cb, Rb, S.obox + 16 * (b0 + b - nsb_all))
+                                  : ball_near_cyl(cb, Rb, S.ocyl + 16 * (b0 + b - nbx_all));
+          if (!nr) near &= ~(1ull << b);
+          if (!__ballot((near >> b) & 1ull)) any &= ~(1ull << b);
+        }
         if (!any) continue;
         for (int a = S.lsph_off[li]; a < S.lsph_off[li + 1]; ++a) {
           const double *sp = S.lsph + 4 * a;
@@ -564,6 +569,27 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
     const double *l = sc->obox_l + 3 * b;
     obox[16 * b + 15] = 0.5 * std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]) * (1.0 + 1e-12);
   }
+  // the obstacles' balls in one array (spheres, boxes, cylinders), padded to
+  // a multiple of 4 with balls too far away to reach (centre 1e150, radius 0)
+  const int nobs = sc->n_osph + sc->n_obox + sc->n_ocyl;
+  std::vector<double> cull(4 * (size_t)((nobs + 3) / 4 * 4), 0.0);
+  for (int b = nobs; b < (nobs + 3) / 4 * 4; ++b) cull[4 * b] = cull[4 * b + 1] = cull[4 * b + 2] = 1e150;
+  for (int b = 0; b < sc->n_osph; ++b)
+    for (int j = 0; j < 4; ++j) cull[4 * b + j] = osph[4 * b + j];
+  for (int b = 0; b < sc->n_obox; ++b) {
+    double *c = &cull[4 * (sc->n_osph + b)];
+    c[0] = obox[16 * b + 3];
+    c[1] = obox[16 * b + 7];
+    c[2] = obox[16 * b + 11];
+    c[3] = obox[16 * b + 15];
+  }
+  for (int b = 0; b < sc->n_ocyl; ++b) {
+    double *c = &cull[4 * (sc->n_osph + sc->n_obox + b)];
+    c[0] = ocyl[16 * b + 3];
+    c[1] = ocyl[16 * b + 7];
+    c[2] = ocyl[16 * b + 11];
+    c[3] = ocyl[16 * b + 14];
+  }
   // per-link bounding balls (link frame): centre at the middle of the
   // geometry's extent, radius covering every sphere and capsule of the link
   std::vector<double> lbound(4 * (size_t)nj, 0.0);
@@ -622,6 +648,7 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   size_t o_ob = put(obox.data(), obox.size());
   size_t o_oc = put(ocyl.data(), ocyl.size());
   size_t o_lb = put(lbound.data(), lbound.size());
+  size_t o_cl = put(cull.data(), cull.size());
   size_t n_dbl = blob.size();
   std::vector<int32_t> ints;
   ints.insert(ints.end(), sc->joint_axis, sc->joint_axis + nj);
@@ -661,6 +688,7 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   out->osph = db + o_os;
   out->obox = db + o_ob;
   out->lbound = db + o_lb;
+  out->cull = db + o_cl;
   // the geometry is summed over at most a few dozen terms of size `scale`
   // (reach times the chain length): rounding stays below 1e-13 * scale
   out->eps = 1e-9 * scale * (double)(nj + 1);
