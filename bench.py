@@ -352,8 +352,9 @@ def cfree_leg(ip, wl, prec, budget, n_free, steps=3):
 
 
 def extra_legs(ip, wls, main_wl):
-    """The other workloads of the suite, one line each: the d=5 arm (C2), the
-    precision stress at its scale (C5, with its FP64 fallback rate), an
+    """The other workloads of the suite, one line each: the d=3 planar arm
+    (C1), the d=5 arm (C2), the precision stress at its scale (C5, with its
+    FP64 fallback rate), an
     RBF-kernel manifold, the iterative intersection on the benchmark
     workload, and the seed search on the benchmark's f."""
     import torch
@@ -461,7 +462,7 @@ def main():
     extras = {}
     if args.legs:
         from paper_2406_04795_amd import inputs as I
-        extras = {"c2_d5": I.config_c2(eps=3e-4), "c5_stress_d5": I.config_c5(),
+        extras = {"c1_d3": I.config_c1(), "c2_d5": I.config_c2(eps=3e-4), "c5_stress_d5": I.config_c5(),
                   "rbf_d5": I.rbf_case(5, 500, 0.15, 0.1, seed=1, n_seeds=4)}
     reqs = []
     if args.serve:

@@ -218,6 +218,9 @@ void ip_problem_free(ip_problem *p);
 int ip_trace(ip_ctx *ctx, const ip_problem *p, uint64_t batch_budget_bytes,
              int32_t precision, uint32_t flags, ip_cells **out);
 
+/* The traced cells (Sec. V-A: the output of the trace is the set of
+ * intersecting edges with their intersection points, one cell each; Sec.
+ * V-B: the same set built batch by batch).  Count and statistics: */
 int64_t ip_cells_count(const ip_cells *c);
 int ip_cells_stats(const ip_cells *c, ip_stats *out);
 /* Copy cells to host buffers (any may be NULL): v (n x d int32, smaller
@@ -266,7 +269,9 @@ int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict,
  * rate (Sec. V-B: only the C_free points go back to the host). */
 int ip_cells_download_free(ip_ctx *ctx, const ip_cells *c, double *free_soa);
 
-/* f at lattice vertices (device v_dev: n x d int32 -> device f_dev: n).
+/* f at lattice vertices (Sec. V-A: the manifold's value at the vertices of
+ * the triangulation decides which edges intersect; device v_dev: n x d
+ * int32 -> device f_dev: n).
  * IP_FP64: canonical FP64.  IP_FP32_CERTIFY: FP32 with the bound, FP64 for
  * the vertices the bound cannot settle; bound_dev (may be NULL) receives the
  * bound used (0 for FP64 results). */

@@ -221,13 +221,15 @@ def ip_cells_stats(cells) -> dict:
     return st.as_dict()
 
 
-def ip_cells_download(ctx, cells, d):
+def ip_cells_download(ctx, cells, d, points=True):
+    """(v (n, d) int32, mask (n,) uint32, points (n, d) or None)."""
     n = ip_cells_count(cells)
-    v = np.zeros((n, d), np.int32)
-    m = np.zeros(n, np.uint32)
-    p = np.zeros((n, d), np.float64)
+    v = np.empty((n, d), np.int32)
+    m = np.empty(n, np.uint32)
+    p = np.empty((n, d), np.float64) if points else None
     _chk(ctx, _lib.ip_cells_download(ctx, cells, v.ctypes.data_as(_ip),
-                                     m.ctypes.data_as(C.POINTER(C.c_uint32)), p.ctypes.data_as(_dp)))
+                                     m.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                     p.ctypes.data_as(_dp) if points else None))
     return v, m, p
 
 
@@ -384,8 +386,8 @@ class Cells:
     def stats(self):
         return ip_cells_stats(self.h)
 
-    def download(self):
-        return ip_cells_download(self.ctx.h, self.h, self.d)
+    def download(self, points=True):
+        return ip_cells_download(self.ctx.h, self.h, self.d, points)
 
     def check(self, scene):
         self.n_free = ip_check_cells(self.ctx.h, self.h, scene)

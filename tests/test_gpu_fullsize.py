@@ -134,3 +134,39 @@ def test_fullsize_sampled_cells_match_oracle(ip, ctx, full, name):
         assert (np.abs(p - opts) / scale).max() <= 1e-5
     # the verdict the oracle gives at the library's own point
     assert np.array_equal(ver, O.check(wl.scene, p).astype(np.uint8))
+
+
+def _splitmix64(z):
+    z = z ^ (z >> np.uint64(30))
+    z = z * np.uint64(0xBF58476D1CE4E5B9)
+    z = z ^ (z >> np.uint64(27))
+    z = z * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def test_fullsize_digest_recomputed_on_host(ip, ctx, full, summaries):
+    """The order-independent digest that the count-and-digest comparisons
+    rest on, recomputed on the host from the downloaded cells of the full
+    FP32-certified trace (keys packed as include/ip.h states)."""
+    wl, prob = full
+    n32, d32, _ = summaries["fp32"]
+    c = ip.Cells(ctx, prob, budget=BUDGET, precision=ip.IP_FP32_CERTIFY)
+    try:
+        v, m, _ = c.download(points=False)
+        bits, vmin = c.key_layout()
+    finally:
+        c.close()
+    assert len(m) == n32
+    d = wl.f.d
+    s, x = np.uint64(0), np.uint64(0)
+    with np.errstate(over="ignore"):
+        for a in range(0, len(m), 1 << 25):
+            vv = v[a:a + (1 << 25)].astype(np.int64) - vmin.astype(np.int64)
+            assert (vv >= 0).all() and (vv < (1 << bits)).all()
+            key = m[a:a + (1 << 25)].astype(np.uint64) << np.uint64(d * bits)
+            for j in range(d):
+                key |= vv[:, j].astype(np.uint64) << np.uint64(j * bits)
+            h = _splitmix64(key)
+            s = s + np.add.reduce(h, dtype=np.uint64)
+            x = x ^ np.bitwise_xor.reduce(h)
+    assert (int(s), int(x)) == d32
