@@ -275,6 +275,16 @@ def latency_summary(res):
             "requests": len(res), "failed": sum(r["status"] != 0 for r in res)}
 
 
+def timeline(res):
+    """Per request: d, cells, submit time, queue wait, admission wait, time
+    traced and checked, the trace's own stream time, device allocations that
+    missed the context cache (count, bytes), admitted bytes (ms, bytes)."""
+    return [[r["d"], r["n_cells"], round(r["t_submit"] * 1e3, 2), round((r["t_start"] - r["t_submit"]) * 1e3, 2),
+             round((r["t_admit"] - r["t_start"]) * 1e3, 2), round((r["t_done"] - r["t_admit"]) * 1e3, 2),
+             round(r["stats"]["ms_total"], 2), r["stats"]["n_hip_malloc"], r["stats"]["hip_malloc_bytes"],
+             r["admitted_bytes"]] for r in res]
+
+
 def request_sizes(res):
     """Per-request cells and admitted (projected) bytes, as quantiles."""
     q = [0, 10, 50, 90, 100]
@@ -426,6 +436,8 @@ def main():
                     help="batch-triangulation workspace cap per batch (GiB)")
     ap.add_argument("--serve", type=int, default=256, help="serving requests (0: skip)")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--serve-log", default="",
+                    help="write every serving request's timeline (JSON, per mode) to this path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", type=int, default=1, help="run the other workloads' lines (0: skip)")
     ap.add_argument("--workload-cache", default="",
@@ -588,12 +600,18 @@ def main():
               file=sys.stderr, flush=True)
         srv = {"requests": len(reqs), "slots": args.slots, "arrival_rate_per_s": round(rate, 2),
                "isolated_service_ms": round(t_service * 1e3, 3), "request_sizes": request_sizes(iso)}
+        log = {"isolated": timeline(iso)}
         for key, slots, prec in (("fp32_certify", args.slots, ip.IP_FP32_CERTIFY),
                                  ("fp64", args.slots, ip.IP_FP64),
                                  ("queue_only_fp32", 1, ip.IP_FP32_CERTIFY)):
-            srv[key] = latency_summary(serving(ip, reqs, slots, rate, prec))
+            res = serving(ip, reqs, slots, rate, prec)
+            srv[key] = latency_summary(res)
+            log[key] = timeline(res)
             print(f"[bench] serving {key}: {srv[key]}", file=sys.stderr, flush=True)
         out["serving"] = srv
+        if args.serve_log:
+            with open(args.serve_log, "w") as fh:
+                json.dump(log, fh)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))

@@ -260,7 +260,9 @@ int ip_check(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n,
  * free (verdict 0) points (Sec. V-B: only C_free points go back to the
  * host).  *n_free receives their count. */
 int ip_check_cells(ip_ctx *ctx, ip_cells *c, const ip_scene *scene, int64_t *n_free);
-/* Host copies of the verdicts (n bytes) and free points (n_free x d). */
+/* Host copies of the verdicts (n bytes) and free points (row-major
+ * n_free x d, interleaved on the device and copied once).  Either pointer
+ * may be NULL.  Waits for the context's stream. */
 int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict,
                             double *free_pts);
 /* The free points to the host as they lie on the device, one column per
@@ -369,7 +371,9 @@ typedef struct {
   uint64_t digest[2];        /* order-independent digest of the traced edge keys:
                                 sum and xor of SplitMix64(key), mod 2^64 */
   double t_submit, t_start, t_done;  /* seconds, server's monotonic clock */
-  double *free_pts;          /* host, n_free x d (NULL without a scene) */
+  double *free_pts;          /* host, n_free x d (NULL without a scene):
+                                page-locked memory from the server's pool,
+                                which ip_result_free returns there */
   ip_cells *cells;           /* with IP_KEEP_CELLS; download with ctx = NULL */
   char error[160];
   uint64_t admitted_bytes;   /* the projection (or mem_bytes) it was admitted by */

@@ -594,7 +594,35 @@ __global__ void gather_kernel(const uint64_t *keys, const double *pts, int64_t l
   }
 }
 
+// Rows [0, n) of a column-major point array (column j at soa + j ld) into
+// row-major order, one output double per lane, so the stores coalesce.
+__global__ void interleave_kernel(const double *soa, int64_t ld, int64_t n, int d, double *aos) {
+  const int64_t total = n * d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / d;
+    const int j = (int)(i - r * d);
+    aos[i] = soa[(int64_t)j * ld + r];
+  }
+}
+
 }  // namespace
+
+extern "C++" int ip_free_points_to_host(ip_ctx *ctx, const ip_cells *c, double *host) {
+  const int64_t nf = c->n_free;
+  if (nf <= 0) return IP_OK;
+  void *buf = nullptr;
+  IP_TRY(ip_dalloc(ctx, &buf, (size_t)nf * c->d * 8));
+  const int64_t total = nf * c->d;
+  hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)), dim3(256), 0,
+                     ctx->stream, (const double *)c->free_pts, c->n, nf, c->d, (double *)buf);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host, buf, (size_t)total * 8, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  ip_dfree(ctx, buf);
+  if (e != hipSuccess) return ip_hip(ctx, e, "free points to host");
+  return IP_OK;
+}
 
 int ip_cells_digest(ip_ctx *ctx, const ip_cells *c, uint64_t digest[2]) {
   if (!ctx && c) ctx = c->ctx;
@@ -694,18 +722,10 @@ int ip_cells_download_check(ip_ctx *ctx, const ip_cells *c, uint8_t *verdict, do
   if (!ctx && c) ctx = c->ctx;
   if (!ctx) return IP_EINVAL;
   if (!c || !c->verdict) return ip_fail(ctx, IP_EINVAL, "cells have not been checked");
-  const int d = c->d;
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
   if (verdict && c->n)
     IP_TRY_HIP(ctx, hipMemcpyAsync(verdict, c->verdict, (size_t)c->n, hipMemcpyDeviceToHost, ctx->stream));
-  if (free_pts && c->n_free) {
-    std::vector<double> soa((size_t)c->n_free * d);
-    for (int j = 0; j < d; ++j)
-      IP_TRY_HIP(ctx, hipMemcpyAsync(soa.data() + (size_t)j * c->n_free, c->free_pts + (size_t)j * c->n,
-                                     (size_t)c->n_free * 8, hipMemcpyDeviceToHost, ctx->stream));
-    IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (int64_t i = 0; i < c->n_free; ++i)
-      for (int j = 0; j < d; ++j) free_pts[i * d + j] = soa[(size_t)j * c->n_free + i];
-  }
+  if (free_pts) IP_TRY(ip_free_points_to_host(ctx, c, free_pts));
   IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return IP_OK;
 }

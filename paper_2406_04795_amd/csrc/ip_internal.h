@@ -700,6 +700,9 @@ int ip_noalloc_setup(ip_ctx *ctx);
 int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n, int64_t ld,
                   uint8_t *verdict_dev);
 int ip_check_gather_impl(ip_ctx *ctx, const ip_scene *scene, ip_cells *c);
+// The checked cells' C_free points, row-major n_free x d, into host memory
+// (interleaved on the device, then one copy); waits for the stream.
+int ip_free_points_to_host(ip_ctx *ctx, const ip_cells *c, double *host);
 
 // f evaluation of the vertices listed in `list` (slots of the vertex table);
 // results go into vt_vals[slot].  Defined in feval.hip.

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstddef>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -16,6 +17,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "ip_internal.h"
@@ -91,6 +93,67 @@ struct Job {
   bool done = false;
 };
 
+// Page-locked host blocks for the C_free points of results: the device
+// copies into them at the link's rate, with no page faults on the host, and
+// ip_result_free returns them here.  Idle blocks are kept up to `limit`
+// bytes (the largest go first beyond it).
+struct PinnedPool {
+  std::mutex mu;
+  std::multimap<size_t, void *> idle;
+  size_t idle_bytes = 0, limit = 1ull << 30;
+
+  void *get(size_t bytes, size_t *cap) {
+    const size_t gran = 2ull << 20;
+    const size_t want = (bytes + gran - 1) / gran * gran;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto it = idle.lower_bound(want);
+      if (it != idle.end() && it->first <= 2 * want) {
+        void *p = it->second;
+        *cap = it->first;
+        idle_bytes -= it->first;
+        idle.erase(it);
+        return p;
+      }
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    *cap = want;
+    return p;
+  }
+  void put(void *p, size_t cap) {
+    std::vector<void *> drop;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      idle.emplace(cap, p);
+      idle_bytes += cap;
+      while (idle_bytes > limit && !idle.empty()) {
+        auto last = std::prev(idle.end());
+        drop.push_back(last->second);
+        idle_bytes -= last->first;
+        idle.erase(last);
+      }
+    }
+    for (void *q : drop) (void)hipHostFree(q);
+  }
+  ~PinnedPool() {
+    for (auto &kv : idle) (void)hipHostFree(kv.second);
+  }
+};
+
+// A result with where its free points came from; ip_result_free gets the
+// public part, the first member.
+struct ResultBox {
+  ip_result r;
+  PinnedPool *pool = nullptr;  // free_pts from this pool (else new[])
+  size_t cap = 0;
+};
+static_assert(std::is_standard_layout<ResultBox>::value && offsetof(ResultBox, r) == 0,
+              "ip_result must be the first member of its box");
+
 }  // namespace
 
 struct ip_server {
@@ -109,6 +172,7 @@ struct ip_server {
   std::condition_variable cv_mem;
   bool stop = false;
   std::chrono::steady_clock::time_point t0;
+  PinnedPool pinned;
 
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 
@@ -157,11 +221,17 @@ struct ip_server {
       r->n_cells = c->n;
       ip_cells_stats(c, &r->stats);
       if (q.has_scene && r->n_free > 0) {
-        r->free_pts = new (std::nothrow) double[(size_t)r->n_free * q.f.d];
+        ResultBox *box = reinterpret_cast<ResultBox *>(r);
+        const size_t bytes = (size_t)r->n_free * q.f.d * sizeof(double);
+        r->free_pts = (double *)pinned.get(bytes, &box->cap);
+        if (r->free_pts)
+          box->pool = &pinned;
+        else
+          r->free_pts = new (std::nothrow) double[(size_t)r->n_free * q.f.d];
         if (!r->free_pts)
           rc = ip_fail(ctx, IP_ENOMEM, "host allocation failed");
         else
-          rc = ip_cells_download_check(ctx, c, nullptr, r->free_pts);
+          rc = ip_free_points_to_host(ctx, c, r->free_pts);
       }
     }
     if (rc == IP_OK && (q.flags & IP_KEEP_CELLS)) {
@@ -243,9 +313,10 @@ int ip_server_submit(ip_server *s, const ip_request *req, uint64_t *id) {
   if (!job) return IP_ENOMEM;
   own(req, job->req);
   job->req.bytes = req->mem_bytes;  // 0: projected by the slot that takes it
-  job->res = new (std::nothrow) ip_result();
-  if (!job->res) return IP_ENOMEM;
-  memset(job->res, 0, sizeof(ip_result));
+  ResultBox *box = new (std::nothrow) ResultBox();
+  if (!box) return IP_ENOMEM;
+  memset(&box->r, 0, sizeof(ip_result));
+  job->res = &box->r;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     job->res->t_submit = s->now();
@@ -284,9 +355,15 @@ int ip_server_wait(ip_server *s, uint64_t id, ip_result **out) {
 
 void ip_result_free(ip_result *r) {
   if (!r) return;
-  delete[] r->free_pts;
+  ResultBox *box = reinterpret_cast<ResultBox *>(r);
+  if (r->free_pts) {
+    if (box->pool)
+      box->pool->put(r->free_pts, box->cap);
+    else
+      delete[] r->free_pts;
+  }
   if (r->cells) ip_cells_free(r->cells);
-  delete r;
+  delete box;
 }
 
 void ip_server_destroy(ip_server *s) {
