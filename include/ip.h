@@ -33,7 +33,8 @@ enum {
   IP_ENOMEM = -2,   /* device memory or batch budget too small */
   IP_ERANGE = -3,   /* lattice coordinates of the domain overflow the 64-bit keys */
   IP_EDEVICE = -4,  /* HIP runtime error (message in ip_last_error) */
-  IP_EAGAIN = -5    /* result not ready (serving loop) */
+  IP_EAGAIN = -5,   /* result not ready (serving loop) */
+  IP_ECANCELED = -6 /* a batch callback asked to stop (ip_trace_check_batches) */
 };
 
 enum {
@@ -260,6 +261,38 @@ int ip_check(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n,
  * free (verdict 0) points (Sec. V-B: only C_free points go back to the
  * host).  *n_free receives their count. */
 int ip_check_cells(ip_ctx *ctx, ip_cells *c, const ip_scene *scene, int64_t *n_free);
+/* Batch by batch, the way the paper's batch stage runs (Sec. V-B, Fig. 6:
+ * each batch's cells get their intersection points, are checked, and only
+ * the C_free points go to the host before the batch's memory is reused).
+ * Needs batch triangulation (coarse_k >= 2) and a scene; precision and
+ * flags as for ip_trace.  For each batch, on the calling thread, fn(user,
+ * batch, free_pts, n_free, n_cells) receives the batch's C_free points
+ * (host, row-major n_free x d, page-locked, valid until fn returns) and its
+ * cell count; a nonzero return stops the trace with IP_ECANCELED.  fn may
+ * be NULL (counts and digest only).  The union over the batches is exactly
+ * the set that ip_trace + ip_check_cells give (each cell once, in another
+ * order).  batch_budget_bytes sizes a batch by its workspace plus its
+ * projected output, (9 + 24 d) bytes per projected cell (key, points,
+ * verdict, free-point copy and staging); the projection is 1.6 nc k^(d-1)
+ * cells over |Sigma| per coarse simplex (nc: coarse crossing edges), so a
+ * batch's memory is bounded by the budget up to the projection's error
+ * (over-full batches grow their buffers and go on).  What stays resident
+ * across batches: Sigma, the coarse trace and the global set of the edges
+ * on shared coarse faces (8 bytes per such edge plus its table slots).
+ * *out receives totals: cells, free points, batches, the digest of the
+ * traced set (as ip_cells_digest) and the statistics. */
+typedef int (*ip_batch_fn)(void *user, int64_t batch, const double *free_pts, int64_t n_free, int64_t n_cells);
+typedef struct {
+  int64_t n_cells;
+  int64_t n_free;
+  int64_t batches;
+  uint64_t digest[2];
+  ip_stats stats;
+} ip_batch_summary;
+int ip_trace_check_batches(ip_ctx *ctx, const ip_problem *p, uint64_t batch_budget_bytes, int32_t precision,
+                           uint32_t flags, const ip_scene *scene, ip_batch_fn fn, void *user,
+                           ip_batch_summary *out);
+
 /* Host copies of the verdicts (n bytes) and free points (row-major
  * n_free x d, interleaved on the device and copied once).  Either pointer
  * may be NULL.  Waits for the context's stream. */

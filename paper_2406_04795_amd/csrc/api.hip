@@ -394,6 +394,7 @@ void ip_destroy(ip_ctx *ctx) {
   for (auto &kv : ctx->cache.size_of) (void)hipFree(kv.first);  // blocks never returned
   if (ctx->ctr_dev) (void)hipFree(ctx->ctr_dev);
   if (ctx->ctr_host) (void)hipHostFree(ctx->ctr_host);
+  if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   delete ctx;
@@ -482,6 +483,45 @@ void ip_problem_free(ip_problem *p) {
   if (p->poly_dev) (void)hipFree(p->poly_dev);
   if (p->rbf_dev) (void)hipFree(p->rbf_dev);
   delete p;
+}
+
+int ip_trace_check_batches(ip_ctx *ctx, const ip_problem *p, uint64_t batch_budget_bytes, int32_t precision,
+                           uint32_t flags, const ip_scene *scene, ip_batch_fn fn, void *user,
+                           ip_batch_summary *out) {
+  if (!ctx) return IP_EINVAL;
+  if (!out || !p || !scene) return ip_fail(ctx, IP_EINVAL, "null argument");
+  memset(out, 0, sizeof(*out));
+  if (p->ctx != ctx) return ip_fail(ctx, IP_EINVAL, "problem belongs to another context");
+  if (precision != IP_FP64 && precision != IP_FP32_CERTIFY) return ip_fail(ctx, IP_EINVAL, "unknown precision");
+  if (p->k < 2) return ip_fail(ctx, IP_EINVAL, "per-batch tracing needs batch triangulation (coarse_k >= 2)");
+  if (scene->n_joints != p->d) return ip_fail(ctx, IP_EINVAL, "scene joints must equal the dimension");
+  IP_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  IP_TRY_HIP(ctx, hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return ip_hip(ctx, e, "hipEventCreate");
+  }
+  const int64_t nm0 = ctx->n_hip_malloc, bm0 = ctx->hip_malloc_bytes;
+  e = hipEventRecord(e0, ctx->stream);
+  int rc = e == hipSuccess ? ip_trace_batches_impl(ctx, p, batch_budget_bytes, precision, flags, scene, fn, user, out)
+                           : ip_hip(ctx, e, "hipEventRecord");
+  out->stats.n_hip_malloc = ctx->n_hip_malloc - nm0;
+  out->stats.hip_malloc_bytes = ctx->hip_malloc_bytes - bm0;
+  if (rc == IP_OK) {
+    e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) rc = ip_hip(ctx, e, "ip_trace_check_batches timing");
+    out->stats.ms_total = ms;
+  } else {
+    (void)hipStreamSynchronize(ctx->stream);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 int ip_trace(ip_ctx *ctx, const ip_problem *p, uint64_t batch_budget_bytes, int32_t precision, uint32_t flags,
@@ -606,6 +646,13 @@ __global__ void interleave_kernel(const double *soa, int64_t ld, int64_t n, int 
 }
 
 }  // namespace
+
+extern "C++" int ip_digest_accumulate(ip_ctx *ctx, const uint64_t *keys, int64_t n, unsigned long long *acc) {
+  if (n <= 0) return IP_OK;
+  hipLaunchKernelGGL(digest_kernel, dim3(1024), dim3(256), 0, ctx->stream, keys, n, acc, acc + 1);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
+}
 
 extern "C++" int ip_free_points_to_host(ip_ctx *ctx, const ip_cells *c, double *host) {
   const int64_t nf = c->n_free;

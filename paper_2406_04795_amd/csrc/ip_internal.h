@@ -621,6 +621,9 @@ struct ip_ctx {
   int64_t hip_malloc_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int64_t last_fallback = 0;  // FP64 re-evaluations of the last ip_feval
+  // page-locked staging of the per-batch C_free hand-off (grow-only)
+  void *host_stage = nullptr;
+  size_t host_stage_bytes = 0;
 };
 
 struct ip_problem {
@@ -700,6 +703,12 @@ int ip_noalloc_setup(ip_ctx *ctx);
 int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n, int64_t ld,
                   uint8_t *verdict_dev);
 int ip_check_gather_impl(ip_ctx *ctx, const ip_scene *scene, ip_cells *c);
+// Per-batch trace, check and C_free hand-off (ip_trace_check_batches).
+int ip_trace_batches_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, uint32_t flags,
+                          const ip_scene *scene, ip_batch_fn fn, void *user, ip_batch_summary *out);
+// Adds the digest terms of keys[0 .. n) to acc[0] (sum) and acc[1] (xor),
+// device accumulators, on the context's stream.
+int ip_digest_accumulate(ip_ctx *ctx, const uint64_t *keys, int64_t n, unsigned long long *acc);
 // The checked cells' C_free points, row-major n_free x d, into host memory
 // (interleaved on the device, then one copy); waits for the stream.
 int ip_free_points_to_host(ip_ctx *ctx, const ip_cells *c, double *host);

@@ -1994,12 +1994,135 @@ int redo_points(ip_ctx *ctx, const ip_problem *p, const uint64_t *keys, const ui
   return IP_OK;
 }
 
+template <int D>
+int refine_T(ip_ctx *ctx, const ip_problem *p, int32_t prec, int iters, ip_cells *c);
+
+// Per-batch hand-off of the batch stage (ip_trace_check_batches): each
+// batch's cells get their points (by the caller), then are refined, checked
+// and their C_free points copied to page-locked host memory for the
+// callback; the batch's buffers are reused by the next batch.
+struct BatchStream {
+  ip_ctx *ctx = nullptr;
+  const ip_scene *scene = nullptr;
+  ip_batch_fn fn = nullptr;
+  void *user = nullptr;
+  int32_t prec = IP_FP64;
+  int iters = 0;
+  unsigned long long *dg = nullptr;  // device: digest sum and xor
+  uint8_t *verdict = nullptr;        // device, vcap bytes
+  uint64_t vcap = 0;
+  double *pts = nullptr;             // device batch points, SoA d x ld
+  uint64_t ld = 0;
+  int64_t n_cells = 0, n_free = 0, batches = 0;
+  double ms_check = 0.0, ms_refine = 0.0;
+  explicit BatchStream(ip_ctx *c) : ctx(c) {}
+  ~BatchStream() {
+    if (ctx) (void)hipStreamSynchronize(ctx->stream);
+    for (void *q : {(void *)dg, (void *)verdict, (void *)pts})
+      if (q) ip_dfree(ctx, q);
+  }
+  BatchStream(const BatchStream &) = delete;
+  BatchStream &operator=(const BatchStream &) = delete;
+  int init() {
+    IP_TRY(alloc(ctx, (void **)&dg, 16));
+    return fill(ctx, dg, 2, 0ull);
+  }
+};
+
+// Projected output bytes of one coarse simplex in the per-batch mode: its
+// share of the fine cells (1.6 nc k^(d-1) / |Sigma|) times key, points,
+// verdict, free-point copy and staging (9 + 24 d bytes per cell).
+template <int D>
+uint64_t stream_bytes_per_sigma(uint64_t nc, uint64_t nsig, int k) {
+  double est = 1.6 * (double)nc;
+  for (int q = 0; q < D - 1; ++q) est *= k;
+  const double per = est / (double)(nsig ? nsig : 1);
+  return (uint64_t)std::ceil(per * (9.0 + 24.0 * D)) + 1;
+}
+
+// The batch's cells are keys[0 .. n) with their points in bs.pts: refine,
+// digest, check, C_free points to the host, callback.  The check kernels
+// reset the whole counter block, so the trace's counters are saved around
+// them.
+template <int D>
+int stream_consume(const ip_problem *p, BatchStream &bs, const uint64_t *keys, uint64_t n) {
+  ip_ctx *ctx = bs.ctx;
+  ip_cells view;
+  view.ctx = ctx;
+  view.d = D;
+  view.B = p->fine.B;
+  view.n = (int64_t)n;
+  view.keys = const_cast<uint64_t *>(keys);
+  view.pts = bs.pts;
+  view.ld = (int64_t)bs.ld;
+  if (n) {
+    IP_TRY(refine_T<D>(ctx, p, bs.prec, bs.iters, &view));
+    bs.ms_refine += view.st.ms_refine;
+    IP_TRY(ip_digest_accumulate(ctx, keys, (int64_t)n, bs.dg));
+  }
+  if (n > bs.vcap) {
+    if (bs.verdict) release(ctx, bs.verdict);
+    bs.verdict = nullptr;
+    bs.vcap = 0;
+    IP_TRY(alloc(ctx, (void **)&bs.verdict, n + n / 4 + 1024));
+    bs.vcap = n + n / 4 + 1024;
+  }
+  view.verdict = bs.verdict;
+  IP_TRY(read_ctr(ctx));
+  const Counters saved = *ctx->ctr_host;
+  int rc = ip_check_gather_impl(ctx, bs.scene, &view);
+  *ctx->ctr_host = saved;
+  hipError_t e = hipMemcpyAsync(ctx->ctr_dev, ctx->ctr_host, sizeof(Counters), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (rc == IP_OK && e != hipSuccess) rc = ip_hip(ctx, e, "counter restore");
+  // the context's page-locked staging, kept across calls
+  const size_t need = (size_t)view.n_free * D * sizeof(double);
+  if (rc == IP_OK && need > ctx->host_stage_bytes) {
+    if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+    ctx->host_stage = nullptr;
+    ctx->host_stage_bytes = 0;
+    const size_t want = need + need / 4 + (1u << 20);
+    e = hipHostMalloc(&ctx->host_stage, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      ctx->host_stage = nullptr;
+      rc = ip_hip(ctx, e, "hipHostMalloc (C_free staging)");
+    } else {
+      ctx->host_stage_bytes = want;
+    }
+  }
+  double *host = (double *)ctx->host_stage;
+  if (rc == IP_OK) rc = ip_free_points_to_host(ctx, &view, host);
+  if (view.free_pts) ip_dfree(ctx, view.free_pts);
+  IP_TRY(rc);
+  bs.ms_check += view.st.ms_check;
+  bs.n_cells += (int64_t)n;
+  bs.n_free += view.n_free;
+  const int64_t b = bs.batches++;
+  if (bs.fn && bs.fn(bs.user, b, host, view.n_free, (int64_t)n) != 0)
+    return ip_fail(ctx, IP_ECANCELED, "stopped by the batch callback");
+  return IP_OK;
+}
+
+// The batch's cell list in the owner list: its owner-emitted keys [0, n_dir)
+// followed by the edge-set keys it added, skeys[set_lo, set_hi).
+inline int stream_batch_keys(BatchSink &g, uint64_t n_dir, uint64_t set_lo, uint64_t set_hi, uint64_t *n_out) {
+  const uint64_t n = n_dir + (set_hi - set_lo);
+  if (n > g.dcap) IP_TRY(g.reserve_direct(n + n / 4 + 1024, n_dir));
+  if (set_hi > set_lo)
+    IP_TRY_HIP(g.ctx, hipMemcpyAsync(g.dkeys + n_dir, g.skeys + set_lo, (set_hi - set_lo) * 8, hipMemcpyDeviceToDevice,
+                                     g.ctx->stream));
+  *n_out = n;
+  return IP_OK;
+}
+
 // Initial sizes of the batch outputs from the coarse edge count: fine edges
 // are about coarse edges x k^(d-1) (the owner list gets 1.6 times that, the
 // set for edges without an owner a quarter); both grow on demand.
+// In the per-batch mode (frac = batch / |Sigma| < 1) both start at one
+// batch's share.
 template <int D>
-int init_sink(BatchSink &g, uint64_t nc, int k) {
-  double est = (double)nc;
+int init_sink(BatchSink &g, uint64_t nc, int k, double frac = 1.0) {
+  double est = (double)nc * std::min(1.0, frac);
   for (int q = 0; q < D - 1; ++q) est *= k;
   IP_TRY(g.reserve_direct((uint64_t)std::min(est * 1.6, 4.0e9) + 1024, 0));
   IP_TRY(g.reserve_set(pow2_at_least((uint64_t)std::min(est * 0.5, 4.0e9)), 0));
@@ -2013,10 +2136,11 @@ int init_sink(BatchSink &g, uint64_t nc, int k) {
 // certified tier settles (sized from their count).
 template <int D>
 int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig_all, uint64_t nsig,
-                    uint64_t nc, uint64_t budget, ip_stats &st, ip_cells *res) {
+                    uint64_t nc, uint64_t budget, ip_stats &st, ip_cells *res, BatchStream *bs) {
   const int NP = a.NP, NE = a.NE;
   if (budget == 0) budget = 4ull << 30;
-  uint64_t B = std::min<uint64_t>(budget / (4 + sizeof(SubPrep<D>)), 0xffffffffull);
+  const uint64_t per_sigma = 4 + sizeof(SubPrep<D>) + (bs ? stream_bytes_per_sigma<D>(nc, nsig, p->k) : 0);
+  uint64_t B = std::min<uint64_t>(budget / per_sigma, 0xffffffffull);
   if (B == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
   if (B > nsig) B = nsig ? nsig : 1;
   IP_TRY(ip_ensure(ctx, ctx->vt_aux, B * 4));
@@ -2025,10 +2149,11 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   IP_TRY(prep_hold.get(B * sizeof(SubPrep<D>)));
   SubPrep<D> *prep = prep_hold.as<SubPrep<D>>();
   BatchSink g(ctx);
-  IP_TRY(init_sink<D>(g, nc, p->k));
+  IP_TRY(init_sink<D>(g, nc, p->k, bs ? (double)B / (double)(nsig ? nsig : 1) : 1.0));
   Counters *c = ctx->ctr_host;
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
   int64_t regrows = 0, n_fallback = 0, n_settled64 = 0, n_pts = 0, batches = 0;
+  uint64_t set_done = 0;
   Timer tf, tx, tp, ts, tq;
   for (uint64_t b0 = 0; b0 < nsig; b0 += B) {
     const uint64_t nb = std::min<uint64_t>(B, nsig - b0);
@@ -2037,6 +2162,8 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
     IP_TRY(tq.start(ctx, &st.ms_prep));
     IP_TRY(launch_prep<D>(ctx, p, a, sig, nb, true, prep));
     IP_TRY(tq.stop(ctx));
+    // per-batch mode: the owner list starts empty for every batch
+    if (bs) IP_TRY(set_counter(ctx, &ctx->ctr_dev->n_direct, 0));
     IP_TRY(run_with_replay(ctx, g, regrows, [&]() -> int {
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_aux));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_unsettled));
@@ -2092,8 +2219,32 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
       fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu deferred, %llu + %llu cells so far\n",
               (long long)batches, (unsigned long long)nb, (unsigned long long)n_def,
               (unsigned long long)c->n_direct, (unsigned long long)c->n_out);
+    if (bs) {
+      const uint64_t set_hi = c->n_out;
+      uint64_t n_b = 0;
+      IP_TRY(stream_batch_keys(g, c->n_direct, set_done, set_hi, &n_b));
+      IP_TRY(grow_points<D>(ctx, 0, std::max<uint64_t>(n_b, 1), bs->pts, bs->ld));
+      IP_TRY(sub_points<D>(ctx, p, g.dkeys, 0, n_b, bs->pts, bs->ld, tp, st, n_fallback));
+      IP_TRY(stream_consume<D>(p, *bs, g.dkeys, n_b));
+      set_done = set_hi;
+    }
   }
   (void)NP;
+  if (bs) {
+    IP_TRY(tf.flush(ctx));
+    IP_TRY(tx.flush(ctx));
+    IP_TRY(tp.flush(ctx));
+    IP_TRY(ts.flush(ctx));
+    IP_TRY(tq.flush(ctx));
+    res->d = D;
+    st.n_cells = bs->n_cells;
+    st.n_batches = batches;
+    st.n_vertices += n_pts;
+    st.regrows += regrows;
+    st.n_fallback += n_fallback;
+    st.n_settled64 += n_settled64;
+    return IP_OK;
+  }
   const uint64_t n_dir = c->n_direct, n_set = c->n_out, n = n_dir + n_set;
   IP_TRY(g.assemble<D>(n_dir, n_set, false));
   double *pts = nullptr;
@@ -2137,16 +2288,17 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
 // that fits the budget fixes the batch size.
 template <int D>
 int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const uint64_t *sig_all, uint64_t nsig,
-                    uint64_t nc, uint64_t budget, bool cert, ip_stats &st, ip_cells *res) {
+                    uint64_t nc, uint64_t budget, bool cert, ip_stats &st, ip_cells *res, BatchStream *bs) {
   const int k = p->k, NP = a.NP, NE = a.NE;
   // a slot: VEnt, eval-list entry and, certified, its bound and fallback
   // entry; per coarse simplex (one per 2 NP slots) its preparation record
+  // and, in the per-batch mode, its projected output
   const uint64_t slot_bytes = sizeof(VEnt) + 4 + (cert ? 8 : 0);
+  const uint64_t per_sigma = sizeof(SubPrep<D>) + (bs ? stream_bytes_per_sigma<D>(nc, nsig, k) : 0);
   if (budget == 0) budget = 4ull << 30;
   uint64_t vcap_b = 0;
   for (uint64_t cc = 1024; cc <= (1ull << 32); cc <<= 1)
-    if (cc * slot_bytes + (cc / 2) * 4 + cc / (2 * (uint64_t)NP) * sizeof(SubPrep<D>) <= budget &&
-        cc >= 2 * (uint64_t)NP)
+    if (cc * slot_bytes + (cc / 2) * 4 + cc / (2 * (uint64_t)NP) * per_sigma <= budget && cc >= 2 * (uint64_t)NP)
       vcap_b = cc;
   if (vcap_b == 0) return ip_fail(ctx, IP_ENOMEM, "batch budget below one coarse simplex");
   uint64_t B = vcap_b / (2 * (uint64_t)NP);
@@ -2176,7 +2328,7 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   IP_TRY(prep_hold.get(B * sizeof(SubPrep<D>)));
   SubPrep<D> *prep = prep_hold.as<SubPrep<D>>();
   BatchSink g(ctx);
-  IP_TRY(init_sink<D>(g, nc, k));
+  IP_TRY(init_sink<D>(g, nc, k, bs ? (double)B / (double)(nsig ? nsig : 1) : 1.0));
   Counters *c = ctx->ctr_host;
   IP_TRY_HIP(ctx, hipMemsetAsync(ctx->ctr_dev, 0, sizeof(Counters), ctx->stream));
   Timer tf, tx, tp, ts, tq;
@@ -2203,6 +2355,8 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
     IP_TRY(eval_pending(f, n_ev));
     IP_TRY(tf.stop(ctx));
     st.n_vertices += (int64_t)n_ev;
+    // per-batch mode: the owner list starts empty for every batch
+    if (bs) IP_TRY(set_counter(ctx, &ctx->ctr_dev->n_direct, 0));
     IP_TRY(run_with_replay(ctx, g, f.regrows, [&]() -> int {
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cof));
       IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_shared));
@@ -2219,17 +2373,30 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
       fprintf(stderr, "[ip] batch %lld: %llu coarse simplices, %llu new vertices, %llu + %llu cells so far\n",
               (long long)batches, (unsigned long long)nb, (unsigned long long)n_ev, (unsigned long long)dir_hi,
               (unsigned long long)set_hi);
-    // points of this batch's new edges, from the batch vertex table
-    IP_TRY(grow_points<D>(ctx, dir_done, dir_hi, g.dpts, g.dld));
-    IP_TRY(grow_points<D>(ctx, set_done, set_hi, g.spts, g.sld));
+    // points of this batch's new edges, from the batch vertex table (the
+    // per-batch mode lists them in the owner list first)
     struct Part {
       const uint64_t *keys;
       uint64_t lo, hi;
       double *pts;
       uint64_t ld;
     };
-    const Part parts[2] = {{g.dkeys, dir_done, dir_hi, g.dpts, g.dld}, {g.skeys, set_done, set_hi, g.spts, g.sld}};
-    for (const Part &q : parts) {
+    Part parts[2];
+    int n_parts = 2;
+    uint64_t n_b = 0;
+    if (bs) {
+      IP_TRY(stream_batch_keys(g, dir_hi, set_done, set_hi, &n_b));
+      IP_TRY(grow_points<D>(ctx, 0, std::max<uint64_t>(n_b, 1), bs->pts, bs->ld));
+      parts[0] = {g.dkeys, 0, n_b, bs->pts, bs->ld};
+      n_parts = 1;
+    } else {
+      IP_TRY(grow_points<D>(ctx, dir_done, dir_hi, g.dpts, g.dld));
+      IP_TRY(grow_points<D>(ctx, set_done, set_hi, g.spts, g.sld));
+      parts[0] = {g.dkeys, dir_done, dir_hi, g.dpts, g.dld};
+      parts[1] = {g.skeys, set_done, set_hi, g.spts, g.sld};
+    }
+    for (int pi = 0; pi < n_parts; ++pi) {
+      const Part &q = parts[pi];
       if (q.hi <= q.lo) continue;
       uint64_t *redo = nullptr;
       if (cert) {
@@ -2253,8 +2420,27 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
         IP_TRY(redo_points<D>(ctx, p, q.keys, redo, ctx->ctr_host->n_aux, q.pts, q.ld, f.n_fallback));
       }
     }
-    dir_done = dir_hi;
+    if (bs) {
+      IP_TRY(stream_consume<D>(p, *bs, g.dkeys, n_b));
+      dir_done = 0;
+    } else {
+      dir_done = dir_hi;
+    }
     set_done = set_hi;
+  }
+  if (bs) {
+    IP_TRY(tf.flush(ctx));
+    IP_TRY(tx.flush(ctx));
+    IP_TRY(tp.flush(ctx));
+    IP_TRY(ts.flush(ctx));
+    IP_TRY(tq.flush(ctx));
+    res->d = D;
+    st.n_cells = bs->n_cells;
+    st.n_batches = batches;
+    st.regrows += f.regrows;
+    st.n_fallback += f.n_fallback;
+    st.n_settled64 += f.n_settled64;
+    return IP_OK;
   }
   IP_TRY(g.assemble<D>(dir_done, set_done, true));
   IP_TRY(tf.flush(ctx));
@@ -2281,7 +2467,8 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
 }
 
 template <int D>
-int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip_cells *res) {
+int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip_cells *res,
+                BatchStream *bs = nullptr) {
   ip_stats &st = res->st;
   const int k = p->k;
   const int LB = lehmer_bits(D);
@@ -2379,9 +2566,9 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
                   tpf_hold.as<uint64_t>(), tpv_hold.as<uint64_t>(), cvt, cvt_cap - 1};
   int rc;
   if (cert && p->poly.ok)
-    rc = subdivide_fused<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, st, res);
+    rc = subdivide_fused<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, st, res, bs);
   else
-    rc = subdivide_table<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, cert, st, res);
+    rc = subdivide_table<D>(ctx, p, a, (const uint64_t *)sig_list, nsig, nc, budget, cert, st, res, bs);
   (void)hipStreamSynchronize(ctx->stream);
   st.regrows += s.regrows;
   st.n_fallback += s.n_fallback;
@@ -2788,6 +2975,55 @@ int ip_region_eval_impl(ip_ctx *ctx, const ip_problem *p, const int32_t *simp, i
     case 7: return region_eval_T<7>(ctx, p, simp, n, y, f, bound, np_out);
     default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
   }
+}
+
+namespace {
+
+template <int D>
+int trace_batches_T(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, int iters,
+                    const ip_scene *scene, ip_batch_fn fn, void *user, ip_batch_summary *out) {
+  const bool cert = prec == IP_FP32_CERTIFY && p->f.kernel == IP_KERNEL_POLY && ip_has_fp32_form(p);
+  BatchStream bs(ctx);
+  bs.scene = scene;
+  bs.fn = fn;
+  bs.user = user;
+  bs.prec = prec;
+  bs.iters = iters;
+  IP_TRY(bs.init());
+  ip_cells res;
+  res.ctx = ctx;
+  IP_TRY(trace_batch<D>(ctx, p, budget, cert, &res, &bs));
+  unsigned long long dg[2] = {0, 0};
+  IP_TRY_HIP(ctx, hipMemcpyAsync(dg, bs.dg, 16, hipMemcpyDeviceToHost, ctx->stream));
+  IP_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  out->n_cells = bs.n_cells;
+  out->n_free = bs.n_free;
+  out->batches = bs.batches;
+  out->digest[0] = dg[0];
+  out->digest[1] = dg[1];
+  out->stats = res.st;
+  out->stats.ms_check = bs.ms_check;
+  out->stats.ms_refine = bs.ms_refine;
+  out->stats.refine_iters = iters;
+  return IP_OK;
+}
+
+}  // namespace
+
+int ip_trace_batches_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, uint32_t flags,
+                          const ip_scene *scene, ip_batch_fn fn, void *user, ip_batch_summary *out) {
+  const int iters = (int)((flags >> 4) & 15u);
+#define IP_TB(DD) return trace_batches_T<DD>(ctx, p, budget, prec, iters, scene, fn, user, out)
+  switch (p->d) {
+    case 2: IP_TB(2);
+    case 3: IP_TB(3);
+    case 4: IP_TB(4);
+    case 5: IP_TB(5);
+    case 6: IP_TB(6);
+    case 7: IP_TB(7);
+    default: return ip_fail(ctx, IP_EINVAL, "dimension out of range");
+  }
+#undef IP_TB
 }
 
 int ip_trace_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, uint32_t flags,

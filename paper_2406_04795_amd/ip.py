@@ -21,7 +21,7 @@ if not os.path.exists(LIBPATH):
 
 _lib = C.CDLL(LIBPATH)
 
-IP_OK, IP_EINVAL, IP_ENOMEM, IP_ERANGE, IP_EDEVICE, IP_EAGAIN = 0, -1, -2, -3, -4, -5
+IP_OK, IP_EINVAL, IP_ENOMEM, IP_ERANGE, IP_EDEVICE, IP_EAGAIN, IP_ECANCELED = 0, -1, -2, -3, -4, -5, -6
 IP_FP64, IP_FP32_CERTIFY = 0, 1
 IP_MAX_D = 7
 
@@ -93,6 +93,15 @@ class ip_result(C.Structure):
 IP_KEEP_CELLS = 1
 
 
+class ip_batch_summary(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_free", C.c_int64), ("batches", C.c_int64),
+                ("digest", C.c_uint64 * 2), ("stats", ip_stats)]
+
+
+# int fn(void *user, int64_t batch, const double *free_pts, int64_t n_free, int64_t n_cells)
+ip_batch_fn = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int64, _dp, C.c_int64, C.c_int64)
+
+
 def IP_REFINE(n: int) -> int:
     """ip_trace flag: n (0..15) iterations of the iterative intersection."""
     return (int(n) & 15) << 4
@@ -117,6 +126,8 @@ _sig = {
     "ip_check": (C.c_int, [_vp, _P(ip_scene), _vp, C.c_int64, C.c_int64, _vp]),
     "ip_check_cells": (C.c_int, [_vp, _vp, _P(ip_scene), _P(C.c_int64)]),
     "ip_cells_download_check": (C.c_int, [_vp, _vp, C.POINTER(C.c_uint8), _dp]),
+    "ip_trace_check_batches": (C.c_int, [_vp, _vp, C.c_uint64, C.c_int32, C.c_uint32, _P(ip_scene), ip_batch_fn,
+                                         _vp, _P(ip_batch_summary)]),
     "ip_cells_download_free": (C.c_int, [_vp, _vp, _vp]),
     "ip_feval": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, _vp, _vp]),
     "ip_feval_noalloc": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, _vp, _vp]),
@@ -359,12 +370,52 @@ class Context:
         self.close()
 
 
+def ip_trace_check_batches(ctx, prob, scene, d, budget=0, precision=IP_FP64, flags=0, on_batch=None,
+                           collect=False):
+    """Per-batch trace + check with the C_free points handed to the host
+    batch by batch.  on_batch(batch, free_pts (n_free x d, a view valid only
+    during the call), n_cells) may return True to stop (IPError
+    IP_ECANCELED).  Returns (summary dict, list of per-batch copies of the
+    free points if collect else None)."""
+    keep = []
+    s = _scene_struct(scene, keep)
+    got = [] if collect else None
+    err = []
+
+    def cb(_user, batch, pts, n_free, n_cells):
+        try:
+            view = (np.ctypeslib.as_array(pts, shape=(n_free * d,)).reshape(n_free, d) if n_free > 0
+                    else np.zeros((0, d)))
+            if got is not None:
+                got.append(view.copy())
+            if on_batch is not None and on_batch(batch, view, n_cells):
+                return 1
+            return 0
+        except Exception as e:  # an exception stops the trace and is re-raised
+            err.append(e)
+            return 1
+
+    fn = ip_batch_fn(cb)
+    out = ip_batch_summary()
+    rc = _lib.ip_trace_check_batches(ctx, prob, budget, precision, flags, C.byref(s), fn, None, C.byref(out))
+    if err:
+        raise err[0]
+    _chk(ctx, rc)
+    summ = {"n_cells": out.n_cells, "n_free": out.n_free, "batches": out.batches,
+            "digest": (out.digest[0], out.digest[1]), "stats": out.stats.as_dict()}
+    return summ, got
+
+
 class Problem:
     def __init__(self, ctx: Context, wl, coarse_k=None):
         self.ctx = ctx
         self.d = wl.f.d
         self.h = ip_problem_create(ctx.h, wl.f, wl.lat, wl.dom, wl.seeds,
                                    wl.k if coarse_k is None else coarse_k)
+
+    def trace_check_batches(self, scene, budget=0, precision=IP_FP64, flags=0, on_batch=None, collect=False):
+        return ip_trace_check_batches(self.ctx.h, self.h, scene, self.d, budget, precision, flags, on_batch,
+                                      collect)
 
     def close(self):
         if self.h:

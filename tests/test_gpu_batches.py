@@ -1,0 +1,210 @@
+"""GPU parity of the per-batch pipeline (Sec. V-B, Fig. 6: each batch is
+subdivided, its intersection points computed and checked, and only its
+C_free points go to the host): the union of the batches' free points equals
+the oracle's free points of the batch-triangulated set, bit for bit in FP64;
+cell count and digest equal the oracle's; batch size, precision tier and
+cancellation behave as documented."""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2406_04795_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ip():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    from paper_2406_04795_amd import ip as _ip
+    return _ip
+
+
+@pytest.fixture(scope="module")
+def ctx(ip):
+    c = ip.Context(0)
+    yield c
+    c.close()
+
+
+# scenes picked (obstacle stream and count) so that the cells' verdicts are
+# mixed: about 67 % free at d = 4 and 75 % at d = 5 (oracle)
+def _arm_d4():
+    rng = np.random.default_rng(41)
+    sc = I.spatial_arm_scene(rng, 4, spheres_per_link=2, sphere_r=0.05, n_osph=1, n_obox=1,
+                             obst_ball=((0.0, 0.0, 0.3), 0.6))
+    return I.cubic_case(4, 200, 0.15, 0.01, seed=3, n_seeds=4, k=4, scene=sc)
+
+
+def _arm_d5():
+    rng = np.random.default_rng(40)
+    sc = I.spatial_arm_scene(rng, 5, spheres_per_link=2, sphere_r=0.05, n_osph=2, n_obox=1, n_ocyl=1,
+                             obst_ball=((0.0, 0.0, 0.3), 0.9))
+    return I.cubic_case(5, 500, 0.5, 0.02, seed=1, n_seeds=4, k=2, scene=sc)
+
+
+def _c1_k2():
+    wl = I.config_c1()
+    wl.k = 2
+    return wl
+
+
+CASES = {"c1_d3_k2": _c1_k2, "arm_d4_k4": _arm_d4, "arm_d5_k2": _arm_d5}
+
+
+def _rows(a):
+    return a[np.lexsort(a.T[::-1])] if len(a) else a
+
+
+def _splitmix64(z):
+    z = z ^ (z >> np.uint64(30))
+    z = z * np.uint64(0xBF58476D1CE4E5B9)
+    z = z ^ (z >> np.uint64(27))
+    z = z * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def _host_digest(v, m, bits, vmin):
+    d = v.shape[1]
+    vv = v.astype(np.int64) - vmin.astype(np.int64)
+    assert (vv >= 0).all() and (vv < (1 << bits)).all()
+    with np.errstate(over="ignore"):
+        key = m.astype(np.uint64) << np.uint64(d * bits)
+        for j in range(d):
+            key |= vv[:, j].astype(np.uint64) << np.uint64(j * bits)
+        h = _splitmix64(key)
+        return int(np.add.reduce(h, dtype=np.uint64)), int(np.bitwise_xor.reduce(h))
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(name, iters=0):
+    """Oracle batch trace of CASES[name], its points (linear, or `iters`
+    Illinois steps), their verdicts and the free points."""
+    wl = CASES[name]()
+    v, m, _ = O.trace_batch(wl, k=wl.k)
+    pts = O.points(wl, v, m)[0] if iters == 0 else O.points_refined(wl, v, m, iters)
+    ver = O.check(wl.scene, pts)
+    return wl, v, m, pts[ver == 0]
+
+
+def _key_layout(ip, ctx, prob):
+    c = ip.Cells(ctx, prob)
+    try:
+        return c.key_layout()
+    finally:
+        c.close()
+
+
+def _batches(ip, ctx, wl, **kw):
+    p = ip.Problem(ctx, wl)
+    try:
+        summ, got = p.trace_check_batches(wl.scene, collect=True, **kw)
+        layout = _key_layout(ip, ctx, p)
+    finally:
+        p.close()
+    free = np.concatenate(got) if got else np.zeros((0, wl.f.d))
+    return summ, got, free, layout
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_batches_match_oracle(ip, ctx, name):
+    print(f"per-batch case {name}", flush=True)
+    wl, v, m, ofree = oracle_case(name)
+    # a budget of a few hundred coarse simplices' projected output: many batches
+    summ, got, free, (bits, vmin) = _batches(ip, ctx, wl, budget=256 * 1024)
+    assert 0 < len(ofree) < len(v)
+    assert summ["batches"] == len(got) > 1
+    assert summ["n_cells"] == len(v)
+    assert summ["n_free"] == len(ofree) == len(free)
+    assert summ["digest"] == _host_digest(v, m, bits, vmin)
+    assert np.array_equal(_rows(free).view(np.uint64), _rows(ofree).view(np.uint64))
+
+
+def test_batches_budget_invariance_and_callback(ip, ctx):
+    wl, v, m, ofree = oracle_case("arm_d4_k4")
+    one, _, free1, _ = _batches(ip, ctx, wl)
+    seen = []
+
+    def on_batch(b, pts, n_cells):
+        assert pts.shape[1] == wl.f.d
+        seen.append((b, len(pts), n_cells))
+
+    p = ip.Problem(ctx, wl)
+    try:
+        many, got = p.trace_check_batches(wl.scene, budget=128 * 1024, on_batch=on_batch, collect=True)
+    finally:
+        p.close()
+    assert one["batches"] == 1 and many["batches"] > 10
+    assert [s[0] for s in seen] == list(range(many["batches"]))
+    assert sum(s[2] for s in seen) == many["n_cells"] == one["n_cells"] == len(v)
+    assert sum(s[1] for s in seen) == many["n_free"] == len(ofree)
+    assert many["digest"] == one["digest"]
+    free = np.concatenate(got)
+    assert np.array_equal(_rows(free).view(np.uint64), _rows(free1).view(np.uint64))
+
+
+@pytest.mark.parametrize("name", ["arm_d4_k4", "arm_d5_k2"])
+def test_batches_fp32_equal_resident_path(ip, ctx, name):
+    """The certified mode per batch gives the same cells, points and
+    verdicts as its resident path (trace, check, download)."""
+    wl = CASES[name]()
+    p = ip.Problem(ctx, wl)
+    try:
+        summ, got = p.trace_check_batches(wl.scene, budget=256 * 1024, precision=ip.IP_FP32_CERTIFY, collect=True)
+        c = ip.Cells(ctx, p, precision=ip.IP_FP32_CERTIFY)
+        try:
+            nf = c.check(wl.scene)
+            _, fp = c.download_check()
+            dg = c.digest()
+            n = c.n
+        finally:
+            c.close()
+    finally:
+        p.close()
+    assert summ["batches"] > 1
+    assert summ["n_cells"] == n and summ["n_free"] == nf
+    assert summ["digest"] == tuple(dg)
+    free = np.concatenate(got)
+    assert np.array_equal(_rows(free).view(np.uint64), _rows(fp).view(np.uint64))
+
+
+def test_batches_refined_points_match_oracle(ip, ctx):
+    wl, v, m, ofree = oracle_case("arm_d4_k4", iters=3)
+    summ, got, free, _ = _batches(ip, ctx, wl, budget=256 * 1024, flags=ip.IP_REFINE(3))
+    assert summ["stats"]["refine_iters"] == 3
+    assert summ["n_free"] == len(ofree)
+    assert np.array_equal(_rows(free).view(np.uint64), _rows(ofree).view(np.uint64))
+
+
+def test_batches_cancel_and_errors(ip, ctx):
+    wl = CASES["arm_d4_k4"]()
+    p = ip.Problem(ctx, wl)
+    try:
+        with pytest.raises(ip.IPError) as e:
+            p.trace_check_batches(wl.scene, budget=256 * 1024, on_batch=lambda b, pts, n: b == 1)
+        assert e.value.code == ip.IP_ECANCELED
+        # the context keeps working after a stopped call
+        summ, _ = p.trace_check_batches(wl.scene)
+        assert summ["n_cells"] > 0
+    finally:
+        p.close()
+    # direct tracing (coarse_k = 1) has no batches
+    p1 = ip.Problem(ctx, wl, coarse_k=1)
+    try:
+        with pytest.raises(ip.IPError) as e:
+            p1.trace_check_batches(wl.scene)
+        assert e.value.code == ip.IP_EINVAL
+    finally:
+        p1.close()
+    # a callback that raises stops the trace and the error reaches the caller
+    p = ip.Problem(ctx, wl)
+    try:
+        def boom(b, pts, n):
+            raise RuntimeError("stop here")
+        with pytest.raises(RuntimeError, match="stop here"):
+            p.trace_check_batches(wl.scene, on_batch=boom)
+    finally:
+        p.close()
