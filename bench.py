@@ -361,6 +361,70 @@ def cfree_leg(ip, wl, prec, budget, n_free, steps=3):
             "d2h_ms": round(t_copy * 1e3, 3), "d2h_gbs": round(nf * wl.f.d * 8 / t_copy / 1e9, 2)}
 
 
+def per_batch_leg(ip, wl, prec, budgets_gib, steps=3):
+    """The paper's batch pipeline (trace, check and the C_free points to the
+    host batch by batch) at each batch budget: time per step, batches, and
+    the device memory the context holds after its first call (free device
+    memory before the context minus after), beside the same figure for the
+    resident path (cells, points and free points all on the device)."""
+    import torch
+    if wl.scene is None or wl.k < 2:
+        return None
+
+    def held(run):
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        ctx = ip.Context(0)
+        prob = ip.Problem(ctx, wl)
+        try:
+            keep = run(ctx, prob)
+            torch.cuda.synchronize()
+            used = free0 - torch.cuda.mem_get_info()[0]
+            return used, keep, ctx, prob
+        except Exception:
+            prob.close()
+            ctx.close()
+            raise
+
+    def resident(ctx, prob):
+        c = ip.Cells(ctx, prob, precision=prec)
+        c.check(wl.scene)
+        return c
+
+    used, c, ctx, prob = held(resident)
+    c.close()
+    prob.close()
+    ctx.close()
+    out = {"resident_device_gib": round(used / 2 ** 30, 2)}
+    for gib in budgets_gib:
+        budget = int(gib * 2 ** 30)
+        used, summ, ctx, prob = held(lambda cx, pr: pr.trace_check_batches(wl.scene, budget=budget,
+                                                                           precision=prec)[0])
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step_ms, mallocs = [], []
+            for _ in range(steps):
+                t1 = time.perf_counter()
+                summ, _ = prob.trace_check_batches(wl.scene, budget=budget, precision=prec)
+                step_ms.append(round((time.perf_counter() - t1) * 1e3, 1))
+                mallocs.append(summ["stats"]["n_hip_malloc"])
+            el = (time.perf_counter() - t0) / steps
+        finally:
+            prob.close()
+            ctx.close()
+        st = summ["stats"]
+        out[f"budget_{gib:g}gib"] = {
+            "simplices_per_s": summ["n_cells"] / el, "ms_per_step": round(el * 1e3, 3),
+            "batches": summ["batches"], "cells": summ["n_cells"], "free_points": summ["n_free"],
+            "device_gib": round(used / 2 ** 30, 2), "check_ms": round(st["ms_check"], 3),
+            "points_ms": round(st["ms_points"], 3), "subdivide_ms": round(st["ms_subdivide"], 3),
+            "step_ms": step_ms, "hip_malloc_per_step": mallocs}
+        print(f"[bench] per-batch pipeline, budget {gib:g} GiB: {out[f'budget_{gib:g}gib']}", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def extra_legs(ip, wls, main_wl):
     """The other workloads of the suite, one line each: the d=3 planar arm
     (C1), the d=5 arm (C2), the precision stress at its scale (C5, with its
@@ -588,6 +652,9 @@ def main():
 
     # the same step with the C_free points copied to pinned host memory (the
     # paper's pipeline hands them to the host): PCIe-inclusive, not `value`
+    # the paper's per-batch hand-off: C_free to the host after every batch,
+    # device memory bounded by the batch budget (not `value`)
+    out["per_batch_cfree_to_host"] = per_batch_leg(ip, wl, main_prec, (4.0, args.budget_gib))
     out["with_cfree_to_host"] = cfree_leg(ip, wl, main_prec, budget, nf)
     if extras:
         out["legs"] = extra_legs(ip, extras, wl)

@@ -265,11 +265,14 @@ int ip_check_cells(ip_ctx *ctx, ip_cells *c, const ip_scene *scene, int64_t *n_f
  * each batch's cells get their intersection points, are checked, and only
  * the C_free points go to the host before the batch's memory is reused).
  * Needs batch triangulation (coarse_k >= 2) and a scene; precision and
- * flags as for ip_trace.  For each batch, on the calling thread, fn(user,
- * batch, free_pts, n_free, n_cells) receives the batch's C_free points
- * (host, row-major n_free x d, page-locked, valid until fn returns) and its
- * cell count; a nonzero return stops the trace with IP_ECANCELED.  fn may
- * be NULL (counts and digest only).  The union over the batches is exactly
+ * flags as for ip_trace.  For each batch, on the calling thread and in batch
+ * order, fn(user, batch, free_pts, n_free, n_cells) receives the batch's
+ * C_free points (host, row-major n_free x d, page-locked, valid until fn
+ * returns) and its cell count; a nonzero return stops the trace with
+ * IP_ECANCELED.  A batch's copy to the host runs on a second stream while
+ * the next batch is traced, so its callback comes once that copy has landed
+ * (at the latest when the call returns).  fn may be NULL (counts and digest
+ * only).  The union over the batches is exactly
  * the set that ip_trace + ip_check_cells give (each cell once, in another
  * order).  batch_budget_bytes sizes a batch by its workspace plus its
  * projected output, (9 + 24 d) bytes per projected cell (key, points,

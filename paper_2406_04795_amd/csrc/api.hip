@@ -654,21 +654,31 @@ extern "C++" int ip_digest_accumulate(ip_ctx *ctx, const uint64_t *keys, int64_t
   return IP_OK;
 }
 
+extern "C++" int ip_interleave_free(ip_ctx *ctx, const ip_cells *c, double *out_dev) {
+  const int64_t nf = c->n_free;
+  if (nf <= 0) return IP_OK;
+  const int64_t total = nf * c->d;
+  hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)), dim3(256), 0,
+                     ctx->stream, (const double *)c->free_pts, c->n, nf, c->d, out_dev);
+  IP_TRY_HIP(ctx, hipGetLastError());
+  return IP_OK;
+}
+
 extern "C++" int ip_free_points_to_host(ip_ctx *ctx, const ip_cells *c, double *host) {
   const int64_t nf = c->n_free;
   if (nf <= 0) return IP_OK;
   void *buf = nullptr;
   IP_TRY(ip_dalloc(ctx, &buf, (size_t)nf * c->d * 8));
   const int64_t total = nf * c->d;
-  hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)), dim3(256), 0,
-                     ctx->stream, (const double *)c->free_pts, c->n, nf, c->d, (double *)buf);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(host, buf, (size_t)total * 8, hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  int rc = ip_interleave_free(ctx, c, (double *)buf);
+  if (rc == IP_OK) {
+    hipError_t e = hipMemcpyAsync(host, buf, (size_t)total * 8, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) rc = ip_hip(ctx, e, "free points to host");
+  }
+  if (rc != IP_OK) (void)hipStreamSynchronize(ctx->stream);
   ip_dfree(ctx, buf);
-  if (e != hipSuccess) return ip_hip(ctx, e, "free points to host");
-  return IP_OK;
+  return rc;
 }
 
 int ip_cells_digest(ip_ctx *ctx, const ip_cells *c, uint64_t digest[2]) {

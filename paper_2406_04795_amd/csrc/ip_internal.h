@@ -709,6 +709,9 @@ int ip_trace_batches_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int
 // Adds the digest terms of keys[0 .. n) to acc[0] (sum) and acc[1] (xor),
 // device accumulators, on the context's stream.
 int ip_digest_accumulate(ip_ctx *ctx, const uint64_t *keys, int64_t n, unsigned long long *acc);
+// The checked cells' C_free points, row-major n_free x d, into device
+// memory out_dev (n_free d doubles), on the context's stream.
+int ip_interleave_free(ip_ctx *ctx, const ip_cells *c, double *out_dev);
 // The checked cells' C_free points, row-major n_free x d, into host memory
 // (interleaved on the device, then one copy); waits for the stream.
 int ip_free_points_to_host(ip_ctx *ctx, const ip_cells *c, double *host);

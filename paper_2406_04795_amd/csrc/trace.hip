@@ -1999,8 +1999,11 @@ int refine_T(ip_ctx *ctx, const ip_problem *p, int32_t prec, int iters, ip_cells
 
 // Per-batch hand-off of the batch stage (ip_trace_check_batches): each
 // batch's cells get their points (by the caller), then are refined, checked
-// and their C_free points copied to page-locked host memory for the
-// callback; the batch's buffers are reused by the next batch.
+// and their C_free points interleaved into one of two device staging slots;
+// a copy stream moves the slot to page-locked host memory while the compute
+// stream goes on with the next batch, and the batch's callback runs once its
+// copy has landed (when its slot is needed again, or at the end), in batch
+// order.  The batch's other buffers are reused by the next batch.
 struct BatchStream {
   ip_ctx *ctx = nullptr;
   const ip_scene *scene = nullptr;
@@ -2013,11 +2016,27 @@ struct BatchStream {
   uint64_t vcap = 0;
   double *pts = nullptr;             // device batch points, SoA d x ld
   uint64_t ld = 0;
+  hipStream_t copy = nullptr;        // device-to-host copies of the slots
+  struct Slot {
+    double *dev = nullptr;           // device staging (row-major free points)
+    size_t dev_bytes = 0;
+    hipEvent_t ready = nullptr, copied = nullptr;
+    bool pending = false;            // a copy in flight or a callback due
+    int64_t batch = 0, n_free = 0, n_cells = 0;
+  } slot[2];
+  size_t half = 0;                   // bytes per slot in ctx->host_stage
   int64_t n_cells = 0, n_free = 0, batches = 0;
   double ms_check = 0.0, ms_refine = 0.0;
   explicit BatchStream(ip_ctx *c) : ctx(c) {}
   ~BatchStream() {
     if (ctx) (void)hipStreamSynchronize(ctx->stream);
+    if (copy) (void)hipStreamSynchronize(copy);
+    for (Slot &q : slot) {
+      if (q.dev) ip_dfree(ctx, q.dev);
+      if (q.ready) (void)hipEventDestroy(q.ready);
+      if (q.copied) (void)hipEventDestroy(q.copied);
+    }
+    if (copy) (void)hipStreamDestroy(copy);
     for (void *q : {(void *)dg, (void *)verdict, (void *)pts})
       if (q) ip_dfree(ctx, q);
   }
@@ -2025,7 +2044,30 @@ struct BatchStream {
   BatchStream &operator=(const BatchStream &) = delete;
   int init() {
     IP_TRY(alloc(ctx, (void **)&dg, 16));
-    return fill(ctx, dg, 2, 0ull);
+    IP_TRY(fill(ctx, dg, 2, 0ull));
+    IP_TRY_HIP(ctx, hipStreamCreateWithFlags(&copy, hipStreamNonBlocking));
+    for (Slot &q : slot) {
+      IP_TRY_HIP(ctx, hipEventCreateWithFlags(&q.ready, hipEventDisableTiming));
+      IP_TRY_HIP(ctx, hipEventCreateWithFlags(&q.copied, hipEventDisableTiming));
+    }
+    return IP_OK;
+  }
+  double *host_of(int i) const { return (double *)((unsigned char *)ctx->host_stage + (size_t)i * half); }
+  // Waits for slot i's copy and runs its callback.
+  int drain(int i) {
+    Slot &q = slot[i];
+    if (!q.pending) return IP_OK;
+    q.pending = false;
+    IP_TRY_HIP(ctx, hipEventSynchronize(q.copied));
+    if (fn && fn(user, q.batch, host_of(i), q.n_free, q.n_cells) != 0)
+      return ip_fail(ctx, IP_ECANCELED, "stopped by the batch callback");
+    return IP_OK;
+  }
+  // Both slots, older batch first.
+  int drain_all() {
+    const int first = (slot[0].pending && slot[1].pending && slot[1].batch < slot[0].batch) ? 1 : 0;
+    IP_TRY(drain(first));
+    return drain(1 - first);
   }
 };
 
@@ -2038,6 +2080,61 @@ uint64_t stream_bytes_per_sigma(uint64_t nc, uint64_t nsig, int k) {
   for (int q = 0; q < D - 1; ++q) est *= k;
   const double per = est / (double)(nsig ? nsig : 1);
   return (uint64_t)std::ceil(per * (9.0 + 24.0 * D)) + 1;
+}
+
+// Batch number bs.batches, checked in `view`: its free points interleaved
+// into a staging slot on the compute stream, then copied to the host on the
+// copy stream.  The slot's previous batch is handed over first; the host
+// staging (two slots, in the context, kept across calls) grows only when
+// neither slot has a copy in flight.
+constexpr size_t kCopyChunk = 1ull << 30;
+
+template <int D>
+int stream_handoff(BatchStream &bs, const ip_cells &view, int64_t n_cells) {
+  ip_ctx *ctx = bs.ctx;
+  const int64_t b = bs.batches;
+  const int i = (int)(b & 1);
+  BatchStream::Slot &q = bs.slot[i];
+  IP_TRY(bs.drain(i));
+  const size_t need = (size_t)view.n_free * D * sizeof(double);
+  if (need > bs.half || 2 * bs.half > ctx->host_stage_bytes) {
+    IP_TRY(bs.drain_all());
+    const size_t want = std::max<size_t>(need + need / 4 + (1u << 20), ctx->host_stage_bytes / 2);
+    if (2 * want > ctx->host_stage_bytes) {
+      if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+      ctx->host_stage = nullptr;
+      ctx->host_stage_bytes = 0;
+      IP_TRY_HIP(ctx, hipHostMalloc(&ctx->host_stage, 2 * want, hipHostMallocDefault));
+      ctx->host_stage_bytes = 2 * want;
+    }
+    bs.half = ctx->host_stage_bytes / 2;
+  }
+  if (need > q.dev_bytes) {
+    if (q.dev) ip_dfree(ctx, q.dev);
+    q.dev = nullptr;
+    q.dev_bytes = 0;
+    IP_TRY(alloc(ctx, (void **)&q.dev, need + need / 4 + 1024));
+    q.dev_bytes = need + need / 4 + 1024;
+  }
+  IP_TRY(ip_interleave_free(ctx, &view, q.dev));
+  IP_TRY_HIP(ctx, hipEventRecord(q.ready, ctx->stream));
+  IP_TRY_HIP(ctx, hipStreamWaitEvent(bs.copy, q.ready, 0));
+  // copies of at most 1 GiB each (single copies of several GiB ran well
+  // below the link's rate)
+  for (size_t off = 0; off < need; off += kCopyChunk) {
+    const size_t len = std::min<size_t>(kCopyChunk, need - off);
+    IP_TRY_HIP(ctx, hipMemcpyAsync((unsigned char *)bs.host_of(i) + off, (const unsigned char *)q.dev + off, len,
+                                   hipMemcpyDeviceToHost, bs.copy));
+  }
+  IP_TRY_HIP(ctx, hipEventRecord(q.copied, bs.copy));
+  q.pending = true;
+  q.batch = b;
+  q.n_free = view.n_free;
+  q.n_cells = n_cells;
+  bs.batches = b + 1;
+  bs.n_cells += n_cells;
+  bs.n_free += view.n_free;
+  return IP_OK;
 }
 
 // The batch's cells are keys[0 .. n) with their points in bs.pts: refine,
@@ -2075,31 +2172,10 @@ int stream_consume(const ip_problem *p, BatchStream &bs, const uint64_t *keys, u
   hipError_t e = hipMemcpyAsync(ctx->ctr_dev, ctx->ctr_host, sizeof(Counters), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (rc == IP_OK && e != hipSuccess) rc = ip_hip(ctx, e, "counter restore");
-  // the context's page-locked staging, kept across calls
-  const size_t need = (size_t)view.n_free * D * sizeof(double);
-  if (rc == IP_OK && need > ctx->host_stage_bytes) {
-    if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
-    ctx->host_stage = nullptr;
-    ctx->host_stage_bytes = 0;
-    const size_t want = need + need / 4 + (1u << 20);
-    e = hipHostMalloc(&ctx->host_stage, want, hipHostMallocDefault);
-    if (e != hipSuccess) {
-      ctx->host_stage = nullptr;
-      rc = ip_hip(ctx, e, "hipHostMalloc (C_free staging)");
-    } else {
-      ctx->host_stage_bytes = want;
-    }
-  }
-  double *host = (double *)ctx->host_stage;
-  if (rc == IP_OK) rc = ip_free_points_to_host(ctx, &view, host);
+  if (rc == IP_OK) rc = stream_handoff<D>(bs, view, (int64_t)n);
   if (view.free_pts) ip_dfree(ctx, view.free_pts);
   IP_TRY(rc);
   bs.ms_check += view.st.ms_check;
-  bs.n_cells += (int64_t)n;
-  bs.n_free += view.n_free;
-  const int64_t b = bs.batches++;
-  if (bs.fn && bs.fn(bs.user, b, host, view.n_free, (int64_t)n) != 0)
-    return ip_fail(ctx, IP_ECANCELED, "stopped by the batch callback");
   return IP_OK;
 }
 
@@ -2231,6 +2307,7 @@ int subdivide_fused(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
   }
   (void)NP;
   if (bs) {
+    IP_TRY(bs->drain_all());
     IP_TRY(tf.flush(ctx));
     IP_TRY(tx.flush(ctx));
     IP_TRY(tp.flush(ctx));
@@ -2429,6 +2506,7 @@ int subdivide_table(ip_ctx *ctx, const ip_problem *p, const SubArgs &a, const ui
     set_done = set_hi;
   }
   if (bs) {
+    IP_TRY(bs->drain_all());
     IP_TRY(tf.flush(ctx));
     IP_TRY(tx.flush(ctx));
     IP_TRY(tp.flush(ctx));

@@ -19,6 +19,10 @@ if not os.path.exists(LIBPATH):
     raise ImportError(f"{LIBPATH} is missing: build it with paper_2406_04795_amd/build.py "
                       "(or __graft_entry__.build()); there is no fallback path")
 
+# torch first: the library then binds to the HIP runtime torch has loaded, so
+# that both share one runtime (streams and device pointers pass between them)
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIBPATH)
 
 IP_OK, IP_EINVAL, IP_ENOMEM, IP_ERANGE, IP_EDEVICE, IP_EAGAIN, IP_ECANCELED = 0, -1, -2, -3, -4, -5, -6
