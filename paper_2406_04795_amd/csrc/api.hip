@@ -395,6 +395,8 @@ void ip_destroy(ip_ctx *ctx) {
   if (ctx->ctr_dev) (void)hipFree(ctx->ctr_dev);
   if (ctx->ctr_host) (void)hipHostFree(ctx->ctr_host);
   if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+  for (void *q : ctx->dev_stage)
+    if (q) (void)hipFree(q);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   delete ctx;

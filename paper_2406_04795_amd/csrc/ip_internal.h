@@ -621,9 +621,12 @@ struct ip_ctx {
   int64_t hip_malloc_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int64_t last_fallback = 0;  // FP64 re-evaluations of the last ip_feval
-  // page-locked staging of the per-batch C_free hand-off (grow-only)
+  // page-locked staging of the per-batch C_free hand-off and its two device
+  // staging slots (grow-only, kept across calls)
   void *host_stage = nullptr;
   size_t host_stage_bytes = 0;
+  void *dev_stage[2] = {nullptr, nullptr};
+  size_t dev_stage_bytes[2] = {0, 0};
 };
 
 struct ip_problem {

@@ -2018,8 +2018,6 @@ struct BatchStream {
   uint64_t ld = 0;
   hipStream_t copy = nullptr;        // device-to-host copies of the slots
   struct Slot {
-    double *dev = nullptr;           // device staging (row-major free points)
-    size_t dev_bytes = 0;
     hipEvent_t ready = nullptr, copied = nullptr;
     bool pending = false;            // a copy in flight or a callback due
     int64_t batch = 0, n_free = 0, n_cells = 0;
@@ -2032,7 +2030,6 @@ struct BatchStream {
     if (ctx) (void)hipStreamSynchronize(ctx->stream);
     if (copy) (void)hipStreamSynchronize(copy);
     for (Slot &q : slot) {
-      if (q.dev) ip_dfree(ctx, q.dev);
       if (q.ready) (void)hipEventDestroy(q.ready);
       if (q.copied) (void)hipEventDestroy(q.copied);
     }
@@ -2109,21 +2106,24 @@ int stream_handoff(BatchStream &bs, const ip_cells &view, int64_t n_cells) {
     }
     bs.half = ctx->host_stage_bytes / 2;
   }
-  if (need > q.dev_bytes) {
-    if (q.dev) ip_dfree(ctx, q.dev);
-    q.dev = nullptr;
-    q.dev_bytes = 0;
-    IP_TRY(alloc(ctx, (void **)&q.dev, need + need / 4 + 1024));
-    q.dev_bytes = need + need / 4 + 1024;
+  if (need > ctx->dev_stage_bytes[i]) {
+    // the slot is drained: its previous copy has landed
+    if (ctx->dev_stage[i]) IP_TRY_HIP(ctx, hipFree(ctx->dev_stage[i]));
+    ctx->dev_stage[i] = nullptr;
+    ctx->dev_stage_bytes[i] = 0;
+    const size_t want = need + need / 4 + (2u << 20);
+    IP_TRY_HIP(ctx, hipMalloc(&ctx->dev_stage[i], want));
+    ctx->dev_stage_bytes[i] = want;
   }
-  IP_TRY(ip_interleave_free(ctx, &view, q.dev));
+  double *dev = (double *)ctx->dev_stage[i];
+  IP_TRY(ip_interleave_free(ctx, &view, dev));
   IP_TRY_HIP(ctx, hipEventRecord(q.ready, ctx->stream));
   IP_TRY_HIP(ctx, hipStreamWaitEvent(bs.copy, q.ready, 0));
   // copies of at most 1 GiB each (single copies of several GiB ran well
   // below the link's rate)
   for (size_t off = 0; off < need; off += kCopyChunk) {
     const size_t len = std::min<size_t>(kCopyChunk, need - off);
-    IP_TRY_HIP(ctx, hipMemcpyAsync((unsigned char *)bs.host_of(i) + off, (const unsigned char *)q.dev + off, len,
+    IP_TRY_HIP(ctx, hipMemcpyAsync((unsigned char *)bs.host_of(i) + off, (const unsigned char *)dev + off, len,
                                    hipMemcpyDeviceToHost, bs.copy));
   }
   IP_TRY_HIP(ctx, hipEventRecord(q.copied, bs.copy));
