@@ -110,15 +110,16 @@ def prep_flops_per_simplex(wl) -> int:
 def check_flops_per_cell(wl) -> int:
     """FP64 operations of the collision kernel per configuration: per link
     the own sine/cosine (42), the link transform (a rotation about one axis
-    after a joint offset: 36), the link ball's world centre (18) and the
-    ball's culling test against a ball around every obstacle (10 each).
-    Early exits are ignored; the exact tests of the pairs that pass culling
-    are not counted."""
+    after a joint offset: 36), the link ball's world centre (18) and half its
+    squared norm (6), and the ball's culling test against a ball around
+    every obstacle (c.o - |c|^2/2 as three fma: 6 each).  Early exits are
+    ignored; the exact tests of the pairs that pass culling are not
+    counted."""
     sc = wl.scene
     d = wl.f.d
     ocyl = getattr(sc, "ocyl_rh", None)
     n_obs = len(sc.osph_r) + len(sc.obox_l) + (0 if ocyl is None else len(ocyl))
-    return d * (42 + 36 + 18) + d * 10 * n_obs
+    return d * (42 + 36 + 18 + 6) + d * 6 * n_obs
 
 
 def points_flops_per_cell(wl) -> int:

@@ -34,8 +34,12 @@ struct SceneDev {
   const double *ocyl;         // [T(12) rc h rb pad] (16 doubles), rb as for boxes
   const double *lbound;       // per link [cx cy cz R]: a ball in the link frame
                               // holding all of the link's geometry (R < 0: none)
-  const double *cull;         // per obstacle (spheres, boxes, cylinders) [cx cy cz rb]: a
-                              // ball holding it; padded to a multiple of 4 with far balls
+  const double *cull;         // per link, per obstacle (spheres, boxes, cylinders, padded
+                              // to a multiple of 4 with far ones) [ox oy oz t]: o the
+                              // centre of a ball of radius rb holding the obstacle and
+                              // t = (|o|^2 - (R + eps + rb)^2) / 2 with R the link's
+                              // ball radius; the balls can meet only if c.o - |c|^2/2 >= t
+  int32_t nobs_pad;           // obstacles per link row of cull
   double eps;                 // margin of the culling test
 };
 
@@ -225,11 +229,6 @@ __device__ __forceinline__ bool sphere_cyl(const double *c, double r, const doub
 // predicates, so skipping their tests leaves every verdict unchanged.  Boxes
 // and cylinders are first tested against a ball holding them (centre x,
 // radius rb): farther than R + rb, the ball cannot reach them.
-__device__ __forceinline__ bool ball_near_ball(const double *c, double R, double x, double y, double z, double rb) {
-  const double rr = R + rb;
-  return !(sq3(c[0] - x, c[1] - y, c[2] - z) > rr * rr);
-}
-
 __device__ __forceinline__ bool ball_near_sphere(const double *c, double R, const double *o) {
   const double rr = R + o[3];
   return !(sq3(c[0] - o[0], c[1] - o[1], c[2] - o[2]) > rr * rr);
@@ -297,21 +296,33 @@ __global__ __launch_bounds__(256, 4) void check_kernel(SceneDev S, const double 
       double cb[3];
       xform(T, lb, cb);
       const double Rb = lb[3] + S.eps;
+      const double hc = -0.5 * sq3(cb[0], cb[1], cb[2]);
+      // li is wave-uniform: the row is read with scalar loads
+      const double *crow = S.cull + 4 * (int64_t)__builtin_amdgcn_readfirstlane(li * S.nobs_pad);
       for (int b0 = 0; b0 < nobs; b0 += 64) {
         const int nb = nobs - b0 < 64 ? nobs - b0 : 64;
-        // every obstacle's ball, four at a time from one contiguous array
-        // (one wave-uniform load of 16 doubles per group); then the boxes
-        // and cylinders that some lane's ball reaches against their exact
-        // distance
-        uint64_t near = 0;
+        // every obstacle's ball, four at a time from the link's row (one
+        // wave-uniform load of 16 doubles per group): c.o - |c|^2/2 against
+        // the obstacle's threshold, a bit per obstacle in two 32-bit words;
+        // then the boxes and cylinders that some lane's ball reaches against
+        // their exact distance
+        uint32_t nlo = 0, nhi = 0;
         const int nsb = nsb_all - b0 < 0 ? 0 : (nsb_all - b0 < nb ? nsb_all - b0 : nb);
         const int nbx = nbx_all - b0 < 0 ? 0 : (nbx_all - b0 < nb ? nbx_all - b0 : nb);
         for (int b = 0; b < nb; b += 4) {
-          const double *cl = S.cull + 4 * (b0 + b);
+          const double *cl = crow + 4 * (b0 + b);
+          uint32_t m = 0;
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            near |= (uint64_t)ball_near_ball(cb, Rb, cl[4 * u], cl[4 * u + 1], cl[4 * u + 2], cl[4 * u + 3]) << (b + u);
+          for (int u = 0; u < 4; ++u) {
+            const double v = fma(cb[0], cl[4 * u], fma(cb[1], cl[4 * u + 1], fma(cb[2], cl[4 * u + 2], hc)));
+            m |= !(v < cl[4 * u + 3]) ? (1u << u) : 0u;
+          }
+          if (b < 32)
+            nlo |= m << b;
+          else
+            nhi |= m << (b - 32);
         }
+        uint64_t near = ((uint64_t)nhi << 32) | nlo;
         near &= nb == 64 ? ~0ull : (1ull << nb) - 1ull;
         if (hit) near = 0;
         uint64_t any = wave_or64(near);
@@ -569,22 +580,23 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
     const double *l = sc->obox_l + 3 * b;
     obox[16 * b + 15] = 0.5 * std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]) * (1.0 + 1e-12);
   }
-  // the obstacles' balls in one array (spheres, boxes, cylinders), padded to
-  // a multiple of 4 with balls too far away to reach (centre 1e150, radius 0)
+  // the obstacles' balls (spheres, boxes, cylinders), padded to a multiple
+  // of 4 with balls too far away to reach (centre 1e150, radius 0)
   const int nobs = sc->n_osph + sc->n_obox + sc->n_ocyl;
-  std::vector<double> cull(4 * (size_t)((nobs + 3) / 4 * 4), 0.0);
-  for (int b = nobs; b < (nobs + 3) / 4 * 4; ++b) cull[4 * b] = cull[4 * b + 1] = cull[4 * b + 2] = 1e150;
+  const int nobs_pad = (nobs + 3) / 4 * 4;
+  std::vector<double> oball(4 * (size_t)nobs_pad, 0.0);
+  for (int b = nobs; b < nobs_pad; ++b) oball[4 * b] = oball[4 * b + 1] = oball[4 * b + 2] = 1e150;
   for (int b = 0; b < sc->n_osph; ++b)
-    for (int j = 0; j < 4; ++j) cull[4 * b + j] = osph[4 * b + j];
+    for (int j = 0; j < 4; ++j) oball[4 * b + j] = osph[4 * b + j];
   for (int b = 0; b < sc->n_obox; ++b) {
-    double *c = &cull[4 * (sc->n_osph + b)];
+    double *c = &oball[4 * (sc->n_osph + b)];
     c[0] = obox[16 * b + 3];
     c[1] = obox[16 * b + 7];
     c[2] = obox[16 * b + 11];
     c[3] = obox[16 * b + 15];
   }
   for (int b = 0; b < sc->n_ocyl; ++b) {
-    double *c = &cull[4 * (sc->n_osph + sc->n_obox + b)];
+    double *c = &oball[4 * (sc->n_osph + sc->n_obox + b)];
     c[0] = ocyl[16 * b + 3];
     c[1] = ocyl[16 * b + 7];
     c[2] = ocyl[16 * b + 11];
@@ -634,6 +646,23 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
     for (int j = 0; j < 15; ++j) scale = std::max(scale, std::fabs(obox[16 * b + j]));
   for (int b = 0; b < sc->n_ocyl; ++b)
     for (int j = 0; j < 14; ++j) scale = std::max(scale, std::fabs(ocyl[16 * b + j]));
+  // the geometry is summed over at most a few dozen terms of size `scale`
+  // (reach times the chain length): rounding stays below 1e-13 * scale
+  const double eps = 1e-9 * scale * (double)(nj + 1);
+  // per link and obstacle, the culling threshold of the expanded squared
+  // distance |c - o|^2 = |c|^2 - 2 c.o + |o|^2; its rounding (a few ulp of
+  // |c|^2 + |o|^2) is far below the margin 2 (R + rb) eps it is compared with
+  std::vector<double> cull(4 * (size_t)nobs_pad * nj, 0.0);
+  for (int li = 0; li < nj; ++li)
+    for (int b = 0; b < nobs_pad; ++b) {
+      const double *o = &oball[4 * b];
+      double *c = &cull[4 * ((size_t)li * nobs_pad + b)];
+      const double rr = (lbound[4 * li + 3] + eps) + o[3];
+      c[0] = o[0];
+      c[1] = o[1];
+      c[2] = o[2];
+      c[3] = b < nobs ? 0.5 * ((o[0] * o[0] + o[1] * o[1] + o[2] * o[2]) - rr * rr) : 1e300;
+    }
   // one contiguous blob: doubles first, then ints
   std::vector<double> blob;
   auto put = [&](const double *p, size_t n) {
@@ -689,9 +718,8 @@ int upload_scene(ip_ctx *ctx, const ip_scene *sc, SceneDev *out) {
   out->obox = db + o_ob;
   out->lbound = db + o_lb;
   out->cull = db + o_cl;
-  // the geometry is summed over at most a few dozen terms of size `scale`
-  // (reach times the chain length): rounding stays below 1e-13 * scale
-  out->eps = 1e-9 * scale * (double)(nj + 1);
+  out->nobs_pad = nobs_pad;
+  out->eps = eps;
   return IP_OK;
 }
 
