@@ -706,6 +706,10 @@ int ip_noalloc_setup(ip_ctx *ctx);
 int ip_check_impl(ip_ctx *ctx, const ip_scene *scene, const double *q_dev, int64_t n, int64_t ld,
                   uint8_t *verdict_dev);
 int ip_check_gather_impl(ip_ctx *ctx, const ip_scene *scene, ip_cells *c);
+// Sorts the n coarse n-simplex keys sig (base vertex packed in D fields of B
+// bits above LB Lehmer bits) by the Morton code of the base vertex, in place;
+// waits for the stream.  Defined in order.hip.
+int ip_sort_sigma(ip_ctx *ctx, uint64_t *sig, uint64_t n, int D, int B, int LB);
 // Per-batch trace, check and C_free hand-off (ip_trace_check_batches).
 int ip_trace_batches_impl(ip_ctx *ctx, const ip_problem *p, uint64_t budget, int32_t prec, uint32_t flags,
                           const ip_scene *scene, ip_batch_fn fn, void *user, ip_batch_summary *out);

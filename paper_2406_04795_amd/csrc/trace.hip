@@ -2623,6 +2623,14 @@ int trace_batch(ip_ctx *ctx, const ip_problem *p, uint64_t budget, bool cert, ip
   }
   DevTmp sig_hold(ctx), tpts_hold(ctx), tedge_hold(ctx), tgrp_hold(ctx), tpf_hold(ctx), tpv_hold(ctx);
   sig_hold.p = sig_list;
+  {
+    // Morton order of the base vertices: neighbouring simplices run together
+    Timer tso;
+    IP_TRY(tso.start(ctx, &st.ms_sigma));
+    IP_TRY(ip_sort_sigma(ctx, (uint64_t *)sig_list, nsig, D, p->coarse.B, LB));
+    IP_TRY(tso.stop(ctx));
+    IP_TRY(tso.flush(ctx));
+  }
   st.n_sigma = (int64_t)nsig;
   st.n_coarse_edges = (int64_t)nc;
   if (log_on())
