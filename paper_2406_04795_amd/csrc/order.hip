@@ -33,8 +33,8 @@ int ip_sort_sigma(ip_ctx *ctx, uint64_t *sig, uint64_t n, int D, int B, int LB) 
   if (n < 2) return IP_OK;
   const int bits = D * B + LB;
   if (bits > 64) return ip_fail(ctx, IP_ERANGE, "Sigma keys wider than 64 bits");
-  // keys in, sort keys, and the sorted outputs: four arrays of n, then the
-  // sort's temporary storage
+  // sort keys, sorted keys and sorted Sigma keys (three arrays of n), then
+  // the sort's temporary storage
   size_t tmp_bytes = 0;
   hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, (const uint64_t *)nullptr,
                                                     (uint64_t *)nullptr, (const uint64_t *)nullptr,
