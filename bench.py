@@ -504,6 +504,8 @@ def main():
     ap.add_argument("--serve-log", default="",
                     help="write every serving request's timeline (JSON, per mode) to this path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--handoff", type=int, default=1,
+                    help="run the C_free hand-off lines (resident copy, per-batch pipeline); 0: skip")
     ap.add_argument("--legs", type=int, default=1, help="run the other workloads' lines (0: skip)")
     ap.add_argument("--workload-cache", default="",
                     help="pickle of the generated workload: loaded if present, else written (profiling runs)")
@@ -655,8 +657,9 @@ def main():
     # paper's pipeline hands them to the host): PCIe-inclusive, not `value`
     # the paper's per-batch hand-off: C_free to the host after every batch,
     # device memory bounded by the batch budget (not `value`)
-    out["per_batch_cfree_to_host"] = per_batch_leg(ip, wl, main_prec, (4.0, args.budget_gib))
-    out["with_cfree_to_host"] = cfree_leg(ip, wl, main_prec, budget, nf)
+    if args.handoff:
+        out["per_batch_cfree_to_host"] = per_batch_leg(ip, wl, main_prec, (4.0, args.budget_gib))
+        out["with_cfree_to_host"] = cfree_leg(ip, wl, main_prec, budget, nf)
     if extras:
         out["legs"] = extra_legs(ip, extras, wl)
     if reqs:
