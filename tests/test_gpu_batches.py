@@ -208,3 +208,30 @@ def test_batches_cancel_and_errors(ip, ctx):
             p.trace_check_batches(wl.scene, on_batch=boom)
     finally:
         p.close()
+
+
+def test_batches_empty_and_all_colliding(ip, ctx):
+    """Nothing to trace gives no batch and a zero summary; a scene that every
+    cell collides with gives batches with no free points."""
+    wl = CASES["c1_d3_k2"]()
+    wl.seeds = np.zeros((1, 3))   # far from f = 0: no sign change in its simplex
+    seen = []
+    p = ip.Problem(ctx, wl)
+    try:
+        summ, got = p.trace_check_batches(wl.scene, on_batch=lambda b, pts, n: seen.append(b), collect=True)
+    finally:
+        p.close()
+    assert summ["n_cells"] == 0 and summ["n_free"] == 0 and summ["batches"] == 0
+    assert summ["digest"] == (0, 0) and got == [] and seen == []
+    # one obstacle sphere holding the whole planar arm's reach: every cell collides
+    wl = CASES["c1_d3_k2"]()
+    sc = wl.scene
+    sc.osph_c = np.zeros((1, 3))
+    sc.osph_r = np.array([100.0])
+    p = ip.Problem(ctx, wl)
+    try:
+        summ, got = p.trace_check_batches(sc, budget=256 * 1024, collect=True)
+    finally:
+        p.close()
+    assert summ["batches"] > 1 and summ["n_cells"] > 0 and summ["n_free"] == 0
+    assert all(len(g) == 0 for g in got)
