@@ -13,7 +13,7 @@ one); the plain FP64 path is timed beside it on the same GPU.  The serving
 section replays a Poisson stream of mixed proof requests through the
 library's server and reports p50/p99 latency.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -513,7 +513,7 @@ def main():
                     help="only run one plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the traced path has no multi-GPU mode in this build",
+        print("bench.py runs on one GPU only: the traced path has no multi-GPU mode",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration > 0:
