@@ -191,6 +191,14 @@ def test_batches_cancel_and_errors(ip, ctx):
         assert summ["n_cells"] > 0
     finally:
         p.close()
+    # a budget below one coarse simplex
+    p = ip.Problem(ctx, wl)
+    try:
+        with pytest.raises(ip.IPError) as e:
+            p.trace_check_batches(wl.scene, budget=64)
+        assert e.value.code == ip.IP_ENOMEM
+    finally:
+        p.close()
     # direct tracing (coarse_k = 1) has no batches
     p1 = ip.Problem(ctx, wl, coarse_k=1)
     try:
