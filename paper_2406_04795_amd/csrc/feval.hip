@@ -605,6 +605,11 @@ int launch_feval64(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint
   return dispatch64<0>(ctx, p->f, L, list, n_list, (const uint64_t *)vt, nullptr, (double *)vt + 1);
 }
 
+int launch_feval64_dev(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n_max,
+                       const unsigned long long *n_dev, VEnt *vt) {
+  return dispatch64<0>(ctx, p->f, L, list, n_max, (const uint64_t *)vt, nullptr, (double *)vt + 1, n_dev);
+}
+
 int launch_feval64_raw(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const int32_t *v, uint64_t n,
                        double *out) {
   return dispatch64<1>(ctx, p->f, L, nullptr, n, nullptr, v, out);

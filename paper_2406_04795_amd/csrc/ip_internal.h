@@ -734,6 +734,10 @@ int launch_set_vb(ip_ctx *ctx, const uint32_t *list, uint64_t n, float *vb, floa
 // vt: vertex-table entries; the result goes into vt[slot].f.
 int launch_feval64(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list,
                    uint64_t n_list, VEnt *vt);
+// The same for list[0 .. *n_dev) with *n_dev (written on the device by an
+// earlier kernel) at most n_max: no host read of the count.
+int launch_feval64_dev(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const uint32_t *list, uint64_t n_max,
+                       const unsigned long long *n_dev, VEnt *vt);
 // Canonical FP64 f at n raw vertices (int32, row-major n x d) into out[i].
 int launch_feval64_raw(ip_ctx *ctx, const ip_problem *p, const LatDev &L, const int32_t *v, uint64_t n,
                        double *out);

@@ -655,6 +655,19 @@ int eval_pending(Run &s, uint64_t n) {
   return launch_feval64(ctx, s.p, s.L, s.fb, nfb, s.vt);
 }
 
+// eval_pending without the host read of the fallback count: the canonical
+// pass is sized on the device (at most n), and the caller takes the level's
+// fallback counts from its next counter read.
+int eval_pending_async(Run &s, uint64_t n) {
+  if (!s.cert) return launch_feval64(s.ctx, s.p, s.L, s.eval, n, s.vt);
+  ip_ctx *ctx = s.ctx;
+  if (n == 0) return IP_OK;
+  IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_fb));
+  IP_TRY(zero_field(ctx, &ctx->ctr_dev->n_cert64));
+  IP_TRY(launch_feval32(ctx, s.p, s.L, s.eval, n, s.vt, s.vb, s.fb, &ctx->ctr_dev->n_fb));
+  return launch_feval64_dev(ctx, s.p, s.L, s.fb, n, &ctx->ctr_dev->n_fb, s.vt);
+}
+
 template <int D, bool EDGES>
 int level_pass(Run &s, uint64_t lo, uint64_t hi) {
   ip_ctx *ctx = s.ctx;
@@ -722,8 +735,9 @@ int trace_direct(Run &s, ip_stats &st, uint64_t *n_out_ret) {
       if (c->vt_fail & 2u) return ip_fail(ctx, IP_EDEVICE, "internal: traced edge lost its vertex");
     }
     cof_total += c->n_cof;
+    const bool evaluated = c->n_eval > 0;
     IP_TRY(tf.start(ctx, &st.ms_feval));
-    IP_TRY(eval_pending(s, c->n_eval));
+    IP_TRY(eval_pending_async(s, c->n_eval));
     IP_TRY(tf.stop(ctx));
     // pass 2: new edges; OUT must hold one new edge per coface at most
     IP_TRY(out_reserve(s, hi + c->n_cof + 1, hi));
@@ -731,6 +745,11 @@ int trace_direct(Run &s, ip_stats &st, uint64_t *n_out_ret) {
     IP_TRY((level_pass<D, true>(s, lo, hi)));
     IP_TRY(tx.stop(ctx));
     IP_TRY(read_ctr(ctx));
+    if (s.cert && evaluated) {
+      // this level's FP32 evaluation left these counts
+      s.n_fallback += (int64_t)c->n_fb;
+      s.n_settled64 += (int64_t)c->n_cert64;
+    }
     lo = hi;
     hi = c->n_out;
   }
