@@ -362,7 +362,7 @@ def cfree_leg(ip, wl, prec, budget, n_free, steps=3):
             "d2h_ms": round(t_copy * 1e3, 3), "d2h_gbs": round(nf * wl.f.d * 8 / t_copy / 1e9, 2)}
 
 
-def per_batch_leg(ip, wl, prec, budgets_gib, steps=3):
+def per_batch_leg(ip, wl, prec, budgets_gib, steps=3, resident=True):
     """The paper's batch pipeline (trace, check and the C_free points to the
     host batch by batch) at each batch budget: time per step, batches, and
     the device memory the context holds after its first call (free device
@@ -387,16 +387,18 @@ def per_batch_leg(ip, wl, prec, budgets_gib, steps=3):
             ctx.close()
             raise
 
-    def resident(ctx, prob):
+    def resident_run(ctx, prob):
         c = ip.Cells(ctx, prob, precision=prec)
         c.check(wl.scene)
         return c
 
-    used, c, ctx, prob = held(resident)
-    c.close()
-    prob.close()
-    ctx.close()
-    out = {"resident_device_gib": round(used / 2 ** 30, 2)}
+    out = {}
+    if resident:
+        used, c, ctx, prob = held(resident_run)
+        c.close()
+        prob.close()
+        ctx.close()
+        out["resident_device_gib"] = round(used / 2 ** 30, 2)
     for gib in budgets_gib:
         budget = int(gib * 2 ** 30)
         used, summ, ctx, prob = held(lambda cx, pr: pr.trace_check_batches(wl.scene, budget=budget,
@@ -511,6 +513,8 @@ def main():
                     help="pickle of the generated workload: loaded if present, else written (profiling runs)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run one plain device-to-device copy of this many GiB (counter calibration)")
+    ap.add_argument("--per-batch-only", type=float, default=0.0,
+                    help="only run the per-batch hand-off line at this budget (GiB) on the cached workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the traced path has no multi-GPU mode",
@@ -538,6 +542,35 @@ def main():
             import pickle
             with open(args.workload_cache, "wb") as fh:
                 pickle.dump(wl, fh)
+    if args.per_batch_only > 0:
+        import torch
+
+        from paper_2406_04795_amd import ip
+        assert torch.cuda.is_available(), "bench needs a GPU"
+        res = per_batch_leg(ip, wl, ip.IP_FP32_CERTIFY, (args.per_batch_only,), resident=False)
+        print(json.dumps(res))
+        return
+    # the per-batch hand-off in a process of its own, before this one touches
+    # the GPU: after a large resident trace has run and been freed in a
+    # process, that process's per-batch copies run slower (the line measured
+    # after the main steps below shows it)
+    fresh = None
+    if args.handoff and wl.k >= 2 and wl.scene is not None:
+        import pickle
+        import subprocess
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "wl.pkl")
+            with open(path, "wb") as fh:
+                pickle.dump(wl, fh)
+            print("[bench] per-batch pipeline in a fresh process", file=sys.stderr, flush=True)
+            r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--per-batch-only", "4",
+                                "--workload-cache", path], capture_output=True, text=True, timeout=900)
+            sys.stderr.write(r.stderr[-2000:])
+            if r.returncode == 0 and r.stdout.strip():
+                fresh = json.loads(r.stdout.strip().splitlines()[-1])
+            else:
+                print(f"[bench] fresh-process per-batch line failed ({r.returncode})", file=sys.stderr, flush=True)
     extras = {}
     if args.legs:
         from paper_2406_04795_amd import inputs as I
@@ -659,6 +692,8 @@ def main():
     # device memory bounded by the batch budget (not `value`)
     if args.handoff:
         out["per_batch_cfree_to_host"] = per_batch_leg(ip, wl, main_prec, (4.0, args.budget_gib))
+        if out["per_batch_cfree_to_host"] is not None and fresh is not None:
+            out["per_batch_cfree_to_host"]["fresh_process"] = fresh
         out["with_cfree_to_host"] = cfree_leg(ip, wl, main_prec, budget, nf)
     if extras:
         out["legs"] = extra_legs(ip, extras, wl)
