@@ -125,7 +125,8 @@ def check_flops_per_cell(wl) -> int:
 def points_flops_per_cell(wl) -> int:
     """FP64 operations of the intersection-point kernel per traced edge: both
     ends' coordinates (2 x 2 d^2), both ends' FP64 monomial values with their
-    bound sums (2 x 5 per non-constant monomial), t and the point (3 d + 2)."""
+    bound sums and the bound test (2 x (5 per non-constant monomial + 2)), t
+    and the point (3 d + 2)."""
     from math import comb
     d, p = wl.f.d, wl.f.p
     return 2 * (2 * d * d + 5 * (comb(d + p, p) - 1) + 2) + 3 * d + 2
